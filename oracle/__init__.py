@@ -1,0 +1,134 @@
+"""FP64 CPU oracle of the PSDF (test infrastructure only).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never imports it and shares no code with it.
+
+``psdf_oracle.cpp`` holds the arithmetic (the paper's four-stage pipeline,
+Sec. IV); this module only compiles it with g++ and marshals numpy arrays.
+``textbook.py`` holds independent checks of that arithmetic (Minkowski
+difference signed distance, dense boundary sampling) used to pin the oracle.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "psdf_oracle.cpp")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+DEFAULT_EPS = 1e-12
+DEFAULT_EPS_SAT = 1e-6
+DEFAULT_ETA = 1000.0
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (-O2, OpenMP) into ``oracle/liboracle.so``."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        lib.oracle_psdf.restype = ctypes.c_int
+        lib.oracle_psdf.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp, ip,
+                                    ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, dp, ip, ip, dp, ip, ctypes.c_int]
+        lib.oracle_obstacle.restype = None
+        lib.oracle_obstacle.argtypes = [dp, ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_int,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        dp, ip, dp, dp, dp]
+        lib.oracle_sd_matrix.restype = None
+        lib.oracle_sd_matrix.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp, ip,
+                                         ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, dp, ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def psdf(footprint, poses, edges, obst_off, eps=DEFAULT_EPS, eps_sat=DEFAULT_EPS_SAT,
+         eta=DEFAULT_ETA, nthreads=0):
+    """PSDF value, winning obstacle/edge, gradient and branch flag per stage.
+
+    footprint: (m, 2); poses: (N, 3); edges: (E, 4) rows (ax, ay, bx, by);
+    obst_off: (M + 1,) CSR offsets.  Inputs are promoted to float64.
+    Returns dict(phi, obst, edge, grad, pen, threads).
+    """
+    lib = _load()
+    fp, fpp = _d(footprint)
+    ps, psp = _d(poses)
+    ed = np.ascontiguousarray(edges, dtype=np.float64).reshape(-1, 4)
+    cols = [_d(ed[:, k]) for k in range(4)]
+    off, offp = _i(obst_off)
+    N = ps.shape[0]
+    M = off.shape[0] - 1
+    phi, phip = _d(np.zeros(N))
+    grad, gradp = _d(np.zeros((N, 3)))
+    obst, obstp = _i(np.zeros(N))
+    edge, edgep = _i(np.zeros(N))
+    pen, penp = _i(np.zeros(N))
+    used = lib.oracle_psdf(fpp, fp.shape[0], psp, N, cols[0][1], cols[1][1], cols[2][1],
+                           cols[3][1], offp, M, eps, eps_sat, eta, phip, obstp, edgep, gradp,
+                           penp, int(nthreads))
+    return dict(phi=phi, obst=obst, edge=edge, grad=grad, pen=pen, threads=used)
+
+
+def obstacle(footprint, pose, edges, eps=DEFAULT_EPS, eps_sat=DEFAULT_EPS_SAT, eta=DEFAULT_ETA):
+    """sd, separated flag, d_sep, per-edge pool distance and gradient for one
+    (pose, obstacle); ``edges`` are the obstacle's (mi, 4) edges."""
+    lib = _load()
+    fp, fpp = _d(footprint)
+    ps, psp = _d(pose)
+    ed = np.ascontiguousarray(edges, dtype=np.float64).reshape(-1, 4)
+    mi = ed.shape[0]
+    cols = [_d(ed[:, k]) for k in range(4)]
+    sd, sdp = _d(np.zeros(1))
+    sep, sepp = _i(np.zeros(1))
+    dsep, dsepp = _d(np.zeros(1))
+    pool, poolp = _d(np.zeros(max(mi, 1)))
+    grad, gradp = _d(np.zeros(3))
+    lib.oracle_obstacle(fpp, fp.shape[0], psp, cols[0][1], cols[1][1], cols[2][1], cols[3][1],
+                        mi, eps, eps_sat, eta, sdp, sepp, dsepp, poolp, gradp)
+    return dict(sd=float(sd[0]), separated=bool(sep[0]), d_sep=float(dsep[0]),
+                edge_pool=pool[:mi].copy(), grad=grad.copy())
+
+
+def sd_matrix(footprint, poses, edges, obst_off, eps=DEFAULT_EPS, eps_sat=DEFAULT_EPS_SAT,
+              eta=DEFAULT_ETA, nthreads=0):
+    """sd^i for every (stage, obstacle), shape (N, M)."""
+    lib = _load()
+    fp, fpp = _d(footprint)
+    ps, psp = _d(poses)
+    ed = np.ascontiguousarray(edges, dtype=np.float64).reshape(-1, 4)
+    cols = [_d(ed[:, k]) for k in range(4)]
+    off, offp = _i(obst_off)
+    N, M = ps.shape[0], off.shape[0] - 1
+    out, outp = _d(np.zeros((N, M)))
+    lib.oracle_sd_matrix(fpp, fp.shape[0], psp, N, cols[0][1], cols[1][1], cols[2][1],
+                         cols[3][1], offp, M, eps, eps_sat, eta, outp, int(nthreads))
+    return out

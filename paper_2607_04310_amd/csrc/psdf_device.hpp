@@ -1,0 +1,444 @@
+// Device-side PSDF arithmetic for gfx950 (wave64, FP32 VALU).
+//
+// One lane evaluates one obstacle against one stage pose at a time: the
+// obstacle's world-frame edges live in registers and are reused for every
+// stage the lane visits; the footprint constants are wave-uniform (kernel
+// arguments, i.e. scalar registers).  Everything is written with explicit
+// fmaf and compiled with -ffp-contract=off, so every kernel that inlines
+// these functions produces bit-identical results for the same inputs.
+//
+// Pipeline per (stage, obstacle), Sec. IV-A items 1-4:
+//   1. A~_j = R(theta)^T (A_j - p); the local edge vector v_j = R^T (B_j - A_j)
+//   2. d_v^2 = min_{l,j} |v_l - Q(v_l; A~_j, v_j)|^2 and
+//      d_e^2 = min_{w in V_obs, l} |w - Q(w; v_l, e_l)|^2 with the clamp
+//      t = min(max(u, 0), 1) (identical to ReLU(u) - ReLU(u - 1) for |u| < 2^23)
+//   3. SAT over {n_l} U {n'_j = rot90(v_j) / (|v_j| + eps)}, overlaps
+//      delta(n) = min(beta_i - alpha_P, beta_P - alpha_i), separated if any
+//      delta < -eps_sat; soft-min depth -(1/eta) log sum exp(-eta max(delta, 0))
+//      in max-shifted form
+//   4. sd = sqrt(min(d_v^2, d_e^2)) if separated else -depth
+// The squared norms |v_j|^2 + eps and |v_j| + eps are rotation invariant and
+// are taken once per obstacle from the world-frame edge.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psdf {
+
+constexpr int kMaxFp = 16;    // footprint vertices
+constexpr int kMaxObst = 16;  // edges per obstacle
+constexpr uint64_t kEmptyKey = ~0ull;
+
+// Footprint constants in the robot-local frame (counter-clockwise), prepared
+// once on the host in double precision and rounded to float.  Slots l >= m
+// repeat vertex / edge / axis m - 1, which leaves every min / max / any
+// reduction unchanged; only the soft-min sum masks them.
+struct FpConst {
+  int m;
+  int hard;        // 1: hard minimum (eta <= 0 or +inf)
+  float eps, eps_sat, eta;
+  float vx[kMaxFp], vy[kMaxFp];  // vertices v_l
+  float ex[kMaxFp], ey[kMaxFp];  // robot edge E_l = [v_l, v_{l+1}] as v_{l+1} - v_l
+  float einv[kMaxFp];            // 1 / (|e_l|^2 + eps)
+  float nx[kMaxFp], ny[kMaxFp];  // outward unit normals n_l
+  float pa[kMaxFp], pb[kMaxFp];  // robot interval [alpha_P(n_l), beta_P(n_l)]
+};
+
+// One obstacle in registers.  Slots j >= mi repeat edge mi - 1, which leaves
+// every min / max / any-reduction unchanged; only the soft-min sum masks them.
+template <int MI>
+struct Obst {
+  float ax[MI], ay[MI];   // A_j, world
+  float wx[MI], wy[MI];   // B_j - A_j, world
+  float iv2[MI];          // 1 / (|B_j - A_j|^2 + eps)
+  float il[MI];           // 1 / (|B_j - A_j| + eps)
+  int mi;
+  bool closed;            // B_j == A_{j+1} for all j (bitwise): V_obs = {A~_j}
+  bool bad;               // edge count or range invalid, or a non-finite
+                          // coordinate: the result is NaN
+};
+
+__device__ __forceinline__ float clamp01(float u) { return __builtin_amdgcn_fmed3f(u, 0.0f, 1.0f); }
+
+// Orderable 32-bit image of a float: unsigned order == float order; every NaN
+// maps to 0, below all numbers, so that a NaN result wins the minimum.
+__device__ __forceinline__ uint32_t orderable(float f) {
+  uint32_t u = __float_as_uint(f);
+  if (f != f) return 0u;
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float from_orderable(uint32_t k) {
+  uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  return __uint_as_float(u);
+}
+
+template <int MI>
+__device__ __forceinline__ void load_obstacle(Obst<MI>& o, const float* __restrict__ ax,
+                                              const float* __restrict__ ay,
+                                              const float* __restrict__ bx,
+                                              const float* __restrict__ by, int e0, int mi, int E,
+                                              float eps) {
+  o.mi = mi;
+  o.bad = (mi < 0) || (mi > MI) || (e0 < 0) || (e0 > E - mi);
+  const int n = o.bad ? 1 : (mi < 1 ? 1 : mi);
+  const int base = o.bad ? 0 : e0;
+  const bool any = !o.bad && mi > 0;
+  float bxs[MI], bys[MI];
+#pragma unroll
+  for (int j = 0; j < MI; ++j) {
+    const int jj = j < n ? j : n - 1;
+    float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
+    if (any) {
+      a0 = ax[base + jj]; a1 = ay[base + jj];
+      b0 = bx[base + jj]; b1 = by[base + jj];
+    }
+    o.ax[j] = a0; o.ay[j] = a1;
+    bxs[j] = b0; bys[j] = b1;
+    const float dx = b0 - a0, dy = b1 - a1;
+    o.wx[j] = dx; o.wy[j] = dy;
+    const float l2 = fmaf(dx, dx, dy * dy);
+    o.iv2[j] = 1.0f / (l2 + eps);
+    o.il[j] = 1.0f / (sqrtf(l2) + eps);
+  }
+  bool finite = true;
+#pragma unroll
+  for (int j = 0; j < MI; ++j)
+    finite = finite && isfinite(o.ax[j]) && isfinite(o.ay[j]) && isfinite(bxs[j]) && isfinite(bys[j]);
+  o.bad = o.bad || !finite;
+  bool closed = mi >= 3;
+#pragma unroll
+  for (int j = 0; j < MI; ++j) {
+    const float nx = (j + 1 < mi) ? o.ax[(j + 1) % MI] : o.ax[0];
+    const float ny = (j + 1 < mi) ? o.ay[(j + 1) % MI] : o.ay[0];
+    if (j < mi) closed = closed && (__float_as_uint(bxs[j]) == __float_as_uint(nx)) &&
+                         (__float_as_uint(bys[j]) == __float_as_uint(ny));
+  }
+  o.closed = closed;
+}
+
+// Squared distance from point (px, py) to the segment [a, a + v], with
+// iv2 = 1 / (|v|^2 + eps).  Also returns u for the adjoint.
+__device__ __forceinline__ float seg_d2(float px, float py, float ax, float ay, float vx, float vy,
+                                        float iv2) {
+  const float wx = px - ax, wy = py - ay;
+  const float u = fmaf(wx, vx, wy * vy) * iv2;
+  const float t = clamp01(u);
+  const float rx = fmaf(-t, vx, wx), ry = fmaf(-t, vy, wy);
+  return fmaf(rx, rx, ry * ry);
+}
+
+// Per-stage local quantities of one obstacle.
+template <int MI>
+struct Local {
+  float tax[MI], tay[MI];  // A~_j
+  float vx[MI], vy[MI];    // v_j = R^T (B_j - A_j)
+  float nx[MI], ny[MI];    // n'_j
+};
+
+template <int MI>
+__device__ __forceinline__ void to_local(const Obst<MI>& o, float c, float s, float px, float py,
+                                         Local<MI>& L) {
+#pragma unroll
+  for (int j = 0; j < MI; ++j) {
+    const float dx = o.ax[j] - px, dy = o.ay[j] - py;
+    L.tax[j] = fmaf(c, dx, s * dy);
+    L.tay[j] = fmaf(c, dy, -(s * dx));
+    L.vx[j] = fmaf(c, o.wx[j], s * o.wy[j]);
+    L.vy[j] = fmaf(c, o.wy[j], -(s * o.wx[j]));
+    L.nx[j] = -L.vy[j] * o.il[j];
+    L.ny[j] = L.vx[j] * o.il[j];
+  }
+}
+
+// sd(P0(x), P^i) of one obstacle at one stage (Sec. IV-D).  MF is the number
+// of footprint slots evaluated: the exact m (3..8) or 16 (padded).
+template <int MF, int MI>
+__device__ __forceinline__ float obstacle_sd(const FpConst& F, const Obst<MI>& o, float c, float s,
+                                             float px, float py) {
+  Local<MI> L;
+  to_local(o, c, s, px, py, L);
+
+  // Sec. IV-B pools.
+  float dv2 = __builtin_huge_valf(), de2 = __builtin_huge_valf();
+#pragma unroll
+  for (int l = 0; l < MF; ++l) {
+#pragma unroll
+    for (int j = 0; j < MI; ++j)
+      dv2 = fminf(dv2, seg_d2(F.vx[l], F.vy[l], L.tax[j], L.tay[j], L.vx[j], L.vy[j], o.iv2[j]));
+  }
+  // Sec. IV-C axis intervals, accumulated vertex by vertex over V_obs.
+  float ra_lo[MF], ra_hi[MF];    // obstacle interval on robot axis n_l
+  float oa_lo[MI], oa_hi[MI];    // obstacle interval on its own axis n'_j
+#pragma unroll
+  for (int l = 0; l < MF; ++l) { ra_lo[l] = __builtin_huge_valf(); ra_hi[l] = -__builtin_huge_valf(); }
+#pragma unroll
+  for (int j = 0; j < MI; ++j) { oa_lo[j] = __builtin_huge_valf(); oa_hi[j] = -__builtin_huge_valf(); }
+
+  auto visit = [&](float wx, float wy) {
+#pragma unroll
+    for (int l = 0; l < MF; ++l) {
+      de2 = fminf(de2, seg_d2(wx, wy, F.vx[l], F.vy[l], F.ex[l], F.ey[l], F.einv[l]));
+      const float p = fmaf(wx, F.nx[l], wy * F.ny[l]);
+      ra_lo[l] = fminf(ra_lo[l], p);
+      ra_hi[l] = fmaxf(ra_hi[l], p);
+    }
+#pragma unroll
+    for (int j = 0; j < MI; ++j) {
+      const float p = fmaf(wx, L.nx[j], wy * L.ny[j]);
+      oa_lo[j] = fminf(oa_lo[j], p);
+      oa_hi[j] = fmaxf(oa_hi[j], p);
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < MI; ++k) visit(L.tax[k], L.tay[k]);
+  if (!o.closed) {
+#pragma unroll
+    for (int k = 0; k < MI; ++k) visit(L.tax[k] + L.vx[k], L.tay[k] + L.vy[k]);
+  }
+
+  // Overlaps and the separating-axis test.
+  float dl[MF + MI];
+  bool sep = false;
+#pragma unroll
+  for (int l = 0; l < MF; ++l) {
+    dl[l] = fminf(ra_hi[l] - F.pa[l], F.pb[l] - ra_lo[l]);
+    sep = sep || (dl[l] < -F.eps_sat);
+  }
+#pragma unroll
+  for (int j = 0; j < MI; ++j) {
+    float rlo = __builtin_huge_valf(), rhi = -__builtin_huge_valf();
+#pragma unroll
+    for (int l = 0; l < MF; ++l) {
+      const float p = fmaf(F.vx[l], L.nx[j], F.vy[l] * L.ny[j]);
+      rlo = fminf(rlo, p);
+      rhi = fmaxf(rhi, p);
+    }
+    dl[MF + j] = fminf(oa_hi[j] - rlo, rhi - oa_lo[j]);
+    sep = sep || (dl[MF + j] < -F.eps_sat);
+  }
+
+  float sd = sqrtf(fminf(dv2, de2));
+  if (!sep) {
+    // Soft-min depth over the |N^i| = m + mi axes (padded slots excluded).
+    float mu = __builtin_huge_valf();
+#pragma unroll
+    for (int q = 0; q < MF + MI; ++q) mu = fminf(mu, fmaxf(dl[q], 0.0f));
+    float depth = mu;
+    if (!F.hard) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int q = 0; q < MF + MI; ++q) {
+        const bool live = q < MF ? (q < F.m) : (q - MF < o.mi);
+        if (live) acc += expf(-F.eta * (fmaxf(dl[q], 0.0f) - mu));
+      }
+      depth = mu - logf(acc) / F.eta;
+    }
+    sd = -depth;
+  }
+  if (o.bad) sd = __builtin_nanf("");
+  return sd;
+}
+
+// Reverse-mode adjoint of obstacle_sd with respect to the pose, through the
+// active branch of every min / max (first index on ties), plus the reported
+// edge: the smallest per-edge pool distance (lowest index on ties).
+// Returns sd; writes gscale * dsd/d(x, y, theta) to g[0..2].
+//
+// The adjoint is contracted on the fly: a local point P~ with adjoint gP
+// contributes -R gP to d/dp and gP . (P~_y, -P~_x) to d/dtheta (P~ moves by
+// -R^T dp + dtheta (P~_y, -P~_x)); a local edge vector v with adjoint gv
+// contributes gv . (v_y, -v_x) to d/dtheta.  The winning pool entry and the
+// extreme vertices of each active axis are carried as coordinates, so no
+// register array is indexed at run time.
+template <int MF, int MI>
+__device__ float obstacle_adjoint(const FpConst& F, const Obst<MI>& o, float c, float s, float px,
+                                  float py, float gscale, int& jstar, float g[3]) {
+  constexpr int NV = 2 * MI;        // V_obs slots: A~_k (k < MI), then B~_k (open obstacles)
+  constexpr int KA = MF + MI;       // axis slots: robot normals, then obstacle normals
+  Local<MI> L;
+  to_local(o, c, s, px, py, L);
+  auto vx_of = [&](int k) { return k < MI ? L.tax[k] : L.tax[k - MI] + L.vx[k - MI]; };
+  auto vy_of = [&](int k) { return k < MI ? L.tay[k] : L.tay[k - MI] + L.vy[k - MI]; };
+  auto live_q = [&](int q) { return q < MF ? (q < F.m) : (q - MF < o.mi); };
+
+  float sx = 0.f, sy = 0.f, gth = 0.f;
+  auto add_point = [&](float x, float y, float gx, float gy) {
+    sx += gx; sy += gy; gth += gx * y - gy * x;
+  };
+  auto add_vector = [&](float vx, float vy, float gx, float gy) { gth += gx * vy - gy * vx; };
+
+  // ---- pools (Sec. IV-B), carrying the winning entry
+  float best = __builtin_huge_valf();
+  int btype = 0;                            // 0: robot vertex -> obstacle edge; 1: V_obs point -> robot edge
+  float bPx = 0.f, bPy = 0.f;               // the point
+  float bAx = 0.f, bAy = 0.f, bVx = 0.f, bVy = 0.f, bIv = 0.f;   // the segment [A, A + V]
+  float epool[MI], dA[MI];
+#pragma unroll
+  for (int j = 0; j < MI; ++j) { epool[j] = __builtin_huge_valf(); dA[j] = __builtin_huge_valf(); }
+#pragma unroll
+  for (int l = 0; l < MF; ++l) {
+#pragma unroll
+    for (int j = 0; j < MI; ++j) {
+      const float d2 = seg_d2(F.vx[l], F.vy[l], L.tax[j], L.tay[j], L.vx[j], L.vy[j], o.iv2[j]);
+      epool[j] = fminf(epool[j], d2);
+      if (d2 < best) {
+        best = d2; btype = 0; bPx = F.vx[l]; bPy = F.vy[l];
+        bAx = L.tax[j]; bAy = L.tay[j]; bVx = L.vx[j]; bVy = L.vy[j]; bIv = o.iv2[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (k >= MI && o.closed) break;
+    const float wx = vx_of(k), wy = vy_of(k);
+    float dk = __builtin_huge_valf();
+#pragma unroll
+    for (int l = 0; l < MF; ++l) {
+      const float d2 = seg_d2(wx, wy, F.vx[l], F.vy[l], F.ex[l], F.ey[l], F.einv[l]);
+      dk = fminf(dk, d2);
+      if (d2 < best) {
+        best = d2; btype = 1; bPx = wx; bPy = wy;
+        bAx = F.vx[l]; bAy = F.vy[l]; bVx = F.ex[l]; bVy = F.ey[l]; bIv = F.einv[l];
+      }
+    }
+    epool[k % MI] = fminf(epool[k % MI], dk);
+    if (k < MI) dA[k] = dk;
+  }
+  if (o.closed) {
+    // B~_j coincides with A~_{j+1}: its pool entries also belong to edge j.
+#pragma unroll
+    for (int j = 0; j < MI; ++j) {
+      const float nxt = (j + 1 < o.mi) ? dA[(j + 1) % MI] : dA[0];
+      epool[j] = fminf(epool[j], nxt);
+    }
+  }
+  jstar = 0;
+  {
+    float eb = epool[0];
+#pragma unroll
+    for (int j = 1; j < MI; ++j)
+      if (j < o.mi && epool[j] < eb) { eb = epool[j]; jstar = j; }
+  }
+
+  // ---- overlaps (Sec. IV-C), forward only
+  auto obst_range = [&](float nxq, float nyq, float& lo, float& hi, float& lox, float& loy,
+                        float& hix, float& hiy) {
+    lo = __builtin_huge_valf(); hi = -__builtin_huge_valf();
+    lox = loy = hix = hiy = 0.f;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      if (k >= MI && o.closed) break;
+      const float wx = vx_of(k), wy = vy_of(k);
+      const float p = fmaf(wx, nxq, wy * nyq);
+      if (p < lo) { lo = p; lox = wx; loy = wy; }
+      if (p > hi) { hi = p; hix = wx; hiy = wy; }
+    }
+  };
+  auto robot_range = [&](float nxq, float nyq, float& lo, float& hi, float& lox, float& loy,
+                         float& hix, float& hiy) {
+    lo = __builtin_huge_valf(); hi = -__builtin_huge_valf();
+    lox = loy = hix = hiy = 0.f;
+#pragma unroll
+    for (int l = 0; l < MF; ++l) {
+      const float p = fmaf(F.vx[l], nxq, F.vy[l] * nyq);
+      if (p < lo) { lo = p; lox = F.vx[l]; loy = F.vy[l]; }
+      if (p > hi) { hi = p; hix = F.vx[l]; hiy = F.vy[l]; }
+    }
+  };
+  auto axis = [&](int q, float& nxq, float& nyq) {
+    nxq = q < MF ? F.nx[q] : L.nx[q - MF];
+    nyq = q < MF ? F.ny[q] : L.ny[q - MF];
+  };
+  float dl[KA];
+  bool sep = false;
+#pragma unroll
+  for (int q = 0; q < KA; ++q) {
+    float nxq, nyq, lo, hi, a, b, c0, d0;
+    axis(q, nxq, nyq);
+    obst_range(nxq, nyq, lo, hi, a, b, c0, d0);
+    float alo, ahi;
+    if (q < MF) { alo = F.pa[q]; ahi = F.pb[q]; }
+    else robot_range(nxq, nyq, alo, ahi, a, b, c0, d0);
+    dl[q] = fminf(hi - alo, ahi - lo);
+    sep = sep || (dl[q] < -F.eps_sat);
+  }
+
+  // ---- reverse
+  float sd;
+  if (sep) {
+    sd = sqrtf(best);
+    const float coef = 1.0f / (2.0f * sd);   // d sd / d(d^2)
+    // d^2 = |w - t V|^2, w = P - A, t = clamp((w.V) iv2)
+    const float wx = bPx - bAx, wy = bPy - bAy;
+    const float u = fmaf(wx, bVx, wy * bVy) * bIv;
+    const float t = clamp01(u);
+    const float tp = (u > 0.f && u < 1.f) ? 1.f : 0.f;
+    const float rx = 2.f * coef * fmaf(-t, bVx, wx), ry = 2.f * coef * fmaf(-t, bVy, wy);
+    const float rv = fmaf(rx, bVx, ry * bVy) * tp * bIv;
+    const float gwx = rx - rv * bVx, gwy = ry - rv * bVy;              // d/dw
+    if (btype == 0) {
+      // P is a robot vertex (fixed); A = A~_j and V = v_j move with the pose.
+      add_point(bAx, bAy, -gwx, -gwy);
+      add_vector(bVx, bVy, -t * rx - rv * wx, -t * ry - rv * wy);
+    } else {
+      // P is an obstacle point; the robot edge is fixed.
+      add_point(bPx, bPy, gwx, gwy);
+    }
+  } else {
+    // sd = -depth; d depth / d delta+_q is the softmax weight (hard minimum:
+    // 1 at the first minimum); d delta+ / d delta = 1 for delta > 0, else 0.
+    float mu = __builtin_huge_valf();
+    int qmin = 0;
+#pragma unroll
+    for (int q = 0; q < KA; ++q) {
+      const float dp = fmaxf(dl[q], 0.0f);
+      if (live_q(q) && dp < mu) { mu = dp; qmin = q; }
+    }
+    float depth = mu, acc = 1.0f;
+    if (!F.hard) {
+      acc = 0.0f;
+#pragma unroll
+      for (int q = 0; q < KA; ++q)
+        if (live_q(q)) acc += expf(-F.eta * (fmaxf(dl[q], 0.0f) - mu));
+      depth = mu - logf(acc) / F.eta;
+    }
+    sd = -depth;
+#pragma unroll
+    for (int q = 0; q < KA; ++q) {
+      if (!live_q(q) || !(dl[q] > 0.f)) continue;
+      const float w = F.hard ? ((q == qmin) ? 1.f : 0.f) : expf(-F.eta * (dl[q] - mu)) / acc;
+      if (w == 0.f) continue;
+      const float gd = -w;   // d sd / d delta_q
+      float nxq, nyq, lo, hi, lox, loy, hix, hiy;
+      axis(q, nxq, nyq);
+      obst_range(nxq, nyq, lo, hi, lox, loy, hix, hiy);
+      if (q < MF) {
+        // robot axis: constant in the local frame
+        if (hi - F.pa[q] <= F.pb[q] - lo) add_point(hix, hiy, gd * nxq, gd * nyq);   // beta_i - alpha_P
+        else add_point(lox, loy, -gd * nxq, -gd * nyq);                            // beta_P - alpha_i
+      } else {
+        const int j = q - MF;
+        float alo, ahi, rlx, rly, rhx, rhy;
+        robot_range(nxq, nyq, alo, ahi, rlx, rly, rhx, rhy);
+        float gnx, gny;
+        if (hi - alo <= ahi - lo) {
+          add_point(hix, hiy, gd * nxq, gd * nyq);
+          gnx = gd * (hix - rlx); gny = gd * (hiy - rly);
+        } else {
+          add_point(lox, loy, -gd * nxq, -gd * nyq);
+          gnx = gd * (rhx - lox); gny = gd * (rhy - loy);
+        }
+        // n' = (-v_y, v_x) * il  =>  d/dv = (g_ny, -g_nx) * il
+        add_vector(L.vx[j], L.vy[j], gny * o.il[j], -gnx * o.il[j]);
+      }
+    }
+  }
+  g[0] = gscale * -(c * sx - s * sy);
+  g[1] = gscale * -(s * sx + c * sy);
+  g[2] = gscale * gth;
+  if (o.bad) sd = __builtin_nanf("");
+  return sd;
+}
+
+}  // namespace psdf

@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI (no GPU work): the library loads, exports
+every entry point include/psdf.h declares, and its host validation returns
+the documented error codes before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2607_04310_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "psdf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(psdf_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.lib()
+    syms = declared_symbols()
+    assert "psdf_eval" in syms and "psdf_grad" in syms and "psdf_bwd" in syms
+    for name in syms:
+        assert hasattr(lib, name), name
+    assert lib.psdf_version().decode().startswith("psdf")
+
+
+RECT = np.array([[-0.3, -0.2], [0.3, -0.2], [0.3, 0.2], [-0.3, 0.2]], np.float32)
+
+
+def _call_eval(fp, m=None, N=0, edges=None, params=None, poses=1):
+    fp = np.ascontiguousarray(fp, dtype=np.float32)
+    m = fp.shape[0] if m is None else m
+    e = edges if edges is not None else _lib.PsdfEdges(1, 1, 1, 1, 1, 4, 1, 4)
+    p = params or _lib.PsdfParams(1e-12, 1e-6, 1000.0)
+    d = ctypes.c_void_p(1)
+    return _lib.lib().psdf_eval(fp.ctypes.data_as(ctypes.c_void_p), m, ctypes.c_void_p(poses), N,
+                                ctypes.byref(e), ctypes.byref(p), d, d, d, d, None)
+
+
+def test_valid_footprint_with_no_stage_is_a_no_op():
+    assert _call_eval(RECT) == _lib.PSDF_OK
+    assert _call_eval(RECT[::-1]) == _lib.PSDF_OK        # clockwise accepted
+
+
+@pytest.mark.parametrize("fp,code", [
+    (RECT[:2], _lib.PSDF_ENONCONVEX),                                   # m = 2
+    (np.zeros((17, 2)), _lib.PSDF_ENONCONVEX),                          # m = 17
+    (np.array([[0, 0], [1, 0], [0.2, 0.2], [0, 1]]), _lib.PSDF_ENONCONVEX),   # reflex vertex
+    (np.array([[0, 0], [1, 0], [1, 0], [0, 1]]), _lib.PSDF_EDEGENERATE),      # zero-length edge
+    (np.array([[0, 0], [1, 0], [2, 0], [0, 1]]), _lib.PSDF_ENONCONVEX),       # collinear
+    (np.array([[0, 0], [1, 0], [0, 1], [1, 1]]), _lib.PSDF_ENONCONVEX),       # bow tie
+])
+def test_footprint_validation(fp, code):
+    assert _call_eval(fp) == code
+    assert _lib.lib().psdf_last_error().decode() != ""
+
+
+def test_self_intersecting_star_rejected():
+    ang = np.deg2rad(144.0 * np.arange(5))                 # pentagram: every turn is left
+    star = np.stack([np.cos(ang), np.sin(ang)], 1)
+    assert _call_eval(star) == _lib.PSDF_ENONCONVEX
+
+
+@pytest.mark.parametrize("mbar", [0, 17])
+def test_mbar_bound(mbar):
+    e = _lib.PsdfEdges(1, 1, 1, 1, 1, 4, 1, mbar)
+    assert _call_eval(RECT, edges=e) == _lib.PSDF_ETOOBIG
+
+
+def test_null_and_negative_arguments():
+    assert _call_eval(RECT, N=-1) == _lib.PSDF_EINVAL
+    assert _call_eval(RECT, N=3, poses=0) == _lib.PSDF_EINVAL
+    assert _call_eval(RECT, edges=_lib.PsdfEdges(0, 1, 1, 1, 1, 4, 1, 4)) == _lib.PSDF_EINVAL
+    assert _call_eval(RECT, edges=_lib.PsdfEdges(1, 1, 1, 1, 0, 4, 1, 4)) == _lib.PSDF_EINVAL
+    assert _call_eval(RECT, edges=_lib.PsdfEdges(1, 1, 1, 1, 1, -4, 1, 4)) == _lib.PSDF_EINVAL
+    nan_params = _lib.PsdfParams(1e-12, 1e-6, float("nan"))
+    assert _call_eval(RECT, params=nan_params) == _lib.PSDF_EINVAL
+    assert _call_eval(RECT, params=_lib.PsdfParams(-1.0, 1e-6, 1.0)) == _lib.PSDF_EINVAL
+
+
+def test_encode_workspace_query():
+    assert _lib.lib().psdf_encode_ws_bytes(0) == 0
+    assert _lib.lib().psdf_encode_ws_bytes(1000) >= 4000

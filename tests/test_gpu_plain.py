@@ -1,0 +1,226 @@
+"""GPU parity of psdf_eval / psdf_grad / psdf_bwd / psdf_encode_padded
+(through the C ABI) against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2607_04310_amd import inputs
+from parity import check_stages
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_04310_amd import api as _api
+    return _api
+
+
+def run(api, inst, eta=1000.0, grad=True):
+    print(f"[run] {inst.meta.get('workload')} N={inst.N} E={inst.E} M={inst.M} m={len(inst.footprint)} eta={eta}", flush=True)
+    edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar)
+    poses = torch.tensor(inst.poses, device="cuda")
+    p = api.Params(eta=eta)
+    if grad:
+        d, e, o, g, k = api.psdf_grad(inst.footprint, poses, edges, p)
+        torch.cuda.synchronize()
+        return d.cpu().numpy(), e.cpu().numpy(), o.cpu().numpy(), g.cpu().numpy()
+    d, e, o, k = api.psdf_eval(inst.footprint, poses, edges, p)
+    torch.cuda.synchronize()
+    return d.cpu().numpy(), e.cpu().numpy(), o.cpu().numpy(), None
+
+
+def check(inst, out, eta, stages=None):
+    d, e, o, g = out
+    return check_stages(inst.footprint, inst.poses, inst.edges, inst.obst_off, eta, d, e, o, g,
+                        stages=stages)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("eta", [1000.0, math.inf, 50.0])
+def test_c1(api, seed, eta):
+    inst = inputs.c1(seed)
+    st = check(inst, run(api, inst, eta), eta)
+    assert st["stages"] >= 18
+
+
+def test_c1_eval_matches_grad(api):
+    inst = inputs.c1(0)
+    a = run(api, inst, grad=False)
+    b = run(api, inst, grad=True)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+
+
+def test_c2_full(api):
+    inst = inputs.c2(0)
+    st = check(inst, run(api, inst), 1000.0)
+    assert st["stages"] >= 45
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_mixed(api, seed):
+    """Random convex footprints (3-8 vertices, some clockwise), rectangles and
+    free segments packed around the poses so that many stages penetrate."""
+    rng = np.random.default_rng(1000 + seed)
+    inst = inputs.random_small(rng, n_obst=40, n_poses=70, segments=12, lo=-3, hi=3)
+    if seed % 2:
+        inst.footprint = inst.footprint[::-1].copy()
+    st = check(inst, run(api, inst), 1000.0)
+    assert st["stages"] >= 60 and st["pen"] > 0
+
+
+def _polygon_set(rng, n, kmax, lo, hi):
+    edges, sizes = [], []
+    for _ in range(n):
+        k = int(rng.integers(3, kmax + 1))
+        ang = np.sort(rng.uniform(0, 2 * np.pi, k))
+        r = rng.uniform(0.1, 0.6)
+        c = rng.uniform(lo, hi, 2)
+        pts = (c + r * np.stack([np.cos(ang), np.sin(ang)], 1)).astype(np.float32)
+        pts = inputs._hull_ccw(pts).astype(np.float32)
+        if rng.random() < 0.5:
+            pts = pts[::-1]
+        edges.append(np.concatenate([pts, np.roll(pts, -1, 0)], 1))
+        sizes.append(len(pts))
+    return np.concatenate(edges).astype(np.float32), inputs.csr_offsets(sizes)
+
+
+@pytest.mark.parametrize("kmax,m", [(8, 5), (16, 7), (16, 12), (6, 16)])
+def test_general_polygons(api, kmax, m):
+    """Obstacles of up to 16 edges (both orientations) and footprints of up to
+    16 vertices exercise the 8- and 16-edge classes and the padded footprint."""
+    rng = np.random.default_rng(kmax * 100 + m)
+    edges, off = _polygon_set(rng, 30, kmax, -2.5, 2.5)
+    ang = np.linspace(0, 2 * np.pi, m, endpoint=False) + 0.1
+    fp = (0.4 * np.stack([np.cos(ang), 0.7 * np.sin(ang)], 1)).astype(np.float32)
+    inst = inputs.Instance(fp, inputs.uniform_poses(rng, 50, -2.5, 2.5), edges, off,
+                           int(np.diff(off).max()), dict(workload="polygons"))
+    st = check(inst, run(api, inst), 1000.0)
+    assert st["stages"] >= 45
+
+
+@pytest.mark.parametrize("M,N", [(1, 1), (63, 65), (65, 63), (257, 130), (1000, 7), (3000, 129)])
+def test_ragged_sizes(api, M, N):
+    rng = np.random.default_rng(M * 7 + N)
+    edges = inputs.random_rects(rng, M, 0.1, 0.8, -6, 6)
+    inst = inputs.Instance(inputs.rect_footprint(), inputs.uniform_poses(rng, N, -6, 6), edges,
+                           inputs.csr_offsets([4] * M), 4, dict(workload="ragged"))
+    st = check(inst, run(api, inst), 1000.0)
+    assert st["stages"] + 0 >= N - 2
+
+
+def test_empty_and_padding(api):
+    rng = np.random.default_rng(5)
+    fp = inputs.rect_footprint()
+    poses = inputs.uniform_poses(rng, 9, -2, 2)
+    # no obstacles at all
+    inst = inputs.Instance(fp, poses, np.zeros((0, 4), np.float32), np.zeros(1, np.int32), 4,
+                           dict(workload="empty"))
+    d, e, o, g = run(api, inst)
+    assert np.all(np.isinf(d)) and np.all(e == -1) and np.all(o == -1) and np.all(g == 0)
+    # only empty obstacles
+    inst.obst_off = np.zeros(5, np.int32)
+    d, e, o, g = run(api, inst)
+    assert np.all(np.isinf(d)) and np.all(e == -1) and np.all(g == 0)
+    # empty obstacles between real ones (the paper's S = 0 padding)
+    edges = inputs.random_rects(rng, 6, 0.2, 1.0, -2, 2)
+    sizes = [0, 4, 0, 0, 4, 4, 0, 4, 4, 4, 0]
+    inst = inputs.Instance(fp, poses, edges, inputs.csr_offsets(sizes), 4, dict(workload="padding"))
+    check(inst, run(api, inst), 1000.0)
+
+
+def test_nan_pose_and_bad_obstacle(api):
+    inst = inputs.c1(0)
+    inst.poses = inst.poses.copy()
+    inst.poses[3, 0] = np.nan
+    inst.poses[7, 2] = np.inf
+    d, e, o, g = run(api, inst)
+    assert np.isnan(d[3]) and e[3] == -1 and o[3] == -1 and np.all(np.isnan(g[3]))
+    assert np.isnan(d[7]) and e[7] == -1
+    ok = np.setdiff1d(np.arange(inst.N), [3, 7])
+    check(inst, (d, e, o, g), 1000.0, stages=ok)
+    # an obstacle with more edges than mbar poisons every stage with NaN
+    bad = inputs.c1(1)
+    bad.obst_off = bad.obst_off.copy()
+    bad.obst_off[5] += 1          # obstacle 4 now has 5 edges, obstacle 5 has 3
+    d, e, o, g = run(api, bad)
+    assert np.all(np.isnan(d)) and np.all(e == -1) and np.all(o == -1)
+
+
+def test_bwd_and_autograd_c3(api):
+    """Config 3: PsdfFunction backward (psdf_bwd) against the oracle gradient
+    times random upstream gradients, penetrating stages included."""
+    for seed in range(3):
+        inst = inputs.c3(seed)
+        gout = inst.meta["gout"]
+        edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar)
+        poses = torch.tensor(inst.poses, device="cuda", requires_grad=True)
+        d = api.PsdfFunction.apply(poses, inst.footprint, edges)
+        (d * torch.tensor(gout, device="cuda")).sum().backward()
+        torch.cuda.synchronize()
+        dd = d.detach().cpu().numpy()
+        gp = poses.grad.cpu().numpy()
+        # obstacle / edge come from a plain psdf_grad call on the same inputs
+        _, e, o, _ = run(api, inst)
+        st = check_stages(inst.footprint, inst.poses, inst.edges, inst.obst_off, 1000.0, dd, e, o,
+                          gp, gscale=gout)
+        assert st["pen"] > 0
+
+
+def test_bwd_matches_grad_times_gout(api):
+    inst = inputs.c2(0)
+    edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar)
+    poses = torch.tensor(inst.poses, device="cuda")
+    d, e, o, g, k = api.psdf_grad(inst.footprint, poses, edges)
+    gout = torch.randn(inst.N, device="cuda")
+    gp = api.psdf_bwd(inst.footprint, poses, edges, k, gout)
+    torch.cuda.synchronize()
+    assert torch.equal(gp, g * gout[:, None])
+
+
+def test_repeatable_bitwise(api):
+    inst = inputs.c2(0)
+    a = run(api, inst)
+    b = run(api, inst)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y, equal_nan=True)
+
+
+def test_encode_padded(api):
+    rng = np.random.default_rng(3)
+    Mbar, mbar = 300, 6
+    A = rng.normal(size=(Mbar, mbar, 2)).astype(np.float32)
+    B = rng.normal(size=(Mbar, mbar, 2)).astype(np.float32)
+    S = rng.random((Mbar, mbar)) < 0.6
+    S[7] = False
+    es = api.psdf_encode_padded(torch.tensor(A, device="cuda"), torch.tensor(B, device="cuda"),
+                                torch.tensor(S, device="cuda"))
+    torch.cuda.synchronize()
+    ref_off = np.concatenate([[0], np.cumsum(S.sum(1))]).astype(np.int32)
+    assert np.array_equal(es.obst_off.cpu().numpy(), ref_off)
+    assert np.array_equal(es.ax.cpu().numpy(), A[S][:, 0])
+    assert np.array_equal(es.ay.cpu().numpy(), A[S][:, 1])
+    assert np.array_equal(es.bx.cpu().numpy(), B[S][:, 0])
+    assert np.array_equal(es.by.cpu().numpy(), B[S][:, 1])
+    # the encoded set evaluates like the CSR set built on the host
+    inst = inputs.c1(2)
+    Ap = inst.edges[:, :2].reshape(64, 4, 2)
+    Bp = inst.edges[:, 2:].reshape(64, 4, 2)
+    Ap = np.concatenate([Ap, np.zeros((64, 2, 2), np.float32)], 1)
+    Bp = np.concatenate([Bp, np.zeros((64, 2, 2), np.float32)], 1)
+    Sp = np.zeros((64, 6), bool)
+    Sp[:, :4] = True
+    es = api.psdf_encode_padded(torch.tensor(Ap, device="cuda"), torch.tensor(Bp, device="cuda"),
+                                torch.tensor(Sp, device="cuda"))
+    poses = torch.tensor(inst.poses, device="cuda")
+    d1 = api.psdf_grad(inst.footprint, poses, es)
+    d2 = api.psdf_grad(inst.footprint, poses, api.EdgeSet(inst.edges, inst.obst_off, 4))
+    torch.cuda.synchronize()
+    for x, y in zip(d1[:4], d2[:4]):
+        assert torch.equal(x, y)

@@ -77,9 +77,10 @@ def main():
            torch.empty(N, dtype=torch.int32, device=dev), torch.empty((N, 3), device=dev),
            torch.empty(N, dtype=torch.int64, device=dev))
     params = api.Params()
+    ws = api.workspace(N, M, dev)
 
     def step():
-        api.psdf_grad(inst.footprint, poses, edges, params, out=out)
+        api.psdf_grad(inst.footprint, poses, edges, params, out=out, ws=ws)
 
     for _ in range(args.warmup):
         step()

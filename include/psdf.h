@@ -47,9 +47,13 @@
  *    point-segment pool distance (lowest index on ties), grad[3s..3s+2] =
  *    dphi/d(x, y, theta).  An empty edge set gives d = +inf, obst = edge = -1,
  *    grad = 0; a non-finite pose gives d = NaN, obst = edge = -1, grad = NaN.
- *  - keys (device uint64[N]) is scratch for the per-stage minimum and, on
- *    return, holds the winner of each stage: (orderable(sd) << 32) | obstacle.
- *    psdf_bwd consumes it.
+ *  - keys (device uint64[N]) receives the winner of each stage:
+ *    (orderable(sd) << 32) | obstacle, where orderable maps floats to
+ *    unsigned integers in the same order (NaN lowest).  psdf_bwd consumes it.
+ *  - ws (device, caller-owned) is scratch of at least
+ *    psdf_workspace_bytes(N, M) bytes: the per-work-group partial minima
+ *    and the winners' edge ranges.
+ *    Its content on entry does not matter.
  */
 #ifndef PSDF_H
 #define PSDF_H
@@ -103,23 +107,29 @@ const char* psdf_last_error(void);
 /* Library version string. */
 const char* psdf_version(void);
 
+/* Bytes of the ws argument of psdf_eval / psdf_grad for N stages and M
+ * obstacles (0 when N or M is 0). */
+size_t psdf_workspace_bytes(int32_t N, int32_t M);
+
 /* psdf_eval - phi, winning obstacle and edge for N stage poses (Sec. IV-A..D;
  * Alg. 1, PSDF_Forward).
  *   footprint  host float32[m][2]
  *   poses      device float32[N][3]
  *   edges      host struct describing device arrays
  *   params     host; NULL selects the defaults
- *   d, edge, obst, keys   device outputs of length N (see conventions) */
+ *   d, edge, obst, keys   device outputs of length N (see conventions)
+ *   ws, ws_bytes          device scratch (see conventions) */
 int psdf_eval(const float* footprint, int32_t m, const float* poses, int32_t N,
               const psdf_edges* edges, const psdf_params* params, float* d, int32_t* edge,
-              int32_t* obst, uint64_t* keys, hipStream_t stream);
+              int32_t* obst, uint64_t* keys, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* psdf_grad - psdf_eval plus grad (device float32[N][3]) = dphi/d(x, y, theta)
  * of each stage, the reverse-mode adjoint through the winning obstacle
  * (Sec. IV-D active-branch subgradient; Alg. 1, PSDF_Backward). */
 int psdf_grad(const float* footprint, int32_t m, const float* poses, int32_t N,
               const psdf_edges* edges, const psdf_params* params, float* d, int32_t* edge,
-              int32_t* obst, float* grad, uint64_t* keys, hipStream_t stream);
+              int32_t* obst, float* grad, uint64_t* keys, void* ws, size_t ws_bytes,
+              hipStream_t stream);
 
 /* psdf_bwd - vector-Jacobian product of phi with respect to the poses:
  * gpose[s] = gout[s] * dphi_s/d(x, y, theta) (Alg. 1, PSDF_Backward), from the
@@ -143,10 +153,150 @@ int psdf_encode_padded(const float* A, const float* B, const uint8_t* S, int32_t
                        int32_t mbar, float* ax, float* ay, float* bx, float* by,
                        int32_t* obst_off, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Uneven batches: many independent instances (robots or candidate horizons),
+ * each with its own footprint, horizon and edge set, evaluated by persistent
+ * launches (one per footprint size present; work items = instance x stage
+ * block x obstacle tile, pulled from a device counter, longest first) that
+ * also run each stage's winner adjoint.  Every instance is the plain problem of psdf_grad
+ * (Sec. IV-A..D); the batch only changes how the work is scheduled.
+ *
+ * Packed inputs (device, caller-owned): poses float32[sum N][3]; edge
+ * columns ax, ay, bx, by float32[sum E]; obstacle offsets int32[sum (M + 1)]
+ * with each instance's offsets relative to its own first edge (they start at
+ * 0).  Outputs (device, length sum N, rows in the packed pose order): d,
+ * edge (index within the instance's edges), obst (index within the
+ * instance's obstacles), grad [sum N][3], keys.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t fp_off;   /* first vertex of this instance's footprint in the host footprint array */
+  int32_t m;        /* its vertex count, 3..16 */
+  int32_t pose_off; /* first stage row in the packed poses */
+  int32_t N;        /* stages */
+  int32_t edge_off; /* first edge in the packed edge columns */
+  int32_t E;        /* edges */
+  int32_t obst_off; /* first entry of its offsets in the packed offset array */
+  int32_t M;        /* obstacles (M + 1 offsets) */
+} psdf_batch_desc;
+
+typedef struct psdf_batch_plan psdf_batch_plan;
+
+enum {
+  PSDF_BATCH_GRAPH = 1,    /* replay a captured hipGraph (captured on first run) */
+  PSDF_BATCH_AUTOTUNE = 2  /* psdf_batch_autotune may pick the launch shape */
+};
+
+/* Build a plan.  desc: host array of n_inst descriptors; footprints: host
+ * float32[][2] indexed by desc[k].fp_off; mbar: bound on the edges per
+ * obstacle over all instances (1..16).  Validates every footprint
+ * (PSDF_ENONCONVEX / PSDF_EDEGENERATE name the instance in the message),
+ * allocates the plan's device tables and scratch (freed by
+ * psdf_batch_plan_destroy) on the current device.  Calls that use one plan
+ * must not overlap in time (the plan's scratch is shared). */
+int psdf_batch_plan_create(psdf_batch_plan** plan, const psdf_batch_desc* desc, int32_t n_inst,
+                           const float* footprints, int32_t mbar, const psdf_params* params,
+                           int32_t flags);
+void psdf_batch_plan_destroy(psdf_batch_plan* plan);
+
+/* Evaluate every instance: d, edge, obst, grad and keys as described above.
+ * With PSDF_BATCH_GRAPH the first call (and any call whose pointers differ
+ * from the captured ones) captures the launch into a hipGraph on a
+ * plan-owned stream; later calls replay it on `stream`.  Input contents may
+ * change between replays. */
+int psdf_batch(psdf_batch_plan* plan, const float* poses, const float* ax, const float* ay,
+               const float* bx, const float* by, const int32_t* obst_off, float* d,
+               int32_t* edge, int32_t* obst, float* grad, uint64_t* keys, hipStream_t stream);
+
+/* Autotune the plan's launch shape on real inputs (same arguments as
+ * psdf_batch): times each candidate (stages per work item x obstacles per
+ * tile) on `stream`, synchronising it, keeps the fastest in the plan and in a
+ * process-wide cache keyed by the batch's size signature (later plans of the
+ * same signature start from it; with PSDF_TUNE_CACHE set to a file path the
+ * cache is also read from and appended to that file).  Outputs are left
+ * holding a valid result.  best_ms (host, may be NULL) gets the best time. */
+int psdf_batch_autotune(psdf_batch_plan* plan, const float* poses, const float* ax,
+                        const float* ay, const float* bx, const float* by,
+                        const int32_t* obst_off, float* d, int32_t* edge, int32_t* obst,
+                        float* grad, uint64_t* keys, hipStream_t stream, float* best_ms);
+
+/* The plan's current shape, work-item count and the largest persistent grid
+ * of its launches (one per footprint-size group; host outputs, may be NULL). */
+int psdf_batch_plan_info(const psdf_batch_plan* plan, int32_t* stages_per_item,
+                         int32_t* obstacles_per_tile, int32_t* n_items, int32_t* grid);
+
+/* Certified screened evaluation of a batch (same outputs as psdf_batch, bit
+ * for bit).  Per stage: a conservative lower bound LB_i <= sd_i for every
+ * obstacle (distance from the pose origin to the obstacle minus the
+ * footprint's radius about that origin, minus 1e-3 m; -inf if the origin is
+ * inside), a pool of about `pool` lowest-LB obstacles (1..512), a ranking of
+ * the pool's edges by the screener MLP (theta: device float32[PSDF_MLP_PARAMS],
+ * see below) or, with theta = NULL, by the edge's distance to the pose origin,
+ * exact evaluation of the obstacles owning the `topk` best edges, and the
+ * certificate min over every other obstacle of LB_i > max(phi_K, tau), where
+ * phi_K is the candidates' minimum and tau the distance above which the axis
+ * test separates two convex sets for this footprint.  Stages that fail the
+ * certificate are evaluated in full.  Assumes convex obstacles (Assumption 1)
+ * and at most 16384 obstacles per instance (PSDF_ETOOBIG otherwise).
+ * Optional device outputs (length sum N, may be NULL): stage_cand = obstacles
+ * evaluated exactly by the screen, stage_cert = 1 if certified, cand_keys =
+ * the candidates' minimum key before any fallback. */
+int psdf_batch_screened(psdf_batch_plan* plan, const float* theta, int32_t pool, int32_t topk,
+                        const float* poses, const float* ax, const float* ay, const float* bx,
+                        const float* by, const int32_t* obst_off, float* d, int32_t* edge,
+                        int32_t* obst, float* grad, uint64_t* keys, int32_t* stage_cand,
+                        int32_t* stage_cert, uint64_t* cand_keys, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Edge-screener MLP: 4 -> 64 -> 64 -> 1 with ReLU on per-(stage, edge)
+ * features (the edge's endpoints in the robot frame, divided by 4 m).
+ * Parameters: device float32[PSDF_MLP_PARAMS] = W1[64][4], b1[64],
+ * W2[64][64], b2[64], w3[64], b3.  The kernels round the matrix operands to
+ * BF16 and accumulate in FP32 on the matrix cores.
+ * ------------------------------------------------------------------------ */
+#define PSDF_MLP_PARAMS 4545
+
+/* y[i] = MLP(X[i]) for B feature rows X (device float32[B][4]). */
+int psdf_mlp_forward(const float* theta, const float* X, int32_t B, float* y, hipStream_t stream);
+
+/* Workspace bytes of psdf_mlp_grad / psdf_mlp_train_step for B rows. */
+size_t psdf_mlp_ws_bytes(int32_t B);
+
+/* Gradient of the mean squared error mean_i (MLP(X_i) - T_i)^2 with respect
+ * to theta: grad device float32[PSDF_MLP_PARAMS + 1], the last entry is the
+ * loss.  Deterministic (fixed reduction order). */
+int psdf_mlp_grad(const float* theta, const float* X, const float* T, int32_t B, float* grad,
+                  void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One training step: the gradient as above, then Adam (beta1 0.9, beta2
+ * 0.999, eps 1e-8, step >= 1, learning rate lr) on theta with moments m, v
+ * (device float32[PSDF_MLP_PARAMS], zero before step 1); loss (device float,
+ * may be NULL) receives the batch loss before the update. */
+int psdf_mlp_train_step(float* theta, float* m, float* v, int32_t step, float lr, const float* X,
+                        const float* T, int32_t B, float* loss, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* Training pairs: for n sampled (stage row, edge index within that stage's
+ * instance) pairs of a batch, X[i] (device float32[n][4]) = the edge's
+ * robot-frame endpoints / 4 m and T[i] = its pool distance: the minimum over
+ * the robot vertices to the edge and over its two endpoints to the robot
+ * edges (Sec. IV-B), clipped to [0, 5] m.  Out-of-range pairs give NaN. */
+int psdf_screen_labels(const psdf_batch_plan* plan, const float* poses, const float* ax,
+                       const float* ay, const float* bx, const float* by, const int32_t* stage,
+                       const int32_t* edge, int32_t n, float* X, float* T, hipStream_t stream);
+
+/* Launch shape of the per-stage minimum kernel: blk obstacles per work-group
+ * (64 or 256) and sb stages per work-group (1..64).  A non-zero blk overrides
+ * every later call in the process (for sweeps and the autotuner); blk = 0
+ * restores the automatic choice (the autotuner's cached shape for the
+ * problem size if it has one, else a heuristic).  Results do not depend on
+ * the shape (the minimum and its tie rule are exact). */
+int psdf_set_launch_shape(int32_t blk, int32_t sb);
+
 /* Kernel timer, an instrumentation aid for benchmarks.  With capacity > 0,
  * each launch of the dominant kernel of an entry point (the per-stage minimum
- * kernel of psdf_eval / psdf_grad) is bracketed by a pair of HIP events
- * recorded on the launch stream, for up to `capacity` launches.
+ * kernel of psdf_eval / psdf_grad, the persistent kernel or graph replay of
+ * psdf_batch) is bracketed by a pair of HIP events recorded on the launch
+ * stream, for up to `capacity` launches.
  * psdf_timer_read waits for those events, returns their summed duration in
  * milliseconds and the number of timed launches, and starts a new count.
  * capacity 0 turns the timer off and releases its events.  Not thread-safe

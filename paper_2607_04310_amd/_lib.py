@@ -23,6 +23,7 @@ PSDF_EWS = -5
 PSDF_EHIP = -6
 MAX_FP_VERTS = 16
 MAX_OBST_EDGES = 16
+MLP_PARAMS = 4545
 
 
 class PsdfParams(ctypes.Structure):
@@ -33,6 +34,16 @@ class PsdfEdges(ctypes.Structure):
     _fields_ = [("ax", ctypes.c_void_p), ("ay", ctypes.c_void_p), ("bx", ctypes.c_void_p),
                 ("by", ctypes.c_void_p), ("obst_off", ctypes.c_void_p), ("E", ctypes.c_int32),
                 ("M", ctypes.c_int32), ("mbar", ctypes.c_int32)]
+
+
+class PsdfBatchDesc(ctypes.Structure):
+    _fields_ = [("fp_off", ctypes.c_int32), ("m", ctypes.c_int32), ("pose_off", ctypes.c_int32),
+                ("N", ctypes.c_int32), ("edge_off", ctypes.c_int32), ("E", ctypes.c_int32),
+                ("obst_off", ctypes.c_int32), ("M", ctypes.c_int32)]
+
+
+PSDF_BATCH_GRAPH = 1
+PSDF_BATCH_AUTOTUNE = 2
 
 
 class PsdfError(RuntimeError):
@@ -48,10 +59,28 @@ _I32 = ctypes.c_int32
 _SIGS = {
     "psdf_last_error": (ctypes.c_char_p, []),
     "psdf_version": (ctypes.c_char_p, []),
+    "psdf_workspace_bytes": (ctypes.c_size_t, [_I32, _I32]),
     "psdf_eval": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
-                                 ctypes.POINTER(PsdfParams), _VP, _VP, _VP, _VP, _VP]),
+                                 ctypes.POINTER(PsdfParams), _VP, _VP, _VP, _VP, _VP,
+                                 ctypes.c_size_t, _VP]),
     "psdf_grad": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
-                                 ctypes.POINTER(PsdfParams), _VP, _VP, _VP, _VP, _VP, _VP]),
+                                 ctypes.POINTER(PsdfParams), _VP, _VP, _VP, _VP, _VP, _VP,
+                                 ctypes.c_size_t, _VP]),
+    "psdf_set_launch_shape": (ctypes.c_int, [_I32, _I32]),
+    "psdf_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(PsdfBatchDesc),
+                                              _I32, _VP, _I32, ctypes.POINTER(PsdfParams), _I32]),
+    "psdf_batch_plan_destroy": (None, [_VP]),
+    "psdf_batch": (ctypes.c_int, [_VP] + [_VP] * 11 + [_VP]),
+    "psdf_batch_autotune": (ctypes.c_int, [_VP] + [_VP] * 11 + [_VP, ctypes.POINTER(ctypes.c_float)]),
+    "psdf_batch_screened": (ctypes.c_int, [_VP, _VP, _I32, _I32] + [_VP] * 11 + [_VP] * 3 + [_VP]),
+    "psdf_screen_labels": (ctypes.c_int, [_VP] + [_VP] * 5 + [_VP, _VP, _I32, _VP, _VP, _VP]),
+    "psdf_mlp_forward": (ctypes.c_int, [_VP, _VP, _I32, _VP, _VP]),
+    "psdf_mlp_ws_bytes": (ctypes.c_size_t, [_I32]),
+    "psdf_mlp_grad": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP, _VP, ctypes.c_size_t, _VP]),
+    "psdf_mlp_train_step": (ctypes.c_int, [_VP, _VP, _VP, _I32, ctypes.c_float, _VP, _VP, _I32,
+                                           _VP, _VP, ctypes.c_size_t, _VP]),
+    "psdf_batch_plan_info": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                            ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "psdf_bwd": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
                                 ctypes.POINTER(PsdfParams), _VP, _VP, _VP, _VP]),
     "psdf_encode_ws_bytes": (ctypes.c_size_t, [_I32]),

@@ -75,7 +75,13 @@ def _poses(poses):
     return poses.contiguous()
 
 
-def psdf_eval(footprint, poses, edges: EdgeSet, params: Params | None = None):
+def workspace(N, M, device):
+    """Scratch tensor for psdf_eval / psdf_grad of N stages and M obstacles."""
+    nbytes = int(_lib.lib().psdf_workspace_bytes(int(N), int(M)))
+    return torch.empty(max(nbytes, 8), dtype=torch.uint8, device=device)
+
+
+def psdf_eval(footprint, poses, edges: EdgeSet, params: Params | None = None, ws=None):
     """phi, edge, obstacle and winner keys per stage (psdf_eval of the C ABI)."""
     params = params or Params()
     poses = _poses(poses)
@@ -85,15 +91,18 @@ def psdf_eval(footprint, poses, edges: EdgeSet, params: Params | None = None):
     edge = torch.empty(N, dtype=torch.int32, device=dev)
     obst = torch.empty(N, dtype=torch.int32, device=dev)
     keys = torch.empty(N, dtype=torch.int64, device=dev)
+    ws = workspace(N, edges.M, dev) if ws is None else ws
     fp, fpp, m = _fp(footprint)
     ec, pc = edges.c(), params.c()
     _lib.check(_lib.lib().psdf_eval(fpp, m, poses.data_ptr(), N, ctypes.byref(ec),
                                     ctypes.byref(pc), d.data_ptr(), edge.data_ptr(),
-                                    obst.data_ptr(), keys.data_ptr(), _lib.stream_handle()))
+                                    obst.data_ptr(), keys.data_ptr(), ws.data_ptr(),
+                                    ws.numel(), _lib.stream_handle()))
     return d, edge, obst, keys
 
 
-def psdf_grad(footprint, poses, edges: EdgeSet, params: Params | None = None, out=None):
+def psdf_grad(footprint, poses, edges: EdgeSet, params: Params | None = None, out=None,
+              ws=None):
     """phi, edge, obstacle, dphi/d(x, y, theta) and winner keys per stage."""
     params = params or Params()
     poses = _poses(poses)
@@ -106,12 +115,13 @@ def psdf_grad(footprint, poses, edges: EdgeSet, params: Params | None = None, ou
                torch.empty((N, 3), dtype=torch.float32, device=dev),
                torch.empty(N, dtype=torch.int64, device=dev))
     d, edge, obst, grad, keys = out
+    ws = workspace(N, edges.M, dev) if ws is None else ws
     fp, fpp, m = _fp(footprint)
     ec, pc = edges.c(), params.c()
     _lib.check(_lib.lib().psdf_grad(fpp, m, poses.data_ptr(), N, ctypes.byref(ec),
                                     ctypes.byref(pc), d.data_ptr(), edge.data_ptr(),
                                     obst.data_ptr(), grad.data_ptr(), keys.data_ptr(),
-                                    _lib.stream_handle()))
+                                    ws.data_ptr(), ws.numel(), _lib.stream_handle()))
     return d, edge, obst, grad, keys
 
 
@@ -169,5 +179,169 @@ class PsdfFunction(torch.autograd.Function):
         return gpose, None, None, None
 
 
+class Batch:
+    """Uneven batch of independent instances evaluated by one persistent
+    launch (psdf_batch).  ``instances`` is a sequence of objects with
+    ``footprint`` (m, 2), ``poses`` (N, 3), ``edges`` (E, 4) and ``obst_off``
+    (M + 1,); they are packed host-side once and uploaded."""
+
+    def __init__(self, instances, mbar=None, params: Params | None = None, graph=True,
+                 autotune=False, device="cuda"):
+        self.params = params or Params()
+        fps, poses, edges, offs, desc = [], [], [], [], []
+        nfp = npose = nedge = noff = 0
+        for inst in instances:
+            fp = np.asarray(inst.footprint, dtype=np.float32).reshape(-1, 2)
+            ps = np.asarray(inst.poses, dtype=np.float32).reshape(-1, 3)
+            ed = np.asarray(inst.edges, dtype=np.float32).reshape(-1, 4)
+            of = np.asarray(inst.obst_off, dtype=np.int32)
+            desc.append((nfp, len(fp), npose, len(ps), nedge, len(ed), noff, len(of) - 1))
+            fps.append(fp); poses.append(ps); edges.append(ed); offs.append(of)
+            nfp += len(fp); npose += len(ps); nedge += len(ed); noff += len(of)
+        if mbar is None:
+            sizes = np.concatenate([np.diff(o) for o in offs]) if offs else np.ones(1)
+            mbar = int(max(1, sizes.max() if len(sizes) else 1))
+        self.mbar = int(mbar)
+        self.desc = desc
+        self.n_inst = len(desc)
+        self.footprints = np.ascontiguousarray(np.concatenate(fps) if fps else np.zeros((1, 2), np.float32))
+        dev = torch.device(device)
+        self.poses = torch.tensor(np.concatenate(poses) if poses else np.zeros((0, 3), np.float32), device=dev)
+        ed = np.concatenate(edges) if edges else np.zeros((0, 4), np.float32)
+        cols = torch.tensor(ed, device=dev).t().contiguous()
+        self.ax, self.ay, self.bx, self.by = (cols[k].contiguous() for k in range(4))
+        self.obst_off = torch.tensor(np.concatenate(offs) if offs else np.zeros(1, np.int32), device=dev)
+        S = int(self.poses.shape[0])
+        self.d = torch.empty(S, dtype=torch.float32, device=dev)
+        self.edge = torch.empty(S, dtype=torch.int32, device=dev)
+        self.obst = torch.empty(S, dtype=torch.int32, device=dev)
+        self.grad = torch.empty((S, 3), dtype=torch.float32, device=dev)
+        self.keys = torch.empty(S, dtype=torch.int64, device=dev)
+        arr = (_lib.PsdfBatchDesc * max(1, self.n_inst))(*[_lib.PsdfBatchDesc(*d) for d in desc])
+        flags = (_lib.PSDF_BATCH_GRAPH if graph else 0) | (_lib.PSDF_BATCH_AUTOTUNE if autotune else 0)
+        plan = ctypes.c_void_p(0)
+        pc = self.params.c()
+        _lib.check(_lib.lib().psdf_batch_plan_create(
+            ctypes.byref(plan), arr, self.n_inst, self.footprints.ctypes.data_as(ctypes.c_void_p),
+            self.mbar, ctypes.byref(pc), flags))
+        self.plan = plan
+
+    def _args(self):
+        return [self.poses.data_ptr(), self.ax.data_ptr(), self.ay.data_ptr(), self.bx.data_ptr(),
+                self.by.data_ptr(), self.obst_off.data_ptr(), self.d.data_ptr(),
+                self.edge.data_ptr(), self.obst.data_ptr(), self.grad.data_ptr(),
+                self.keys.data_ptr()]
+
+    def run(self):
+        _lib.check(_lib.lib().psdf_batch(self.plan, *self._args(), _lib.stream_handle()))
+        return self.d, self.edge, self.obst, self.grad, self.keys
+
+    def autotune(self):
+        best = ctypes.c_float(0.0)
+        _lib.check(_lib.lib().psdf_batch_autotune(self.plan, *self._args(), _lib.stream_handle(),
+                                                  ctypes.byref(best)))
+        return best.value
+
+    def info(self):
+        vals = [ctypes.c_int32(0) for _ in range(4)]
+        _lib.check(_lib.lib().psdf_batch_plan_info(self.plan, *[ctypes.byref(v) for v in vals]))
+        return dict(stages_per_item=vals[0].value, obstacles_per_tile=vals[1].value,
+                    n_items=vals[2].value, grid=vals[3].value)
+
+    def screened(self, theta=None, pool=256, topk=256, stats=False):
+        """Certified screened evaluation (psdf_batch_screened); theta None
+        ranks the pool's edges by distance instead of the MLP.  With
+        stats=True also returns (stage_cand, stage_cert, cand_keys)."""
+        S = int(self.poses.shape[0])
+        dev = self.poses.device
+        cand = torch.empty(S, dtype=torch.int32, device=dev) if stats else None
+        cert = torch.empty(S, dtype=torch.int32, device=dev) if stats else None
+        ck = torch.empty(S, dtype=torch.int64, device=dev) if stats else None
+        tptr = theta.data_ptr() if theta is not None else None
+        _lib.check(_lib.lib().psdf_batch_screened(
+            self.plan, tptr, int(pool), int(topk), *self._args(),
+            cand.data_ptr() if stats else None, cert.data_ptr() if stats else None,
+            ck.data_ptr() if stats else None, _lib.stream_handle()))
+        out = (self.d, self.edge, self.obst, self.grad, self.keys)
+        return (out, (cand, cert, ck)) if stats else out
+
+    def labels(self, stage, edge):
+        """Features (n, 4) and exact pool-distance labels (n,) of (stage row,
+        local edge) pairs (psdf_screen_labels)."""
+        dev = self.poses.device
+        st = torch.as_tensor(np.asarray(stage, dtype=np.int32), device=dev)
+        ed = torch.as_tensor(np.asarray(edge, dtype=np.int32), device=dev)
+        n = int(st.numel())
+        X = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        T = torch.empty(n, dtype=torch.float32, device=dev)
+        _lib.check(_lib.lib().psdf_screen_labels(
+            self.plan, self.poses.data_ptr(), self.ax.data_ptr(), self.ay.data_ptr(),
+            self.bx.data_ptr(), self.by.data_ptr(), st.data_ptr(), ed.data_ptr(), n,
+            X.data_ptr(), T.data_ptr(), _lib.stream_handle()))
+        return X, T
+
+    def instance_views(self, k):
+        """(footprint, poses, EdgeSet) views of instance k in the packed arrays."""
+        fo, m, po, N, eo, E, oo, M = self.desc[k]
+        es = EdgeSet.from_device(self.ax[eo:eo + E], self.ay[eo:eo + E], self.bx[eo:eo + E],
+                                 self.by[eo:eo + E], self.obst_off[oo:oo + M + 1], self.mbar)
+        return self.footprints[fo:fo + m], self.poses[po:po + N], es
+
+    def close(self):
+        if self.plan:
+            _lib.lib().psdf_batch_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def set_launch_shape(blk=0, sb=0):
+    """Override the per-stage minimum kernel's launch shape (blk 0 = automatic)."""
+    _lib.check(_lib.lib().psdf_set_launch_shape(int(blk), int(sb)))
+
+
 def hard_min():
     return Params(eta=math.inf)
+
+
+# ------------------------------------------------------------------ screener MLP
+
+def mlp_forward(theta, X):
+    """MLP outputs for feature rows X (device (B, 4) float32)."""
+    X = X.contiguous()
+    B = int(X.shape[0])
+    y = torch.empty(B, dtype=torch.float32, device=X.device)
+    _lib.check(_lib.lib().psdf_mlp_forward(theta.data_ptr(), X.data_ptr(), B, y.data_ptr(),
+                                           _lib.stream_handle()))
+    return y
+
+
+def _mlp_ws(B, device):
+    nbytes = int(_lib.lib().psdf_mlp_ws_bytes(int(B)))
+    return torch.empty(max(nbytes, 4), dtype=torch.uint8, device=device)
+
+
+def mlp_grad(theta, X, T, ws=None):
+    """(gradient of the mean squared error, loss) on the device."""
+    X, T = X.contiguous(), T.contiguous()
+    B = int(X.shape[0])
+    ws = _mlp_ws(B, X.device) if ws is None else ws
+    g = torch.empty(_lib.MLP_PARAMS + 1, dtype=torch.float32, device=X.device)
+    _lib.check(_lib.lib().psdf_mlp_grad(theta.data_ptr(), X.data_ptr(), T.data_ptr(), B,
+                                        g.data_ptr(), ws.data_ptr(), ws.numel(),
+                                        _lib.stream_handle()))
+    return g[:-1], g[-1]
+
+
+def mlp_train_step(theta, m, v, step, lr, X, T, loss=None, ws=None):
+    """One forward/backward/Adam step on the device (psdf_mlp_train_step)."""
+    B = int(X.shape[0])
+    ws = _mlp_ws(B, X.device) if ws is None else ws
+    _lib.check(_lib.lib().psdf_mlp_train_step(
+        theta.data_ptr(), m.data_ptr(), v.data_ptr(), int(step), float(lr), X.data_ptr(),
+        T.data_ptr(), B, loss.data_ptr() if loss is not None else None, ws.data_ptr(),
+        ws.numel(), _lib.stream_handle()))

@@ -1,0 +1,643 @@
+// psdf_batch: plan, work-item list, hipGraph capture and autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "psdf.h"
+#include "psdf_batch.hpp"
+#include "psdf_host.hpp"
+#include "psdf_screen.hpp"
+
+namespace psdf {
+
+struct Shape {
+  int sb;   // stages per work item
+  int nw;   // waves per work-group (obstacles per tile = 64 nw)
+};
+
+}  // namespace psdf
+
+using namespace psdf;
+
+struct psdf_batch_plan {
+  int device = 0;
+  int n_inst = 0;
+  int mi_class = 4;
+  int flags = 0;
+  int total_stages = 0;
+  std::vector<psdf_batch_desc> desc;
+  std::vector<FpConst> fp;
+  Shape shape{1, 4};
+  int n_items = 0;
+  int cu = 256;
+  // one persistent launch per footprint-size group (MF = 3..8 or 16)
+  struct Group { int mf, start, count, grid; };
+  std::vector<Group> groups;
+  // device memory owned by the plan
+  FpConst* d_fp = nullptr;
+  BatchInst* d_inst = nullptr;
+  BatchItem* d_items = nullptr;
+  size_t items_cap = 0;
+  uint64_t* d_partial = nullptr;   // partial keys, then aux words
+  size_t partial_cap = 0;          // entries of each
+  unsigned* d_blockcnt = nullptr;
+  size_t blockcnt_cap = 0;
+  unsigned* d_ctrl = nullptr;        // two counters per group
+  // screening: stage -> instance, stage rows grouped by footprint size,
+  // failed lists and counters (three per group)
+  int* d_stage_inst = nullptr;
+  int* d_stage_list = nullptr;
+  int* d_failed = nullptr;
+  unsigned* d_sctrl = nullptr;
+  struct SGroup { int mf, start, count, max_tiles; };
+  std::vector<SGroup> sgroups;
+  int max_M = 0;
+  // graph
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> bound;
+};
+
+namespace psdf {
+namespace {
+
+std::mutex g_cache_mu;
+std::map<std::string, Shape> g_cache;
+bool g_cache_loaded = false;
+
+std::string signature(const psdf_batch_plan& p) {
+  // batch size signature: instance count, edge class and log2 buckets of the
+  // stage count and of the stage x edge pairs
+  double pairs = 0.0;
+  for (const auto& d : p.desc) pairs += (double)d.N * d.E;
+  char buf[128];
+  snprintf(buf, sizeof buf, "batch:%d:%d:%d:%d", p.n_inst, p.mi_class,
+           (int)std::lround(std::log2(std::max(1, p.total_stages))),
+           (int)std::lround(std::log2(std::max(1.0, pairs))));
+  return buf;
+}
+
+void cache_load_locked() {
+  if (g_cache_loaded) return;
+  g_cache_loaded = true;
+  const char* path = std::getenv("PSDF_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char key[128];
+  int sb, nw;
+  while (std::fscanf(f, "%127s %d %d", key, &sb, &nw) == 3)
+    if (sb >= 1 && sb <= kMaxStageBlock && (nw == 1 || nw == 4)) g_cache[key] = Shape{sb, nw};
+  std::fclose(f);
+}
+
+void cache_store(const std::string& key, Shape s) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  cache_load_locked();
+  g_cache[key] = s;
+  if (const char* path = std::getenv("PSDF_TUNE_CACHE")) {
+    if (FILE* f = std::fopen(path, "a")) {
+      std::fprintf(f, "%s %d %d\n", key.c_str(), s.sb, s.nw);
+      std::fclose(f);
+    }
+  }
+}
+
+bool cache_find(const std::string& key, Shape* s) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  cache_load_locked();
+  auto it = g_cache.find(key);
+  if (it == g_cache.end()) return false;
+  *s = it->second;
+  return true;
+}
+
+constexpr int kGroupMF[] = {3, 4, 5, 6, 7, 8, 16};
+constexpr int kGroups = 7;
+int group_of(int m) { return m <= 8 ? m - 3 : 6; }
+
+hipError_t launch_batch(int mf, int mi_class, int nw, int grid, const BatchArgs& a, hipStream_t st) {
+  switch (mf) {
+    case 3: return launch_batch_mf<3>(mi_class, nw, grid, a, st);
+    case 4: return launch_batch_mf<4>(mi_class, nw, grid, a, st);
+    case 5: return launch_batch_mf<5>(mi_class, nw, grid, a, st);
+    case 6: return launch_batch_mf<6>(mi_class, nw, grid, a, st);
+    case 7: return launch_batch_mf<7>(mi_class, nw, grid, a, st);
+    case 8: return launch_batch_mf<8>(mi_class, nw, grid, a, st);
+    default: return launch_batch_mf<16>(mi_class, nw, grid, a, st);
+  }
+}
+
+int occupancy(int mf, int mi_class, int nw) {
+  int b = 0;
+  hipError_t err;
+  switch (mf) {
+    case 3: err = batch_occupancy_mf<3>(mi_class, nw, &b); break;
+    case 4: err = batch_occupancy_mf<4>(mi_class, nw, &b); break;
+    case 5: err = batch_occupancy_mf<5>(mi_class, nw, &b); break;
+    case 6: err = batch_occupancy_mf<6>(mi_class, nw, &b); break;
+    case 7: err = batch_occupancy_mf<7>(mi_class, nw, &b); break;
+    case 8: err = batch_occupancy_mf<8>(mi_class, nw, &b); break;
+    default: err = batch_occupancy_mf<16>(mi_class, nw, &b); break;
+  }
+  return (err == hipSuccess && b > 0) ? b : 1;
+}
+
+void free_graph(psdf_batch_plan* p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+  p->bound.clear();
+}
+
+// Build the instance table and the item list for a shape; upload both.
+int build_items(psdf_batch_plan* p, Shape sh) {
+  const int tile = 64 * sh.nw;
+  std::vector<BatchInst> inst(p->n_inst);
+  std::vector<BatchItem> items;
+  std::vector<double> cost;
+  size_t part = 0, blocks = 0;
+  for (int k = 0; k < p->n_inst; ++k) {
+    const psdf_batch_desc& d = p->desc[k];
+    BatchInst& b = inst[k];
+    b.pose_off = d.pose_off; b.N = d.N; b.edge_off = d.edge_off; b.E = d.E;
+    b.obst_off = d.obst_off; b.M = d.M; b.m = p->fp[k].m;
+    b.nt = (d.M + tile - 1) / tile;
+    b.part_off = (int)part;
+    b.blk_off = (int)blocks;
+    const int nb = (d.N + sh.sb - 1) / sh.sb;
+    part += (size_t)d.N * b.nt;
+    blocks += nb;
+    if (d.M == 0) continue;
+    const double per_edge = (double)d.E / std::max(1, d.M);
+    for (int bi = 0; bi < nb; ++bi) {
+      const int s0 = bi * sh.sb, ns = std::min(sh.sb, d.N - s0);
+      for (int t = 0; t < b.nt; ++t) {
+        const int o0 = t * tile, no = std::min(tile, d.M - o0);
+        items.push_back(BatchItem{k, s0, ns, o0, no, t});
+        cost.push_back((double)ns * no * per_edge);
+      }
+    }
+  }
+  // group by footprint size, longest processing time first within a group
+  std::vector<int> order(items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  auto grp = [&](int i) { return group_of(p->fp[items[i].inst].m); };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const int ga = grp(a), gb = grp(b);
+    return ga != gb ? ga < gb : cost[a] > cost[b];
+  });
+  std::vector<BatchItem> sorted(items.size());
+  for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
+
+  if (part > p->partial_cap || sorted.size() > p->items_cap || blocks > p->blockcnt_cap)
+    return set_error(PSDF_EINVAL, "internal: plan capacity exceeded");
+  hipError_t err = hipMemcpy(p->d_inst, inst.data(), inst.size() * sizeof(BatchInst),
+                             hipMemcpyHostToDevice);
+  if (err == hipSuccess && !sorted.empty())
+    err = hipMemcpy(p->d_items, sorted.data(), sorted.size() * sizeof(BatchItem),
+                    hipMemcpyHostToDevice);
+  if (err != hipSuccess) return hip_status(err);
+  p->shape = sh;
+  p->n_items = (int)sorted.size();
+  p->groups.clear();
+  for (size_t i = 0; i < order.size();) {
+    const int g = grp(order[i]);
+    size_t j = i;
+    while (j < order.size() && grp(order[j]) == g) ++j;
+    const int mf = kGroupMF[g];
+    const int per_cu = occupancy(mf, p->mi_class, sh.nw);
+    const int count = (int)(j - i);
+    p->groups.push_back({mf, (int)i, count, std::max(1, std::min(count, per_cu * p->cu))});
+    i = j;
+  }
+  free_graph(p);
+  return PSDF_OK;
+}
+
+BatchArgs make_args(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay,
+                    const float* bx, const float* by, const int32_t* off, float* d, int32_t* edge,
+                    int32_t* obst, float* grad, uint64_t* keys) {
+  BatchArgs a;
+  a.fps = p->d_fp; a.insts = p->d_inst; a.items = p->d_items; a.n_items = p->n_items;
+  a.sb = p->shape.sb;
+  a.poses = poses; a.ax = ax; a.ay = ay; a.bx = bx; a.by = by; a.off = off;
+  a.partial = p->d_partial; a.aux = p->d_partial + p->partial_cap;
+  a.blockcnt = p->d_blockcnt; a.ctrl = p->d_ctrl;   // per-group slices set by enqueue
+  a.d = d; a.edge = edge; a.obst = obst; a.grad = grad; a.keys = keys;
+  return a;
+}
+
+int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay,
+        const float* bx, const float* by, const int32_t* off, float* d, int32_t* edge,
+        int32_t* obst, float* grad, uint64_t* keys, hipStream_t stream, bool use_graph) {
+  if (p->total_stages == 0 || p->n_items == 0) {
+    if (p->total_stages == 0) return PSDF_OK;
+  }
+  const BatchArgs a = make_args(p, poses, ax, ay, bx, by, off, d, edge, obst, grad, keys);
+  if (p->n_items == 0) return set_error(PSDF_EINVAL, "batch has stages but no obstacles; "
+                                                      "use psdf_grad for empty edge sets");
+  auto enqueue = [&](hipStream_t st) -> hipError_t {
+    for (const auto& g : p->groups) {
+      BatchArgs ga = a;
+      ga.items = a.items + g.start;
+      ga.n_items = g.count;
+      ga.ctrl = a.ctrl + 2 * group_of(g.mf);
+      hipError_t err = launch_batch(g.mf, p->mi_class, p->shape.nw, g.grid, ga, st);
+      if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+  };
+  if (!use_graph) {
+    timer_begin(stream);
+    hipError_t err = enqueue(stream);
+    timer_end(stream);
+    return hip_status(err);
+  }
+  const std::vector<const void*> ptrs = {poses, ax, ay, bx, by, off, d, edge, obst, grad, keys};
+  if (!p->exec || p->bound != ptrs) {
+    free_graph(p);
+    hipError_t err = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (err != hipSuccess) return hip_status(err);
+    err = enqueue(p->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t err2 = hipStreamEndCapture(p->cap_stream, &g);
+    if (err != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_status(err); }
+    if (err2 != hipSuccess) return hip_status(err2);
+    p->graph = g;
+    err = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    if (err != hipSuccess) { free_graph(p); return hip_status(err); }
+    p->bound = ptrs;
+  }
+  timer_begin(stream);
+  hipError_t err = hipGraphLaunch(p->exec, stream);
+  timer_end(stream);
+  return hip_status(err);
+}
+
+// One wave per stage: the winner adjoint of keys[s] (local obstacle index)
+// and the outputs, for batches whose keys come from the screened path.
+__global__ __launch_bounds__(256) void batch_epilogue_kernel(
+    const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
+    const int* __restrict__ stage_inst, int S, const float* __restrict__ poses,
+    const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ bx,
+    const float* __restrict__ by, const int* __restrict__ off, const uint64_t* __restrict__ keys,
+    float* __restrict__ d, int* __restrict__ edge, int* __restrict__ obst,
+    float* __restrict__ grad) {
+  __shared__ FpLds fl[4];
+  __shared__ WinnerLds wl[4];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + w;
+  if (s >= S) return;
+  const int inst = __builtin_amdgcn_readfirstlane(stage_inst[s]);
+  const BatchInst in = insts[inst];
+  const FpConst& F = fps[inst];
+  stage_footprint(fl[w], F);
+  const uint64_t key = keys[s];
+  const float* p = poses + 3 * s;
+  const float px = p[0], py = p[1];
+  float sn, cs;
+  sincosf(p[2], &sn, &cs);
+  const int i = (int)(key & 0xffffffffu);
+  bool valid = key != kEmptyKey && (key >> 32) != 0 && (uint64_t)i < (uint64_t)in.M;
+  int e0 = 0, mi = 0;
+  if (valid) {
+    e0 = off[in.obst_off + i];
+    mi = off[in.obst_off + i + 1] - e0;
+    e0 += in.edge_off;
+    valid = mi >= 1 && mi <= kMaxObst && e0 >= in.edge_off && e0 <= in.edge_off + in.E - mi;
+  }
+  wave_sync();
+  float dv = __builtin_huge_valf(), g[3] = {0.f, 0.f, 0.f};
+  int ev = -1, ov = -1;
+  if (key != kEmptyKey && !valid) {
+    dv = __builtin_nanf("");
+    g[0] = g[1] = g[2] = dv;
+  } else if (valid) {
+    int jstar = 0;
+    winner_adjoint(F, fl[w], wl[w], ax, ay, bx, by, e0, mi, cs, sn, px, py, true, jstar, g);
+    dv = from_orderable((uint32_t)(key >> 32));
+    ov = i;
+    ev = e0 - in.edge_off + jstar;
+  }
+  if (lane == 0) {
+    d[s] = dv;
+    edge[s] = ev;
+    obst[s] = ov;
+    grad[3 * s + 0] = g[0];
+    grad[3 * s + 1] = g[1];
+    grad[3 * s + 2] = g[2];
+  }
+}
+
+hipError_t launch_screen(int mf, int mi_class, int grid, const ScreenArgs& a, hipStream_t st) {
+  switch (mf) {
+    case 3: return launch_screen_mf<3>(mi_class, grid, a, st);
+    case 4: return launch_screen_mf<4>(mi_class, grid, a, st);
+    case 5: return launch_screen_mf<5>(mi_class, grid, a, st);
+    case 6: return launch_screen_mf<6>(mi_class, grid, a, st);
+    case 7: return launch_screen_mf<7>(mi_class, grid, a, st);
+    case 8: return launch_screen_mf<8>(mi_class, grid, a, st);
+    default: return launch_screen_mf<16>(mi_class, grid, a, st);
+  }
+}
+
+hipError_t launch_fallback(int mf, int mi_class, int grid, int tiles, const ScreenArgs& a,
+                           hipStream_t st) {
+  switch (mf) {
+    case 3: return launch_fallback_mf<3>(mi_class, grid, tiles, a, st);
+    case 4: return launch_fallback_mf<4>(mi_class, grid, tiles, a, st);
+    case 5: return launch_fallback_mf<5>(mi_class, grid, tiles, a, st);
+    case 6: return launch_fallback_mf<6>(mi_class, grid, tiles, a, st);
+    case 7: return launch_fallback_mf<7>(mi_class, grid, tiles, a, st);
+    case 8: return launch_fallback_mf<8>(mi_class, grid, tiles, a, st);
+    default: return launch_fallback_mf<16>(mi_class, grid, tiles, a, st);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_labels(const FpConst* fps, const BatchInst* insts, const int* stage_inst,
+                         const float* poses, const float* ax, const float* ay, const float* bx,
+                         const float* by, const int* stage, const int* edge, int n, int S, float* X,
+                         float* T, hipStream_t st);
+
+}  // namespace psdf
+
+extern "C" {
+
+int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, int32_t topk,
+                        const float* poses, const float* ax, const float* ay, const float* bx,
+                        const float* by, const int32_t* off, float* d, int32_t* edge,
+                        int32_t* obst, float* grad, uint64_t* keys, int32_t* stage_cand,
+                        int32_t* stage_cert, uint64_t* cand_keys, hipStream_t stream) {
+  clear_error();
+  if (!p) return set_error(PSDF_EINVAL, "plan is NULL");
+  if (pool < 1 || pool > kPoolCap || topk < 1)
+    return set_error(PSDF_EINVAL, "pool = %d (1..%d), topk = %d (>= 1)", pool, kPoolCap, topk);
+  if (p->max_M > kScreenMaxM)
+    return set_error(PSDF_ETOOBIG, "an instance has %d obstacles; screening supports %d", p->max_M,
+                     kScreenMaxM);
+  if (p->total_stages == 0) return PSDF_OK;
+  if (!poses || !off || !d || !edge || !obst || !grad || !keys)
+    return set_error(PSDF_EINVAL, "a pose, offset or output pointer is NULL");
+  if (p->max_M > 0 && (!ax || !ay || !bx || !by)) return set_error(PSDF_EINVAL, "an edge array is NULL");
+  ScreenArgs a;
+  a.fps = p->d_fp; a.insts = p->d_inst; a.stage_inst = p->d_stage_inst;
+  a.poses = poses; a.ax = ax; a.ay = ay; a.bx = bx; a.by = by; a.off = off;
+  a.theta = theta; a.pool = pool; a.topk = topk; a.keys = keys;
+  a.stage_cand = stage_cand; a.stage_cert = stage_cert; a.cand_keys = cand_keys;
+  timer_begin(stream);
+  hipError_t err = hipSuccess;
+  for (const auto& g : p->sgroups) {
+    ScreenArgs ga = a;
+    ga.stages = p->d_stage_list + g.start;
+    ga.n_stages = g.count;
+    ga.failed = p->d_failed + g.start;
+    ga.ctrl = p->d_sctrl + 3 * group_of(g.mf);
+    err = launch_screen(g.mf, p->mi_class, g.count, ga, stream);
+    if (err != hipSuccess) break;
+    const int grid = std::max(1, std::min(g.count * g.max_tiles, 4 * p->cu));
+    err = launch_fallback(g.mf, p->mi_class, grid, g.max_tiles, ga, stream);
+    if (err != hipSuccess) break;
+  }
+  timer_end(stream);
+  if (err == hipSuccess) {
+    batch_epilogue_kernel<<<(p->total_stages + 3) / 4, 256, 0, stream>>>(
+        p->d_fp, p->d_inst, p->d_stage_inst, p->total_stages, poses, ax, ay, bx, by, off, keys, d,
+        edge, obst, grad);
+    err = hipGetLastError();
+  }
+  return hip_status(err);
+}
+
+int psdf_screen_labels(const psdf_batch_plan* p, const float* poses, const float* ax,
+                       const float* ay, const float* bx, const float* by, const int32_t* stage,
+                       const int32_t* edge, int32_t n, float* X, float* T, hipStream_t stream) {
+  clear_error();
+  if (!p) return set_error(PSDF_EINVAL, "plan is NULL");
+  if (n < 0) return set_error(PSDF_EINVAL, "n = %d", n);
+  if (n == 0) return PSDF_OK;
+  if (!poses || !ax || !ay || !bx || !by || !stage || !edge || !X || !T)
+    return set_error(PSDF_EINVAL, "NULL argument");
+  return hip_status(launch_labels(p->d_fp, p->d_inst, p->d_stage_inst, poses, ax, ay, bx, by,
+                                  stage, edge, n, p->total_stages, X, T, stream));
+}
+
+
+void psdf_batch_plan_destroy(psdf_batch_plan* p) {
+  if (!p) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  free_graph(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  (void)hipFree(p->d_fp);
+  (void)hipFree(p->d_inst);
+  (void)hipFree(p->d_items);
+  (void)hipFree(p->d_partial);
+  (void)hipFree(p->d_blockcnt);
+  (void)hipFree(p->d_ctrl);
+  (void)hipFree(p->d_stage_inst);
+  (void)hipFree(p->d_stage_list);
+  (void)hipFree(p->d_failed);
+  (void)hipFree(p->d_sctrl);
+  (void)hipSetDevice(cur);
+  delete p;
+}
+
+int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, int32_t n_inst,
+                           const float* footprints, int32_t mbar, const psdf_params* params,
+                           int32_t flags) {
+  clear_error();
+  if (!out) return set_error(PSDF_EINVAL, "plan is NULL");
+  *out = nullptr;
+  if (n_inst < 0 || (n_inst > 0 && (!desc || !footprints)))
+    return set_error(PSDF_EINVAL, "n_inst = %d with a NULL descriptor or footprint array", n_inst);
+  if (mbar < 1 || mbar > kMaxObst) return set_error(PSDF_ETOOBIG, "mbar = %d, 1..%d allowed", mbar, kMaxObst);
+  psdf_batch_plan* p = new psdf_batch_plan();
+  p->n_inst = n_inst;
+  p->mi_class = obst_class(mbar);
+  p->flags = flags;
+  p->desc.assign(desc, desc + n_inst);
+  p->fp.resize(n_inst);
+  size_t part_max = 0, blocks_max = 0, items_max = 0;
+  long stages = 0;
+  for (int k = 0; k < n_inst; ++k) {
+    const psdf_batch_desc& d = desc[k];
+    if (d.N < 0 || d.E < 0 || d.M < 0 || d.pose_off < 0 || d.edge_off < 0 || d.obst_off < 0 ||
+        d.fp_off < 0) {
+      delete p;
+      return set_error(PSDF_EINVAL, "instance %d: negative size or offset", k);
+    }
+    int rc = prepare_footprint(footprints + 2 * (size_t)d.fp_off, d.m, params, &p->fp[k]);
+    if (rc) {
+      std::string msg = last_error();
+      delete p;
+      return set_error(rc, "instance %d: %s", k, msg.c_str());
+    }
+    stages += d.N;
+    const size_t nt64 = (size_t)(d.M + 63) / 64;
+    part_max += (size_t)d.N * nt64;
+    blocks_max += (size_t)d.N;
+    items_max += (size_t)d.N * nt64;
+  }
+  if (stages > 0x7fffffffL) { delete p; return set_error(PSDF_ETOOBIG, "too many stages"); }
+  p->total_stages = (int)stages;
+  hipError_t err = hipGetDevice(&p->device);
+  int cu = 0;
+  if (err == hipSuccess) err = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, p->device);
+  p->cu = cu > 0 ? cu : 256;
+  p->partial_cap = std::max<size_t>(1, part_max);
+  p->items_cap = std::max<size_t>(1, items_max);
+  p->blockcnt_cap = std::max<size_t>(1, blocks_max);
+  if (err == hipSuccess) err = hipMalloc(&p->d_fp, std::max(1, n_inst) * sizeof(FpConst));
+  if (err == hipSuccess) err = hipMalloc(&p->d_inst, std::max(1, n_inst) * sizeof(BatchInst));
+  if (err == hipSuccess) err = hipMalloc(&p->d_items, p->items_cap * sizeof(BatchItem));
+  if (err == hipSuccess) err = hipMalloc(&p->d_partial, 2 * p->partial_cap * sizeof(uint64_t));
+  if (err == hipSuccess) err = hipMalloc(&p->d_blockcnt, p->blockcnt_cap * sizeof(unsigned));
+  if (err == hipSuccess) err = hipMalloc(&p->d_ctrl, 2 * kGroups * sizeof(unsigned));
+  if (err == hipSuccess) err = hipMemset(p->d_blockcnt, 0, p->blockcnt_cap * sizeof(unsigned));
+  if (err == hipSuccess) err = hipMemset(p->d_ctrl, 0, 2 * kGroups * sizeof(unsigned));
+  if (err == hipSuccess && n_inst > 0)
+    err = hipMemcpy(p->d_fp, p->fp.data(), n_inst * sizeof(FpConst), hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+  // screening tables
+  if (err == hipSuccess) {
+    const int S = std::max(1, p->total_stages);
+    std::vector<int> stage_inst(S, 0), list;
+    list.reserve(S);
+    for (int k = 0; k < n_inst; ++k) {
+      for (int t = 0; t < desc[k].N; ++t) stage_inst[desc[k].pose_off + t] = k;
+      p->max_M = std::max(p->max_M, desc[k].M);
+    }
+    for (int g = 0; g < kGroups; ++g) {
+      const int start = (int)list.size();
+      int max_tiles = 1;
+      for (int k = 0; k < n_inst; ++k)
+        if (group_of(p->fp[k].m) == g) {
+          for (int t = 0; t < desc[k].N; ++t) list.push_back(desc[k].pose_off + t);
+          max_tiles = std::max(max_tiles, (desc[k].M + 255) / 256);
+        }
+      if ((int)list.size() > start)
+        p->sgroups.push_back({kGroupMF[g], start, (int)list.size() - start, max_tiles});
+    }
+    err = hipMalloc(&p->d_stage_inst, S * sizeof(int));
+    if (err == hipSuccess) err = hipMalloc(&p->d_stage_list, S * sizeof(int));
+    if (err == hipSuccess) err = hipMalloc(&p->d_failed, S * sizeof(int));
+    if (err == hipSuccess) err = hipMalloc(&p->d_sctrl, 3 * kGroups * sizeof(unsigned));
+    if (err == hipSuccess) err = hipMemset(p->d_sctrl, 0, 3 * kGroups * sizeof(unsigned));
+    if (err == hipSuccess)
+      err = hipMemcpy(p->d_stage_inst, stage_inst.data(), S * sizeof(int), hipMemcpyHostToDevice);
+    if (err == hipSuccess && !list.empty())
+      err = hipMemcpy(p->d_stage_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice);
+  }
+  if (err != hipSuccess) {
+    int rc = hip_status(err);
+    psdf_batch_plan_destroy(p);
+    return rc;
+  }
+  Shape sh{1, 4};
+  if (!cache_find(signature(*p), &sh)) {
+    // heuristic: enough items to spread over the chip, stage blocks as long
+    // as that allows
+    double pairs = 0.0;
+    for (const auto& d : p->desc) pairs += (double)d.N * d.M;
+    sh.sb = 1;
+    while (sh.sb < 16 && pairs / (sh.sb * 2 * 256.0) > 8.0 * p->cu) sh.sb *= 2;
+  }
+  int rc = build_items(p, sh);
+  if (rc) { psdf_batch_plan_destroy(p); return rc; }
+  *out = p;
+  return PSDF_OK;
+}
+
+int psdf_batch(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay,
+               const float* bx, const float* by, const int32_t* off, float* d, int32_t* edge,
+               int32_t* obst, float* grad, uint64_t* keys, hipStream_t stream) {
+  clear_error();
+  if (!p) return set_error(PSDF_EINVAL, "plan is NULL");
+  if (p->total_stages > 0 && (!poses || !off || !d || !edge || !obst || !grad || !keys))
+    return set_error(PSDF_EINVAL, "a pose, offset or output pointer is NULL");
+  if (p->n_items > 0 && (!ax || !ay || !bx || !by)) return set_error(PSDF_EINVAL, "an edge array is NULL");
+  return run(p, poses, ax, ay, bx, by, off, d, edge, obst, grad, keys, stream,
+             (p->flags & PSDF_BATCH_GRAPH) != 0);
+}
+
+int psdf_batch_autotune(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay,
+                        const float* bx, const float* by, const int32_t* off, float* d,
+                        int32_t* edge, int32_t* obst, float* grad, uint64_t* keys,
+                        hipStream_t stream, float* best_ms) {
+  clear_error();
+  if (!p) return set_error(PSDF_EINVAL, "plan is NULL");
+  if (!(p->flags & PSDF_BATCH_AUTOTUNE)) return set_error(PSDF_EINVAL, "plan built without PSDF_BATCH_AUTOTUNE");
+  if (p->n_items == 0) return PSDF_OK;
+  hipEvent_t e0, e1;
+  hipError_t err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  if (err != hipSuccess) return hip_status(err);
+  const int sbs[] = {1, 2, 4, 8, 16};
+  const int nws[] = {1, 4};
+  float best = INFINITY;
+  Shape best_sh = p->shape;
+  int rc = PSDF_OK;
+  for (int nw : nws) {
+    for (int sb : sbs) {
+      rc = build_items(p, Shape{sb, nw});
+      if (rc) break;
+      float t_min = INFINITY;
+      for (int rep = 0; rep < 4 && rc == PSDF_OK; ++rep) {
+        err = hipEventRecord(e0, stream);
+        if (err == hipSuccess) {
+          rc = run(p, poses, ax, ay, bx, by, off, d, edge, obst, grad, keys, stream, false);
+          if (rc) break;
+        }
+        if (err == hipSuccess) err = hipEventRecord(e1, stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err != hipSuccess) { rc = hip_status(err); break; }
+        if (rep > 0) t_min = std::min(t_min, ms);   // first run warms up
+      }
+      if (rc) break;
+      if (t_min < best) { best = t_min; best_sh = Shape{sb, nw}; }
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  rc = build_items(p, best_sh);
+  if (rc) return rc;
+  cache_store(signature(*p), best_sh);
+  rc = run(p, poses, ax, ay, bx, by, off, d, edge, obst, grad, keys, stream, false);
+  if (best_ms) *best_ms = best;
+  return rc;
+}
+
+int psdf_batch_plan_info(const psdf_batch_plan* p, int32_t* stages_per_item,
+                         int32_t* obstacles_per_tile, int32_t* n_items, int32_t* grid) {
+  clear_error();
+  if (!p) return set_error(PSDF_EINVAL, "plan is NULL");
+  if (stages_per_item) *stages_per_item = p->shape.sb;
+  if (obstacles_per_tile) *obstacles_per_tile = 64 * p->shape.nw;
+  if (n_items) *n_items = p->n_items;
+  if (grid) {
+    int g = 0;
+    for (const auto& gr : p->groups) g = std::max(g, gr.grid);
+    *grid = g;
+  }
+  return PSDF_OK;
+}
+
+}  // extern "C"

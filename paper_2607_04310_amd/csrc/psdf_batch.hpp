@@ -1,0 +1,235 @@
+// Persistent kernel of psdf_batch.
+//
+// Work items (instance, stage block, obstacle tile) are grouped by footprint
+// size; one persistent launch per group pulls its items from a device
+// counter, largest first.  For an item, lane <-> obstacle of the tile (edges
+// in registers), the work-group loops over the stage block exactly as the
+// plain per-stage minimum kernel does and writes one partial key and aux word
+// per stage.  The work-group that completes the last tile of a stage block
+// (an agent-scope acq_rel counter per block) then runs the winner adjoint of
+// those stages (one wave per stage) and writes the outputs.  The last
+// work-group to leave resets the item counter, and every block counter is
+// reset by the work-group that consumed it, so consecutive launches (and
+// graph replays) start from zero.  No work-group ever waits for another.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "psdf_device.hpp"
+#include "psdf_host.hpp"
+#include "psdf_winner.hpp"
+
+namespace psdf {
+
+struct BatchInst {
+  int pose_off, N, edge_off, E, obst_off, M;
+  int part_off;   // first partial slot: partial[part_off + s * nt + tile]
+  int nt;         // obstacle tiles
+  int blk_off;    // first stage-block counter
+  int m;          // footprint vertices
+};
+
+struct BatchItem {
+  int inst, s0, ns, o0, no, tile;
+};
+
+struct BatchArgs {
+  const FpConst* fps;
+  const BatchInst* insts;
+  const BatchItem* items;   // this launch's items (one footprint-size group)
+  int n_items;
+  int sb;
+  const float* poses;
+  const float* ax;
+  const float* ay;
+  const float* bx;
+  const float* by;
+  const int* off;
+  uint64_t* partial;
+  uint64_t* aux;
+  unsigned* blockcnt;
+  unsigned* ctrl;   // this launch's [0] next item, [1] work-groups done
+  float* d;
+  int* edge;
+  int* obst;
+  float* grad;
+  uint64_t* keys;
+};
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// One launch per footprint-size group: MF footprint slots, MI obstacle edge
+// class, NW waves per work-group (64 NW obstacles per tile).
+template <int MF, int MI, int NW>
+__global__ __launch_bounds__(64 * NW) void batch_kernel(BatchArgs A) {
+  __shared__ int s_item, s_last;
+  __shared__ float4 st[kMaxStageBlock];
+  __shared__ uint64_t wk[NW][kMaxStageBlock];
+  __shared__ uint64_t wa[NW][kMaxStageBlock];
+  __shared__ FpLds fl[NW];
+  __shared__ WinnerLds wl[NW];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(&A.ctrl[0], 1u);
+    __syncthreads();
+    const int it = uniform(s_item);
+    if (it >= A.n_items) break;
+    const BatchItem item = A.items[it];
+    const int inst = uniform(item.inst), s0 = uniform(item.s0), ns = uniform(item.ns);
+    const int o0 = uniform(item.o0), no = uniform(item.no), tile = uniform(item.tile);
+    const BatchInst in = A.insts[inst];
+    const FpConst& F = A.fps[inst];
+
+    // obstacle of this lane (indices local to the instance; edges global)
+    const int ol = w * 64 + lane;
+    const bool active = ol < no;
+    int e0 = 0, mi = 0;
+    if (active) {
+      const int* off = A.off + in.obst_off;
+      e0 = off[o0 + ol];
+      mi = off[o0 + ol + 1] - e0;
+      e0 += in.edge_off;
+    }
+    const bool local_bad = active && e0 < in.edge_off;   // negative local offset
+    for (int t = threadIdx.x; t < ns; t += 64 * NW) {
+      const float* p = A.poses + 3 * (in.pose_off + s0 + t);
+      float sn, cs;
+      sincosf(p[2], &sn, &cs);
+      st[t] = make_float4(cs, sn, p[0], p[1]);
+    }
+    __syncthreads();
+
+    if (w * 64 < no) {
+      auto emit = [&](int t, uint64_t key, uint64_t a) {
+        if (lane == 0) { wk[w][t] = key; wa[w][t] = a; }
+      };
+      wave_stages<MF, MI>(F, A.ax, A.ay, A.bx, A.by, e0, mi, in.edge_off + in.E, active, local_bad,
+                          o0 + w * 64, ns, st, emit);
+    } else if (lane == 0) {
+      for (int t = 0; t < ns; ++t) { wk[w][t] = kEmptyKey; wa[w][t] = 0; }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ns; t += 64 * NW) {
+      uint64_t k = wk[0][t], a = wa[0][t];
+#pragma unroll
+      for (int v = 1; v < NW; ++v)
+        if (wk[v][t] < k) { k = wk[v][t]; a = wa[v][t]; }
+      const size_t slot = (size_t)in.part_off + (size_t)(s0 + t) * in.nt + tile;
+      A.partial[slot] = k;
+      A.aux[slot] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned* cnt = &A.blockcnt[in.blk_off + s0 / A.sb];
+      const unsigned done =
+          __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+      s_last = done == (unsigned)in.nt;
+      if (s_last) __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (s_last) {
+      // every tile of this stage block has written its partials: run the
+      // winner adjoint of its stages, one wave per stage
+      stage_footprint(fl[w], F);
+      for (int t = w; t < ns; t += NW) {
+        const int s = s0 + t, g = in.pose_off + s;
+        const float* p = A.poses + 3 * g;
+        const float px = p[0], py = p[1];
+        float sn, cs;
+        sincosf(p[2], &sn, &cs);
+        uint64_t key = kEmptyKey, a = 0;
+        const size_t row = (size_t)in.part_off + (size_t)s * in.nt;
+        for (int j = lane; j < in.nt; j += 64) {
+          const uint64_t k = __hip_atomic_load(&A.partial[row + j], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+          if (k < key) {
+            key = k;
+            a = __hip_atomic_load(&A.aux[row + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+        const uint64_t kmin = wave_min_u64(key);
+        const int first = __ffsll((unsigned long long)__ballot(key == kmin)) - 1;
+        a = __shfl((unsigned long long)a, first);
+        key = kmin;
+        wave_sync();
+        const int ge0 = (int)(uint32_t)(a >> 32), gmi = (int)(uint32_t)(a & 0xffffffffu);
+        const bool valid = key != kEmptyKey && (key >> 32) != 0 && gmi >= 1 && gmi <= kMaxObst;
+        float dv = __builtin_huge_valf(), gv[3] = {0.f, 0.f, 0.f};
+        int ev = -1, ov = -1;
+        if (key != kEmptyKey && !valid) {
+          dv = __builtin_nanf("");
+          gv[0] = gv[1] = gv[2] = dv;
+        } else if (valid) {
+          int jstar = 0;
+          winner_adjoint(F, fl[w], wl[w], A.ax, A.ay, A.bx, A.by, ge0, gmi, cs, sn, px, py, true,
+                         jstar, gv);
+          dv = from_orderable((uint32_t)(key >> 32));
+          ov = (int)(key & 0xffffffffu);
+          ev = ge0 - in.edge_off + jstar;
+        }
+        if (lane == 0) {
+          A.keys[g] = key;
+          A.d[g] = dv;
+          A.edge[g] = ev;
+          A.obst[g] = ov;
+          A.grad[3 * g + 0] = gv[0];
+          A.grad[3 * g + 1] = gv[1];
+          A.grad[3 * g + 2] = gv[2];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // the last work-group out resets the item counter for the next launch
+  if (threadIdx.x == 0) {
+    const unsigned done =
+        __hip_atomic_fetch_add(&A.ctrl[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (done == gridDim.x) {
+      __hip_atomic_store(&A.ctrl[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&A.ctrl[1], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+template <int MF, int MI>
+hipError_t launch_batch_t(int nw, int grid, const BatchArgs& a, hipStream_t st) {
+  if (nw == 1) batch_kernel<MF, MI, 1><<<grid, 64, 0, st>>>(a);
+  else batch_kernel<MF, MI, 4><<<grid, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+template <int MF, int MI>
+hipError_t batch_occupancy_t(int nw, int* blocks_per_cu) {
+  if (nw == 1)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel<MF, MI, 1>, 64, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel<MF, MI, 4>, 256, 0);
+}
+
+// Per footprint-size entry points (instantiated in psdf_batch_mf*.hip).
+template <int MF>
+hipError_t launch_batch_mf(int mi_class, int nw, int grid, const BatchArgs& a, hipStream_t st) {
+  if (mi_class == 4) return launch_batch_t<MF, 4>(nw, grid, a, st);
+  if (mi_class == 8) return launch_batch_t<MF, 8>(nw, grid, a, st);
+  return launch_batch_t<MF, 16>(nw, grid, a, st);
+}
+
+template <int MF>
+hipError_t batch_occupancy_mf(int mi_class, int nw, int* blocks_per_cu) {
+  if (mi_class == 4) return batch_occupancy_t<MF, 4>(nw, blocks_per_cu);
+  if (mi_class == 8) return batch_occupancy_t<MF, 8>(nw, blocks_per_cu);
+  return batch_occupancy_t<MF, 16>(nw, blocks_per_cu);
+}
+
+#define PSDF_EXTERN_BATCH(MF)                                                                  \
+  extern template hipError_t launch_batch_mf<MF>(int, int, int, const BatchArgs&, hipStream_t); \
+  extern template hipError_t batch_occupancy_mf<MF>(int, int, int*);
+PSDF_EXTERN_BATCH(3)
+PSDF_EXTERN_BATCH(4)
+PSDF_EXTERN_BATCH(5)
+PSDF_EXTERN_BATCH(6)
+PSDF_EXTERN_BATCH(7)
+PSDF_EXTERN_BATCH(8)
+PSDF_EXTERN_BATCH(16)
+
+}  // namespace psdf

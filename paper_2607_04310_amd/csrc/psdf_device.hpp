@@ -43,6 +43,12 @@ struct FpConst {
   float einv[kMaxFp];            // 1 / (|e_l|^2 + eps)
   float nx[kMaxFp], ny[kMaxFp];  // outward unit normals n_l
   float pa[kMaxFp], pb[kMaxFp];  // robot interval [alpha_P(n_l), beta_P(n_l)]
+  // Screening certificate constants: rmax bounds |v_l| (every footprint
+  // point is within rmax of the pose origin); tau_sep is the distance above
+  // which two convex sets are declared separated by the axis test whatever
+  // the rounding (eps_sat / kappa + margin, kappa = cos of half the largest
+  // exterior angle of the footprint).
+  float rmax, tau_sep;
 };
 
 // One obstacle in registers.  Slots j >= mi repeat edge mi - 1, which leaves
@@ -73,6 +79,29 @@ __device__ __forceinline__ float from_orderable(uint32_t k) {
   return __uint_as_float(u);
 }
 
+// Rotation-invariant constants of an edge with world vector (dx, dy):
+// iv2 = 1 / (|v|^2 + eps) and il = 1 / (|v| + eps) (hardware reciprocal and
+// square root, about 1 ulp).  Every kernel derives them through this
+// function, so they agree bit for bit.
+__device__ __forceinline__ void edge_consts(float dx, float dy, float eps, float& iv2, float& il) {
+  const float l2 = fmaf(dx, dx, dy * dy);
+  iv2 = __builtin_amdgcn_rcpf(l2 + eps);
+  il = __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(l2) + eps);
+}
+
+// Local frame of a world point / vector: R(theta)^T (P - p) and R^T w.
+__device__ __forceinline__ void local_point(float x, float y, float c, float s, float px, float py,
+                                            float& lx, float& ly) {
+  const float dx = x - px, dy = y - py;
+  lx = fmaf(c, dx, s * dy);
+  ly = fmaf(c, dy, -(s * dx));
+}
+__device__ __forceinline__ void local_vector(float wx, float wy, float c, float s, float& lx,
+                                             float& ly) {
+  lx = fmaf(c, wx, s * wy);
+  ly = fmaf(c, wy, -(s * wx));
+}
+
 template <int MI>
 __device__ __forceinline__ void load_obstacle(Obst<MI>& o, const float* __restrict__ ax,
                                               const float* __restrict__ ay,
@@ -97,9 +126,7 @@ __device__ __forceinline__ void load_obstacle(Obst<MI>& o, const float* __restri
     bxs[j] = b0; bys[j] = b1;
     const float dx = b0 - a0, dy = b1 - a1;
     o.wx[j] = dx; o.wy[j] = dy;
-    const float l2 = fmaf(dx, dx, dy * dy);
-    o.iv2[j] = 1.0f / (l2 + eps);
-    o.il[j] = 1.0f / (sqrtf(l2) + eps);
+    edge_consts(dx, dy, eps, o.iv2[j], o.il[j]);
   }
   bool finite = true;
 #pragma unroll
@@ -141,11 +168,8 @@ __device__ __forceinline__ void to_local(const Obst<MI>& o, float c, float s, fl
                                          Local<MI>& L) {
 #pragma unroll
   for (int j = 0; j < MI; ++j) {
-    const float dx = o.ax[j] - px, dy = o.ay[j] - py;
-    L.tax[j] = fmaf(c, dx, s * dy);
-    L.tay[j] = fmaf(c, dy, -(s * dx));
-    L.vx[j] = fmaf(c, o.wx[j], s * o.wy[j]);
-    L.vy[j] = fmaf(c, o.wy[j], -(s * o.wx[j]));
+    local_point(o.ax[j], o.ay[j], c, s, px, py, L.tax[j], L.tay[j]);
+    local_vector(o.wx[j], o.wy[j], c, s, L.vx[j], L.vy[j]);
     L.nx[j] = -L.vy[j] * o.il[j];
     L.ny[j] = L.vx[j] * o.il[j];
   }
@@ -236,207 +260,6 @@ __device__ __forceinline__ float obstacle_sd(const FpConst& F, const Obst<MI>& o
     }
     sd = -depth;
   }
-  if (o.bad) sd = __builtin_nanf("");
-  return sd;
-}
-
-// Reverse-mode adjoint of obstacle_sd with respect to the pose, through the
-// active branch of every min / max (first index on ties), plus the reported
-// edge: the smallest per-edge pool distance (lowest index on ties).
-// Returns sd; writes gscale * dsd/d(x, y, theta) to g[0..2].
-//
-// The adjoint is contracted on the fly: a local point P~ with adjoint gP
-// contributes -R gP to d/dp and gP . (P~_y, -P~_x) to d/dtheta (P~ moves by
-// -R^T dp + dtheta (P~_y, -P~_x)); a local edge vector v with adjoint gv
-// contributes gv . (v_y, -v_x) to d/dtheta.  The winning pool entry and the
-// extreme vertices of each active axis are carried as coordinates, so no
-// register array is indexed at run time.
-template <int MF, int MI>
-__device__ float obstacle_adjoint(const FpConst& F, const Obst<MI>& o, float c, float s, float px,
-                                  float py, float gscale, int& jstar, float g[3]) {
-  constexpr int NV = 2 * MI;        // V_obs slots: A~_k (k < MI), then B~_k (open obstacles)
-  constexpr int KA = MF + MI;       // axis slots: robot normals, then obstacle normals
-  Local<MI> L;
-  to_local(o, c, s, px, py, L);
-  auto vx_of = [&](int k) { return k < MI ? L.tax[k] : L.tax[k - MI] + L.vx[k - MI]; };
-  auto vy_of = [&](int k) { return k < MI ? L.tay[k] : L.tay[k - MI] + L.vy[k - MI]; };
-  auto live_q = [&](int q) { return q < MF ? (q < F.m) : (q - MF < o.mi); };
-
-  float sx = 0.f, sy = 0.f, gth = 0.f;
-  auto add_point = [&](float x, float y, float gx, float gy) {
-    sx += gx; sy += gy; gth += gx * y - gy * x;
-  };
-  auto add_vector = [&](float vx, float vy, float gx, float gy) { gth += gx * vy - gy * vx; };
-
-  // ---- pools (Sec. IV-B), carrying the winning entry
-  float best = __builtin_huge_valf();
-  int btype = 0;                            // 0: robot vertex -> obstacle edge; 1: V_obs point -> robot edge
-  float bPx = 0.f, bPy = 0.f;               // the point
-  float bAx = 0.f, bAy = 0.f, bVx = 0.f, bVy = 0.f, bIv = 0.f;   // the segment [A, A + V]
-  float epool[MI], dA[MI];
-#pragma unroll
-  for (int j = 0; j < MI; ++j) { epool[j] = __builtin_huge_valf(); dA[j] = __builtin_huge_valf(); }
-#pragma unroll
-  for (int l = 0; l < MF; ++l) {
-#pragma unroll
-    for (int j = 0; j < MI; ++j) {
-      const float d2 = seg_d2(F.vx[l], F.vy[l], L.tax[j], L.tay[j], L.vx[j], L.vy[j], o.iv2[j]);
-      epool[j] = fminf(epool[j], d2);
-      if (d2 < best) {
-        best = d2; btype = 0; bPx = F.vx[l]; bPy = F.vy[l];
-        bAx = L.tax[j]; bAy = L.tay[j]; bVx = L.vx[j]; bVy = L.vy[j]; bIv = o.iv2[j];
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    if (k >= MI && o.closed) break;
-    const float wx = vx_of(k), wy = vy_of(k);
-    float dk = __builtin_huge_valf();
-#pragma unroll
-    for (int l = 0; l < MF; ++l) {
-      const float d2 = seg_d2(wx, wy, F.vx[l], F.vy[l], F.ex[l], F.ey[l], F.einv[l]);
-      dk = fminf(dk, d2);
-      if (d2 < best) {
-        best = d2; btype = 1; bPx = wx; bPy = wy;
-        bAx = F.vx[l]; bAy = F.vy[l]; bVx = F.ex[l]; bVy = F.ey[l]; bIv = F.einv[l];
-      }
-    }
-    epool[k % MI] = fminf(epool[k % MI], dk);
-    if (k < MI) dA[k] = dk;
-  }
-  if (o.closed) {
-    // B~_j coincides with A~_{j+1}: its pool entries also belong to edge j.
-#pragma unroll
-    for (int j = 0; j < MI; ++j) {
-      const float nxt = (j + 1 < o.mi) ? dA[(j + 1) % MI] : dA[0];
-      epool[j] = fminf(epool[j], nxt);
-    }
-  }
-  jstar = 0;
-  {
-    float eb = epool[0];
-#pragma unroll
-    for (int j = 1; j < MI; ++j)
-      if (j < o.mi && epool[j] < eb) { eb = epool[j]; jstar = j; }
-  }
-
-  // ---- overlaps (Sec. IV-C), forward only
-  auto obst_range = [&](float nxq, float nyq, float& lo, float& hi, float& lox, float& loy,
-                        float& hix, float& hiy) {
-    lo = __builtin_huge_valf(); hi = -__builtin_huge_valf();
-    lox = loy = hix = hiy = 0.f;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      if (k >= MI && o.closed) break;
-      const float wx = vx_of(k), wy = vy_of(k);
-      const float p = fmaf(wx, nxq, wy * nyq);
-      if (p < lo) { lo = p; lox = wx; loy = wy; }
-      if (p > hi) { hi = p; hix = wx; hiy = wy; }
-    }
-  };
-  auto robot_range = [&](float nxq, float nyq, float& lo, float& hi, float& lox, float& loy,
-                         float& hix, float& hiy) {
-    lo = __builtin_huge_valf(); hi = -__builtin_huge_valf();
-    lox = loy = hix = hiy = 0.f;
-#pragma unroll
-    for (int l = 0; l < MF; ++l) {
-      const float p = fmaf(F.vx[l], nxq, F.vy[l] * nyq);
-      if (p < lo) { lo = p; lox = F.vx[l]; loy = F.vy[l]; }
-      if (p > hi) { hi = p; hix = F.vx[l]; hiy = F.vy[l]; }
-    }
-  };
-  auto axis = [&](int q, float& nxq, float& nyq) {
-    nxq = q < MF ? F.nx[q] : L.nx[q - MF];
-    nyq = q < MF ? F.ny[q] : L.ny[q - MF];
-  };
-  float dl[KA];
-  bool sep = false;
-#pragma unroll
-  for (int q = 0; q < KA; ++q) {
-    float nxq, nyq, lo, hi, a, b, c0, d0;
-    axis(q, nxq, nyq);
-    obst_range(nxq, nyq, lo, hi, a, b, c0, d0);
-    float alo, ahi;
-    if (q < MF) { alo = F.pa[q]; ahi = F.pb[q]; }
-    else robot_range(nxq, nyq, alo, ahi, a, b, c0, d0);
-    dl[q] = fminf(hi - alo, ahi - lo);
-    sep = sep || (dl[q] < -F.eps_sat);
-  }
-
-  // ---- reverse
-  float sd;
-  if (sep) {
-    sd = sqrtf(best);
-    const float coef = 1.0f / (2.0f * sd);   // d sd / d(d^2)
-    // d^2 = |w - t V|^2, w = P - A, t = clamp((w.V) iv2)
-    const float wx = bPx - bAx, wy = bPy - bAy;
-    const float u = fmaf(wx, bVx, wy * bVy) * bIv;
-    const float t = clamp01(u);
-    const float tp = (u > 0.f && u < 1.f) ? 1.f : 0.f;
-    const float rx = 2.f * coef * fmaf(-t, bVx, wx), ry = 2.f * coef * fmaf(-t, bVy, wy);
-    const float rv = fmaf(rx, bVx, ry * bVy) * tp * bIv;
-    const float gwx = rx - rv * bVx, gwy = ry - rv * bVy;              // d/dw
-    if (btype == 0) {
-      // P is a robot vertex (fixed); A = A~_j and V = v_j move with the pose.
-      add_point(bAx, bAy, -gwx, -gwy);
-      add_vector(bVx, bVy, -t * rx - rv * wx, -t * ry - rv * wy);
-    } else {
-      // P is an obstacle point; the robot edge is fixed.
-      add_point(bPx, bPy, gwx, gwy);
-    }
-  } else {
-    // sd = -depth; d depth / d delta+_q is the softmax weight (hard minimum:
-    // 1 at the first minimum); d delta+ / d delta = 1 for delta > 0, else 0.
-    float mu = __builtin_huge_valf();
-    int qmin = 0;
-#pragma unroll
-    for (int q = 0; q < KA; ++q) {
-      const float dp = fmaxf(dl[q], 0.0f);
-      if (live_q(q) && dp < mu) { mu = dp; qmin = q; }
-    }
-    float depth = mu, acc = 1.0f;
-    if (!F.hard) {
-      acc = 0.0f;
-#pragma unroll
-      for (int q = 0; q < KA; ++q)
-        if (live_q(q)) acc += expf(-F.eta * (fmaxf(dl[q], 0.0f) - mu));
-      depth = mu - logf(acc) / F.eta;
-    }
-    sd = -depth;
-#pragma unroll
-    for (int q = 0; q < KA; ++q) {
-      if (!live_q(q) || !(dl[q] > 0.f)) continue;
-      const float w = F.hard ? ((q == qmin) ? 1.f : 0.f) : expf(-F.eta * (dl[q] - mu)) / acc;
-      if (w == 0.f) continue;
-      const float gd = -w;   // d sd / d delta_q
-      float nxq, nyq, lo, hi, lox, loy, hix, hiy;
-      axis(q, nxq, nyq);
-      obst_range(nxq, nyq, lo, hi, lox, loy, hix, hiy);
-      if (q < MF) {
-        // robot axis: constant in the local frame
-        if (hi - F.pa[q] <= F.pb[q] - lo) add_point(hix, hiy, gd * nxq, gd * nyq);   // beta_i - alpha_P
-        else add_point(lox, loy, -gd * nxq, -gd * nyq);                            // beta_P - alpha_i
-      } else {
-        const int j = q - MF;
-        float alo, ahi, rlx, rly, rhx, rhy;
-        robot_range(nxq, nyq, alo, ahi, rlx, rly, rhx, rhy);
-        float gnx, gny;
-        if (hi - alo <= ahi - lo) {
-          add_point(hix, hiy, gd * nxq, gd * nyq);
-          gnx = gd * (hix - rlx); gny = gd * (hiy - rly);
-        } else {
-          add_point(lox, loy, -gd * nxq, -gd * nyq);
-          gnx = gd * (rhx - lox); gny = gd * (rhy - loy);
-        }
-        // n' = (-v_y, v_x) * il  =>  d/dv = (g_ny, -g_nx) * il
-        add_vector(L.vx[j], L.vy[j], gny * o.il[j], -gnx * o.il[j]);
-      }
-    }
-  }
-  g[0] = gscale * -(c * sx - s * sy);
-  g[1] = gscale * -(s * sx + c * sy);
-  g[2] = gscale * gth;
   if (o.bad) sd = __builtin_nanf("");
   return sd;
 }

@@ -6,7 +6,9 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -109,6 +111,18 @@ int prepare_footprint(const float* xy, int m, const psdf_params* params, FpConst
     f.pa[l] = (float)lo;
     f.pb[l] = (float)hi;
   }
+  // certificate constants (see FpConst)
+  double rmax = 0.0, max_ext = 0.0;
+  for (int l = 0; l < m; ++l) {
+    rmax = std::fmax(rmax, std::sqrt(vx[l] * vx[l] + vy[l] * vy[l]));
+    const int a = l, b = (l + 1) % m, c = (l + 2) % m;
+    const double e1x = vx[b] - vx[a], e1y = vy[b] - vy[a], e2x = vx[c] - vx[b], e2y = vy[c] - vy[b];
+    const double ext = std::atan2(e1x * e2y - e1y * e2x, e1x * e2x + e1y * e2y);  // exterior angle
+    max_ext = std::fmax(max_ext, ext);
+  }
+  const double kappa = std::cos(0.5 * max_ext);
+  f.rmax = (float)(rmax * (1.0 + 1e-6) + 1e-6);
+  f.tau_sep = kappa > 1e-3 ? (float)((double)p.eps_sat / kappa + 1e-3) : INFINITY;
   for (int l = m; l < kMaxFp; ++l) {  // padded slots repeat slot m - 1
     f.vx[l] = f.vx[m - 1]; f.vy[l] = f.vy[m - 1];
     f.ex[l] = f.ex[m - 1]; f.ey[l] = f.ey[m - 1];
@@ -145,6 +159,26 @@ LaunchShape choose_shape(int N, int M) {
 }
 
 namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, LaunchShape> g_tuned;   // (mf, mi class, N, M)
+LaunchShape g_override{0, 0};
+int slot_class(int m) { return m <= 8 ? m : 16; }
+}  // namespace
+
+LaunchShape tuned_shape(int m, int mbar, int N, int M) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_override.blk) return g_override;
+  auto it = g_tuned.find(std::make_tuple(slot_class(m), obst_class(mbar), N, M));
+  if (it != g_tuned.end()) return it->second;
+  return choose_shape(N, M);
+}
+
+void remember_shape(int m, int mbar, int N, int M, const LaunchShape& ls) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[std::make_tuple(slot_class(m), obst_class(mbar), N, M)] = ls;
+}
+
+namespace {
 struct Timer {
   std::mutex mu;
   std::vector<hipEvent_t> ev;   // start, stop pairs
@@ -173,6 +207,21 @@ void timer_end(hipStream_t st) {
 }  // namespace psdf
 
 using namespace psdf;
+
+extern "C" int psdf_set_launch_shape(int32_t blk, int32_t sb) {
+  clear_error();
+  if (blk == 0) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_override = LaunchShape{0, 0};
+    return PSDF_OK;
+  }
+  if ((blk != 64 && blk != 256) || sb < 1 || sb > kMaxStageBlock)
+    return set_error(PSDF_EINVAL, "launch shape blk=%d sb=%d (blk 64 or 256, sb 1..%d)", blk, sb,
+                     kMaxStageBlock);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_override = LaunchShape{blk, sb};
+  return PSDF_OK;
+}
 
 extern "C" int psdf_timer_enable(int32_t capacity) {
   clear_error();

@@ -37,10 +37,16 @@ void timer_end(hipStream_t st);
 // Default launch shape of the plain kernel for N stages and M obstacles.
 LaunchShape choose_shape(int N, int M);
 
+// Launch shape for a problem: an explicit override (psdf_set_launch_shape),
+// else the autotuner's cached choice, else choose_shape.
+LaunchShape tuned_shape(int m, int mbar, int N, int M);
+void remember_shape(int m, int mbar, int N, int M, const LaunchShape& ls);
+
 hipError_t launch_plain(const FpConst& F, const float* poses, int N, const psdf_edges& e,
-                        uint64_t* keys, const LaunchShape& ls, hipStream_t st);
+                        uint64_t* partial, const LaunchShape& ls, hipStream_t st);
 hipError_t launch_epilogue(const FpConst& F, const float* poses, int N, const psdf_edges& e,
-                           const uint64_t* keys, const float* gout, int mode, float* d, int* edge,
-                           int* obst, float* grad, hipStream_t st);
+                           const uint64_t* partial, int gx, uint64_t* keys, const float* gout,
+                           int mode, float* d, int* edge, int* obst, float* grad, hipStream_t st);
+int partial_columns(int M, const LaunchShape& ls);
 
 }  // namespace psdf

@@ -1,10 +1,7 @@
-// Explicit instantiation of the plain-path kernels for 4 footprint slots.
+// Explicit instantiation of the per-stage minimum kernel for 4 footprint slots.
 #include "psdf_kernels.hpp"
 
 namespace psdf {
 template hipError_t launch_main_mf<4>(int, const LaunchShape&, const FpConst&, const float*, int,
-                                        const psdf_edges&, uint64_t*, hipStream_t);
-template hipError_t launch_epi_mf<4>(int, const FpConst&, const float*, int, const psdf_edges&,
-                                       const uint64_t*, const float*, int, float*, int*, int*,
-                                       float*, hipStream_t);
+                                       const psdf_edges&, uint64_t*, hipStream_t);
 }  // namespace psdf

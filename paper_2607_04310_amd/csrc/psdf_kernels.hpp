@@ -1,13 +1,15 @@
-// Plain-path kernels, templated on the footprint slot count MF and the
-// obstacle edge class MI; instantiated per MF in psdf_inst_mf*.hip.
+// Per-stage minimum kernel of the plain path, templated on the footprint slot
+// count MF, the obstacle edge class MI and the work-group width BLK;
+// instantiated per MF in psdf_inst_mf*.hip.
 //
-//   main_kernel      lane <-> obstacle; a work-group owns BLK obstacles and a
-//                    block of stages; per stage: sd of the lane's obstacle,
-//                    wave min on the orderable sd, lowest lane of the minimum
-//                    -> one 64-bit atomicMin of (sd, obstacle) per wave and stage
-//   epilogue_kernel  one lane per stage: decode the winner, recompute its
-//                    obstacle with the reverse-mode adjoint, write d, edge,
-//                    obst and the gradient
+// Lane <-> obstacle: a lane loads its obstacle's edges once into registers
+// and evaluates sd for every stage of the work-group's stage block.  Per
+// stage the wave takes the minimum of the orderable sd, the lowest lane
+// holding it names the obstacle (lowest index on ties), and the work-group
+// writes one partial key (orderable(sd) << 32 | obstacle) per stage to
+// partial[stage][blockIdx.x], and the winner's (first edge << 32 | edge
+// count) to aux[stage][blockIdx.x].  The epilogue reduces the partial keys of
+// a stage; no atomics and no initialisation pass are needed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,17 +17,9 @@
 #include "psdf.h"
 #include "psdf_device.hpp"
 #include "psdf_host.hpp"
+#include "psdf_winner.hpp"
 
 namespace psdf {
-
-// ------------------------------------------------------------------ kernels
-
-// Wave-wide minimum of a 32-bit unsigned value.
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, o));
-  return x;
-}
 
 template <int MF, int MI, int BLK>
 __global__ __launch_bounds__(BLK) void main_kernel(FpConst F, const float* __restrict__ poses,
@@ -34,10 +28,24 @@ __global__ __launch_bounds__(BLK) void main_kernel(FpConst F, const float* __res
                                                     const float* __restrict__ bx,
                                                     const float* __restrict__ by,
                                                     const int* __restrict__ off, int E, int M,
-                                                    uint64_t* __restrict__ keys) {
+                                                    uint64_t* __restrict__ partial,
+                                                    uint64_t* __restrict__ aux) {
+  constexpr int NW = BLK / 64;
   __shared__ float4 st[kMaxStageBlock];
+  __shared__ uint64_t wk[NW][kMaxStageBlock];
+  __shared__ uint64_t wa[NW][kMaxStageBlock];
   const int s0 = blockIdx.y * SB;
   const int ns = min(SB, N - s0);
+  const int gx = gridDim.x;
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave_base = blockIdx.x * BLK + w * 64;
+
+  const int i = wave_base + lane;
+  const bool active = i < M;
+  int e0 = 0, mi = 0;
+  if (active) { e0 = off[i]; mi = off[i + 1] - e0; }
+
   for (int t = threadIdx.x; t < ns; t += BLK) {
     const float* p = poses + 3 * (s0 + t);
     float sn, cs;
@@ -46,144 +54,62 @@ __global__ __launch_bounds__(BLK) void main_kernel(FpConst F, const float* __res
   }
   __syncthreads();
 
-  const int wave_base = blockIdx.x * BLK + (threadIdx.x & ~63);
-  if (wave_base >= M) return;
-  const int i = blockIdx.x * BLK + threadIdx.x;
-  const bool active = i < M;
-  int e0 = 0, mi = 0;
-  if (active) { e0 = off[i]; mi = off[i + 1] - e0; }
-  Obst<MI> o;
-  load_obstacle<MI>(o, ax, ay, bx, by, e0, mi, E, F.eps);
-  const bool contributes = active && (mi != 0);
-  const int lane = threadIdx.x & 63;
-
-  for (int t = 0; t < ns; ++t) {
-    const float4 q = st[t];
-    // a non-finite pose makes every obstacle's sd NaN (min / max in the
-    // pipeline would otherwise drop the NaN operands)
-    const bool pose_ok = isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && isfinite(q.w);
-    uint32_t k = 0xffffffffu;
-    if (contributes) k = pose_ok ? orderable(obstacle_sd<MF, MI>(F, o, q.x, q.y, q.z, q.w)) : 0u;
-    const uint32_t kmin = wave_min_u32(k);
-    if (kmin != 0xffffffffu) {
-      const uint64_t hit = __ballot(k == kmin);
-      const int first = __ffsll((unsigned long long)hit) - 1;
-      if (lane == 0)
-        atomicMin((unsigned long long*)&keys[s0 + t],
-                  ((unsigned long long)kmin << 32) | (unsigned)(wave_base + first));
+  if (wave_base < M) {
+    auto emit = [&](int t, uint64_t key, uint64_t a) {
+      if (lane == 0) {
+        if (NW == 1) {
+          partial[(size_t)(s0 + t) * gx + blockIdx.x] = key;
+          aux[(size_t)(s0 + t) * gx + blockIdx.x] = a;
+        } else {
+          wk[w][t] = key;
+          wa[w][t] = a;
+        }
+      }
+    };
+    wave_stages<MF, MI>(F, ax, ay, bx, by, e0, mi, E, active, false, wave_base, ns, st, emit);
+  } else if (NW > 1 && lane == 0) {
+    for (int t = 0; t < ns; ++t) { wk[w][t] = kEmptyKey; wa[w][t] = 0; }
+  }
+  if (NW > 1) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < ns; t += BLK) {
+      uint64_t k = wk[0][t], a = wa[0][t];
+#pragma unroll
+      for (int v = 1; v < NW; ++v)
+        if (wk[v][t] < k) { k = wk[v][t]; a = wa[v][t]; }
+      partial[(size_t)(s0 + t) * gx + blockIdx.x] = k;
+      aux[(size_t)(s0 + t) * gx + blockIdx.x] = a;
     }
   }
 }
 
-// One lane per stage.  mode 0: value only; 1: value + gradient; 2: bwd
-// (gradient scaled by gout, written to grad only).
-template <int MF, int MI>
-__global__ __launch_bounds__(64) void epilogue_kernel(FpConst F, const float* __restrict__ poses,
-                                                      int N, const float* __restrict__ ax,
-                                                      const float* __restrict__ ay,
-                                                      const float* __restrict__ bx,
-                                                      const float* __restrict__ by,
-                                                      const int* __restrict__ off, int E, int M,
-                                                      const uint64_t* __restrict__ keys,
-                                                      const float* __restrict__ gout, int mode,
-                                                      float* __restrict__ d,
-                                                      int* __restrict__ edge,
-                                                      int* __restrict__ obst,
-                                                      float* __restrict__ grad) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= N) return;
-  const uint64_t key = keys[s];
-  const float nan = __builtin_nanf("");
-  float dv, g[3] = {0.f, 0.f, 0.f};
-  int ev = -1, ov = -1;
-  if (key == kEmptyKey) {
-    dv = __builtin_huge_valf();
-  } else if ((key >> 32) == 0 || (key & 0xffffffffu) >= (uint64_t)M) {
-    // NaN result, or a key that names no obstacle of this edge set
-    dv = nan;
-    g[0] = g[1] = g[2] = nan;
-  } else {
-    const int i = (int)(key & 0xffffffffu);
-    const int e0 = off[i], mi = off[i + 1] - e0;
-    Obst<MI> o;
-    load_obstacle<MI>(o, ax, ay, bx, by, e0, mi, E, F.eps);
-    const float* p = poses + 3 * s;
-    float sn, cs;
-    sincosf(p[2], &sn, &cs);
-    const float scale = mode == 2 ? gout[s] : 1.0f;
-    int jstar = 0;
-    obstacle_adjoint<MF, MI>(F, o, cs, sn, p[0], p[1], scale, jstar, g);
-    dv = from_orderable((uint32_t)(key >> 32));
-    ov = i;
-    ev = e0 + jstar;
-  }
-  if (mode == 2) {
-    if (key == kEmptyKey) { g[0] = g[1] = g[2] = 0.f * gout[s]; }
-    grad[3 * s + 0] = g[0];
-    grad[3 * s + 1] = g[1];
-    grad[3 * s + 2] = g[2];
-    return;
-  }
-  d[s] = dv;
-  edge[s] = ev;
-  obst[s] = ov;
-  if (mode == 1) {
-    grad[3 * s + 0] = g[0];
-    grad[3 * s + 1] = g[1];
-    grad[3 * s + 2] = g[2];
-  }
-}
-
-// ------------------------------------------------------------------ dispatch
-
 template <int MF, int MI>
 hipError_t launch_main_t(const LaunchShape& ls, const FpConst& F, const float* poses, int N,
-                                const psdf_edges& e, uint64_t* keys, hipStream_t st) {
+                         const psdf_edges& e, uint64_t* partial, hipStream_t st) {
   dim3 grid((e.M + ls.blk - 1) / ls.blk, (N + ls.sb - 1) / ls.sb);
+  uint64_t* aux = partial + (size_t)N * grid.x;
   if (ls.blk == 64)
     main_kernel<MF, MI, 64><<<grid, 64, 0, st>>>(F, poses, N, ls.sb, e.ax, e.ay, e.bx, e.by,
-                                                  e.obst_off, e.E, e.M, keys);
+                                                  e.obst_off, e.E, e.M, partial, aux);
   else
     main_kernel<MF, MI, 256><<<grid, 256, 0, st>>>(F, poses, N, ls.sb, e.ax, e.ay, e.bx, e.by,
-                                                    e.obst_off, e.E, e.M, keys);
-  return hipGetLastError();
-}
-
-template <int MF, int MI>
-hipError_t launch_epi_t(const FpConst& F, const float* poses, int N, const psdf_edges& e,
-                               const uint64_t* keys, const float* gout, int mode, float* d,
-                               int* edge, int* obst, float* grad, hipStream_t st) {
-  epilogue_kernel<MF, MI><<<(N + 63) / 64, 64, 0, st>>>(F, poses, N, e.ax, e.ay, e.bx, e.by,
-                                                         e.obst_off, e.E, e.M, keys, gout, mode, d,
-                                                         edge, obst, grad);
+                                                    e.obst_off, e.E, e.M, partial, aux);
   return hipGetLastError();
 }
 
 template <int MF>
 hipError_t launch_main_mf(int mi_class, const LaunchShape& ls, const FpConst& F,
-                          const float* poses, int N, const psdf_edges& e, uint64_t* keys,
+                          const float* poses, int N, const psdf_edges& e, uint64_t* partial,
                           hipStream_t st) {
-  if (mi_class == 4) return launch_main_t<MF, 4>(ls, F, poses, N, e, keys, st);
-  if (mi_class == 8) return launch_main_t<MF, 8>(ls, F, poses, N, e, keys, st);
-  return launch_main_t<MF, 16>(ls, F, poses, N, e, keys, st);
+  if (mi_class == 4) return launch_main_t<MF, 4>(ls, F, poses, N, e, partial, st);
+  if (mi_class == 8) return launch_main_t<MF, 8>(ls, F, poses, N, e, partial, st);
+  return launch_main_t<MF, 16>(ls, F, poses, N, e, partial, st);
 }
 
-template <int MF>
-hipError_t launch_epi_mf(int mi_class, const FpConst& F, const float* poses, int N,
-                         const psdf_edges& e, const uint64_t* keys, const float* gout, int mode,
-                         float* d, int* edge, int* obst, float* grad, hipStream_t st) {
-  if (mi_class == 4) return launch_epi_t<MF, 4>(F, poses, N, e, keys, gout, mode, d, edge, obst, grad, st);
-  if (mi_class == 8) return launch_epi_t<MF, 8>(F, poses, N, e, keys, gout, mode, d, edge, obst, grad, st);
-  return launch_epi_t<MF, 16>(F, poses, N, e, keys, gout, mode, d, edge, obst, grad, st);
-}
-
-#define PSDF_EXTERN_MF(MF)                                                                     \
-  extern template hipError_t launch_main_mf<MF>(int, const LaunchShape&, const FpConst&,       \
-                                                const float*, int, const psdf_edges&,          \
-                                                uint64_t*, hipStream_t);                       \
-  extern template hipError_t launch_epi_mf<MF>(int, const FpConst&, const float*, int,         \
-                                               const psdf_edges&, const uint64_t*, const float*, \
-                                               int, float*, int*, int*, float*, hipStream_t);
+#define PSDF_EXTERN_MF(MF)                                                                  \
+  extern template hipError_t launch_main_mf<MF>(int, const LaunchShape&, const FpConst&,    \
+                                                const float*, int, const psdf_edges&,       \
+                                                uint64_t*, hipStream_t);
 PSDF_EXTERN_MF(3)
 PSDF_EXTERN_MF(4)
 PSDF_EXTERN_MF(5)

@@ -1,21 +1,109 @@
 // Plain PSDF path for gfx950: psdf_eval, psdf_grad, psdf_bwd, psdf_encode_padded.
 //
 // Kernel sequence of one call (all on the caller's stream, no host sync):
-// init_keys_kernel (keys[s] = empty), main_kernel (per-stage minimum of
-// (sd, obstacle) by 64-bit atomicMin), epilogue_kernel (winner's adjoint and
-// the outputs).  The kernels live in psdf_kernels.hpp.
+//   main_kernel      per-work-group partial minimum of (sd, obstacle) per stage
+//                    (psdf_kernels.hpp)
+//   epilogue_kernel  one wave per stage: reduce the partial keys, recompute the
+//                    winning obstacle with the wave-parallel adjoint
+//                    (psdf_winner.hpp), write keys, d, edge, obst, gradient
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 
 #include "psdf.h"
 #include "psdf_kernels.hpp"
+#include "psdf_winner.hpp"
 
 namespace psdf {
 
-__global__ void init_keys_kernel(uint64_t* __restrict__ keys, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) keys[i] = kEmptyKey;
+constexpr int kEpiWaves = 4;   // stages per epilogue work-group
+
+// mode 0: value, winner and edge; 1: plus gradient; 2: bwd (gradient scaled
+// by gout[s], written to grad only; keys are read, not reduced).
+__global__ __launch_bounds__(64 * kEpiWaves) void epilogue_kernel(
+    FpConst F, const float* __restrict__ poses, int N, const float* __restrict__ ax,
+    const float* __restrict__ ay, const float* __restrict__ bx, const float* __restrict__ by,
+    const int* __restrict__ off, int E, int M, const uint64_t* __restrict__ partial, int gx,
+    uint64_t* __restrict__ keys, const float* __restrict__ gout, int mode, float* __restrict__ d,
+    int* __restrict__ edge, int* __restrict__ obst, float* __restrict__ grad) {
+  __shared__ FpLds fl[kEpiWaves];
+  __shared__ WinnerLds wl[kEpiWaves];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int s = blockIdx.x * kEpiWaves + w;
+  if (s >= N) return;
+  // Independent loads first: the pose and its rotation, then the partials.
+  const float* p = poses + 3 * s;
+  const float px = p[0], py = p[1];
+  float sn, cs;
+  sincosf(p[2], &sn, &cs);
+  stage_footprint(fl[w], F);
+
+  uint64_t key;
+  int e0 = 0, mi = 0;
+  bool have_aux = false;
+  if (mode == 2) {
+    key = keys[s];
+  } else {
+    // reduce the work-groups' partial keys; the winning column's aux word
+    // carries the obstacle's edge range
+    const uint64_t* aux = partial + (size_t)N * gx;
+    key = kEmptyKey;
+    uint64_t a = 0;
+    for (int j = lane; j < gx; j += 64) {
+      const uint64_t k = partial[(size_t)s * gx + j];
+      if (k < key) { key = k; a = aux[(size_t)s * gx + j]; }
+    }
+    const uint64_t kmin = wave_min_u64(key);
+    const uint64_t hit = __ballot(key == kmin);
+    const int first = __ffsll((unsigned long long)hit) - 1;
+    a = __shfl((unsigned long long)a, first);
+    key = kmin;
+    if (lane == 0) keys[s] = key;
+    e0 = (int)(uint32_t)(a >> 32);
+    mi = (int)(uint32_t)(a & 0xffffffffu);
+    have_aux = true;
+  }
+  wave_sync();
+
+  const float nan = __builtin_nanf("");
+  float dv, g[3] = {0.f, 0.f, 0.f};
+  int ev = -1, ov = -1;
+  const int i = (int)(key & 0xffffffffu);
+  bool valid = key != kEmptyKey && (key >> 32) != 0 && (uint64_t)i < (uint64_t)M;
+  if (valid && !have_aux) {
+    e0 = off[i];
+    mi = off[i + 1] - e0;
+  }
+  valid = valid && mi >= 1 && mi <= kMaxObst && e0 >= 0 && e0 <= E - mi;
+  if (key == kEmptyKey) {
+    dv = __builtin_huge_valf();
+  } else if (!valid) {
+    // NaN result, or a key that names no obstacle of this edge set
+    dv = nan;
+    g[0] = g[1] = g[2] = nan;
+  } else {
+    int jstar = 0;
+    winner_adjoint(F, fl[w], wl[w], ax, ay, bx, by, e0, mi, cs, sn, px, py, mode != 0, jstar, g);
+    dv = from_orderable((uint32_t)(key >> 32));
+    ov = i;
+    ev = e0 + jstar;
+  }
+  if (lane != 0) return;
+  if (mode == 2) {
+    const float sc = gout[s];
+    grad[3 * s + 0] = g[0] * sc;
+    grad[3 * s + 1] = g[1] * sc;
+    grad[3 * s + 2] = g[2] * sc;
+    return;
+  }
+  d[s] = dv;
+  edge[s] = ev;
+  obst[s] = ov;
+  if (mode == 1) {
+    grad[3 * s + 0] = g[0];
+    grad[3 * s + 1] = g[1];
+    grad[3 * s + 2] = g[2];
+  }
 }
 
 static int mf_slots(int m) { return m <= 8 ? m : 16; }
@@ -33,22 +121,25 @@ static int mf_slots(int m) { return m <= 8 ? m : 16; }
     }                                                            \
   }()
 
+int partial_columns(int M, const LaunchShape& ls) { return (M + ls.blk - 1) / ls.blk; }
+
 hipError_t launch_plain(const FpConst& F, const float* poses, int N, const psdf_edges& e,
-                        uint64_t* keys, const LaunchShape& ls, hipStream_t st) {
-  init_keys_kernel<<<(N + 255) / 256, 256, 0, st>>>(keys, N);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess || e.M == 0) return err;
+                        uint64_t* partial, const LaunchShape& ls, hipStream_t st) {
+  if (e.M == 0) return hipSuccess;
   timer_begin(st);
-  err = PSDF_BY_MF(launch_main_mf, obst_class(e.mbar), ls, F, poses, N, e, keys, st);
+  hipError_t err = PSDF_BY_MF(launch_main_mf, obst_class(e.mbar), ls, F, poses, N, e, partial, st);
   timer_end(st);
   return err;
 }
 
 hipError_t launch_epilogue(const FpConst& F, const float* poses, int N, const psdf_edges& e,
-                           const uint64_t* keys, const float* gout, int mode, float* d, int* edge,
-                           int* obst, float* grad, hipStream_t st) {
-  return PSDF_BY_MF(launch_epi_mf, obst_class(e.mbar), F, poses, N, e, keys, gout, mode, d, edge,
-                    obst, grad, st);
+                           const uint64_t* partial, int gx, uint64_t* keys, const float* gout,
+                           int mode, float* d, int* edge, int* obst, float* grad, hipStream_t st) {
+  const int blocks = (N + kEpiWaves - 1) / kEpiWaves;
+  epilogue_kernel<<<blocks, 64 * kEpiWaves, 0, st>>>(F, poses, N, e.ax, e.ay, e.bx, e.by,
+                                                     e.obst_off, e.E, e.M, partial, gx, keys,
+                                                     gout, mode, d, edge, obst, grad);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ EncodeEdges
@@ -126,39 +217,49 @@ static int plain_common(const float* footprint, int32_t m, const float* poses, i
   return PSDF_OK;
 }
 
-int psdf_eval(const float* footprint, int32_t m, const float* poses, int32_t N,
-              const psdf_edges* edges, const psdf_params* params, float* d, int32_t* edge,
-              int32_t* obst, uint64_t* keys, hipStream_t stream) {
+size_t psdf_workspace_bytes(int32_t N, int32_t M) {
+  if (N <= 0 || M <= 0) return 0;
+  // partial keys and their aux words, one column per work-group of 64 lanes
+  return 2 * (size_t)N * (size_t)((M + 63) / 64) * sizeof(uint64_t);
+}
+
+static int plain_run(const float* footprint, int32_t m, const float* poses, int32_t N,
+                     const psdf_edges* edges, const psdf_params* params, float* d, int32_t* edge,
+                     int32_t* obst, float* grad, uint64_t* keys, void* ws, size_t ws_bytes,
+                     int mode, hipStream_t stream) {
   clear_error();
   FpConst F;
   psdf_edges e;
   int rc = plain_common(footprint, m, poses, N, edges, params, F, e);
   if (rc) return rc;
   if (N == 0) return PSDF_OK;
-  if (!d || !edge || !obst || !keys) return set_error(PSDF_EINVAL, "an output pointer is NULL");
-  LaunchShape ls = choose_shape(N, e.M);
-  hipError_t err = launch_plain(F, poses, N, e, keys, ls, stream);
+  if (!d || !edge || !obst || !keys || (mode == 1 && !grad))
+    return set_error(PSDF_EINVAL, "an output pointer is NULL");
+  const size_t need = psdf_workspace_bytes(N, e.M);
+  if (need > 0 && (!ws || ws_bytes < need))
+    return set_error(PSDF_EWS, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  const LaunchShape ls = tuned_shape(F.m, e.mbar, N, e.M);
+  uint64_t* partial = static_cast<uint64_t*>(ws);
+  hipError_t err = launch_plain(F, poses, N, e, partial, ls, stream);
   if (err == hipSuccess)
-    err = launch_epilogue(F, poses, N, e, keys, nullptr, 0, d, edge, obst, nullptr, stream);
+    err = launch_epilogue(F, poses, N, e, partial, e.M > 0 ? partial_columns(e.M, ls) : 0, keys,
+                          nullptr, mode, d, edge, obst, grad, stream);
   return hip_status(err);
+}
+
+int psdf_eval(const float* footprint, int32_t m, const float* poses, int32_t N,
+              const psdf_edges* edges, const psdf_params* params, float* d, int32_t* edge,
+              int32_t* obst, uint64_t* keys, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return plain_run(footprint, m, poses, N, edges, params, d, edge, obst, nullptr, keys, ws,
+                   ws_bytes, 0, stream);
 }
 
 int psdf_grad(const float* footprint, int32_t m, const float* poses, int32_t N,
               const psdf_edges* edges, const psdf_params* params, float* d, int32_t* edge,
-              int32_t* obst, float* grad, uint64_t* keys, hipStream_t stream) {
-  clear_error();
-  FpConst F;
-  psdf_edges e;
-  int rc = plain_common(footprint, m, poses, N, edges, params, F, e);
-  if (rc) return rc;
-  if (N == 0) return PSDF_OK;
-  if (!d || !edge || !obst || !grad || !keys)
-    return set_error(PSDF_EINVAL, "an output pointer is NULL");
-  LaunchShape ls = choose_shape(N, e.M);
-  hipError_t err = launch_plain(F, poses, N, e, keys, ls, stream);
-  if (err == hipSuccess)
-    err = launch_epilogue(F, poses, N, e, keys, nullptr, 1, d, edge, obst, grad, stream);
-  return hip_status(err);
+              int32_t* obst, float* grad, uint64_t* keys, void* ws, size_t ws_bytes,
+              hipStream_t stream) {
+  return plain_run(footprint, m, poses, N, edges, params, d, edge, obst, grad, keys, ws,
+                   ws_bytes, 1, stream);
 }
 
 int psdf_bwd(const float* footprint, int32_t m, const float* poses, int32_t N,
@@ -171,8 +272,8 @@ int psdf_bwd(const float* footprint, int32_t m, const float* poses, int32_t N,
   if (rc) return rc;
   if (N == 0) return PSDF_OK;
   if (!keys || !gout || !gpose) return set_error(PSDF_EINVAL, "keys, gout or gpose is NULL");
-  return hip_status(launch_epilogue(F, poses, N, e, keys, gout, 2, nullptr, nullptr, nullptr,
-                                    gpose, stream));
+  return hip_status(launch_epilogue(F, poses, N, e, nullptr, 0, const_cast<uint64_t*>(keys), gout,
+                                    2, nullptr, nullptr, nullptr, gpose, stream));
 }
 
 size_t psdf_encode_ws_bytes(int32_t Mbar) { return Mbar > 0 ? (size_t)Mbar * sizeof(int) : 0; }

@@ -1,0 +1,456 @@
+// Certified screening of a batch: for each stage, a cheap conservative lower
+// bound LB_i on sd_i for every obstacle, a pool of the P lowest-LB obstacles,
+// a ranking of the pool's edges (the MLP score, or the edge's distance to the
+// pose origin when no network is given), exact evaluation (obstacle_sd) of
+// the obstacles owning the top-K edges, and a certificate: the candidates'
+// minimum phi_K is the stage's PSDF value if every other obstacle has
+//   LB_i > max(phi_K, tau_sep).
+// Then sd_i >= LB_i > phi_K for every excluded obstacle, so the screened key
+// (and winner, and gradient) equal the full evaluation's bit for bit.  A
+// stage that fails the certificate is appended to a list that the fallback
+// kernel evaluates in full.
+//
+// Lower bound (world frame, pose origin p, footprint radius rmax about the
+// origin): for an obstacle whose boundary is a closed convex polygon not
+// containing p, dist(P0(x), P^i) >= dist(p, P^i) - rmax, and dist(p, P^i) is
+// the smallest point-segment distance from p to its edges; an open chain has
+// no interior.  LB_i = dist(p, P^i) - rmax - gamma (gamma absorbs FP32
+// rounding), -inf if p is inside or the obstacle is invalid.  Two convex
+// sets at distance r > tau_sep are separated by the axis test (the largest
+// axis gap is at least kappa r), so their sd is d_sep >= r >= LB_i.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "psdf_batch.hpp"
+#include "psdf_mlp.hpp"
+
+namespace psdf {
+
+constexpr int kScreenThreads = 256;
+constexpr int kScreenKeysPerThread = 64;                       // obstacles per thread
+constexpr int kScreenMaxM = kScreenThreads * kScreenKeysPerThread;   // 16384
+constexpr int kPoolCap = 512;                                  // pool capacity (ties included)
+constexpr float kLbGamma = 1e-3f;
+
+struct ScreenArgs {
+  const FpConst* fps;
+  const BatchInst* insts;
+  const int* stage_inst;   // global stage row -> instance
+  const int* stages;       // this launch's stage rows
+  int n_stages;
+  const float* poses;
+  const float* ax;
+  const float* ay;
+  const float* bx;
+  const float* by;
+  const int* off;
+  const float* theta;      // MLP parameters, or nullptr: rank by edge distance
+  int pool;                // P
+  int topk;                // K
+  uint64_t* keys;
+  int* failed;             // this launch's failed-stage list
+  unsigned* ctrl;          // [0] failed count, [1] fallback item, [2] fallback done
+  int* stage_cand;         // optional: candidates evaluated per stage
+  int* stage_cert;         // optional: 1 if certified
+  uint64_t* cand_keys;     // optional: the candidates' minimum key (before any fallback)
+};
+
+__device__ __forceinline__ float obstacle_lb(float px, float py, const float* __restrict__ ax,
+                                             const float* __restrict__ ay,
+                                             const float* __restrict__ bx,
+                                             const float* __restrict__ by, int e0, int mi, int Eend,
+                                             float eps, float rmax) {
+  if (mi == 0) return __builtin_huge_valf();
+  if (mi < 0 || mi > kMaxObst || e0 < 0 || e0 > Eend - mi) return -__builtin_huge_valf();
+  float d2 = __builtin_huge_valf();
+  bool pos = true, neg = true, closed = mi >= 3, finite = true;
+  for (int j = 0; j < mi; ++j) {
+    const float a0 = ax[e0 + j], a1 = ay[e0 + j], b0 = bx[e0 + j], b1 = by[e0 + j];
+    const int nx = j + 1 < mi ? j + 1 : 0;
+    closed = closed && __float_as_uint(b0) == __float_as_uint(ax[e0 + nx]) &&
+             __float_as_uint(b1) == __float_as_uint(ay[e0 + nx]);
+    finite = finite && isfinite(a0) && isfinite(a1) && isfinite(b0) && isfinite(b1);
+    float iv2, il;
+    edge_consts(b0 - a0, b1 - a1, eps, iv2, il);
+    d2 = fminf(d2, seg_d2(px, py, a0, a1, b0 - a0, b1 - a1, iv2));
+    const float cr = (b0 - a0) * (py - a1) - (b1 - a1) * (px - a0);
+    pos = pos && cr >= 0.f;
+    neg = neg && cr <= 0.f;
+  }
+  if (!finite || (closed && (pos || neg))) return -__builtin_huge_valf();
+  return sqrtf(d2) - rmax - kLbGamma;
+}
+
+__device__ __forceinline__ int block_sum_i32(int v, int* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int r = 0;
+#pragma unroll
+  for (int i = 0; i < kScreenThreads / 64; ++i) r += red[i];
+  __syncthreads();
+  return r;
+}
+
+// Threshold search by bisection on the key values (no atomics): returns X
+// with count(keys <= X) in [lo_n, hi_n] when one exists, else the largest
+// X with count <= hi_n found.  Keys equal to 0xffffffff are unused slots.
+// lo and hi are the smallest and largest used key.
+template <int KPT>
+__device__ uint32_t block_threshold(const uint32_t (&k)[KPT], uint32_t lo, uint32_t hi, int lo_n,
+                                    int hi_n, int* red) {
+  auto count = [&](uint32_t x) {
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) c += k[q] <= x && k[q] != 0xffffffffu;
+    return block_sum_i32(c, red);
+  };
+  uint32_t a = lo, b = hi;
+  int ca = count(a);
+  if (ca > hi_n) return a;   // a tie block larger than the window at the minimum
+  while (b - a > 1u) {
+    const uint32_t mid = a + (b - a) / 2u;
+    const int c = count(mid);
+    if (c > hi_n) b = mid;
+    else if (c < lo_n) { a = mid; ca = c; }
+    else return mid;
+  }
+  return a;
+}
+
+__device__ __forceinline__ uint32_t block_min_u32(uint32_t v, uint32_t* red) {
+  v = wave_min_u32(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  uint32_t r = red[0];
+#pragma unroll
+  for (int i = 1; i < kScreenThreads / 64; ++i) r = min(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+// Exclusive block scan of one int per thread; returns the prefix, *total the sum.
+__device__ __forceinline__ int block_scan(int v, int* scratch, int* total) {
+  const int tid = threadIdx.x;
+  scratch[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < kScreenThreads; o <<= 1) {
+    const int a = tid >= o ? scratch[tid - o] : 0;
+    __syncthreads();
+    scratch[tid] += a;
+    __syncthreads();
+  }
+  const int incl = scratch[tid];
+  *total = scratch[kScreenThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+template <int MF, int MI>
+__global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
+  __shared__ int scan[kScreenThreads];
+  __shared__ uint32_t red[kScreenThreads / 64];
+  __shared__ int pool_o[kPoolCap];        // pool obstacles (local index), increasing
+  __shared__ uint32_t pool_lb[kPoolCap];  // their orderable LB
+  __shared__ float score[kPoolCap * MI];  // per pool edge slot (+inf for unused slots)
+  __shared__ uint8_t cand[kPoolCap];
+  __shared__ int cand_o[kPoolCap];
+  __shared__ uint64_t wkey[kScreenThreads / 64];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int s = A.stages[blockIdx.x];
+  const int inst = __builtin_amdgcn_readfirstlane(A.stage_inst[s]);
+  const BatchInst in = A.insts[inst];
+  const FpConst& F = A.fps[inst];
+  const float* p = A.poses + 3 * s;
+  const float px = p[0], py = p[1];
+  float sn, cs;
+  sincosf(p[2], &sn, &cs);
+  const bool pose_ok = isfinite(px) && isfinite(py) && isfinite(cs) && isfinite(sn);
+  const int M = in.M, Eend = in.edge_off + in.E;
+  const int* off = A.off + in.obst_off;
+
+  // ---- lower bounds, thread t owns obstacles [64 t, 64 t + 64)
+  uint32_t k[kScreenKeysPerThread];
+  const int o_base = tid * kScreenKeysPerThread;
+#pragma unroll
+  for (int q = 0; q < kScreenKeysPerThread; ++q) {
+    const int o = o_base + q;
+    uint32_t key = 0xffffffffu;
+    if (o < M) {
+      const int a = off[o], b = off[o + 1];
+      const float lbv = obstacle_lb(px, py, A.ax, A.ay, A.bx, A.by, in.edge_off + a, b - a, Eend,
+                                    F.eps, F.rmax);
+      key = (b - a == 0) ? 0xffffffffu : orderable(pose_ok ? lbv : -__builtin_huge_valf());
+    }
+    k[q] = key;
+  }
+
+  // ---- pool: every obstacle with LB key <= T, about P of them
+  const int P = max(1, min(A.pool, kPoolCap));
+  uint32_t kmin = 0xffffffffu, kmax = 0u;
+  int used = 0;
+#pragma unroll
+  for (int q = 0; q < kScreenKeysPerThread; ++q)
+    if (k[q] != 0xffffffffu) { kmin = min(kmin, k[q]); kmax = max(kmax, k[q]); ++used; }
+  kmin = block_min_u32(kmin, red);
+  kmax = ~block_min_u32(~kmax, red);
+  const int n_used = block_sum_i32(used, scan);
+  const uint32_t T = n_used > P ? block_threshold<kScreenKeysPerThread>(k, kmin, kmax, (3 * P) / 4,
+                                                                         P, scan)
+                                : 0xfffffffeu;
+  int mine = 0;
+#pragma unroll
+  for (int q = 0; q < kScreenKeysPerThread; ++q) mine += k[q] <= T && k[q] != 0xffffffffu;
+  int pool_n = 0;
+  int at = block_scan(mine, scan, &pool_n);
+  const bool overflow = pool_n > kPoolCap;
+  if (!overflow) {
+#pragma unroll
+    for (int q = 0; q < kScreenKeysPerThread; ++q)
+      if (k[q] <= T && k[q] != 0xffffffffu) {
+        pool_o[at] = o_base + q;
+        pool_lb[at] = k[q];
+        ++at;
+      }
+  }
+  // smallest LB key outside the pool
+  uint32_t rest = 0xffffffffu;
+#pragma unroll
+  for (int q = 0; q < kScreenKeysPerThread; ++q)
+    if (k[q] > T) rest = min(rest, k[q]);
+  rest = block_min_u32(rest, red);
+  __syncthreads();
+
+  uint64_t keyK = kEmptyKey;
+  int n_cand = 0;
+  bool cert = false;
+  if (!overflow && pool_n > 0) {
+    // ---- score the pool's edges
+    const int slots = pool_n * MI;
+    for (int e = tid; e < kPoolCap * MI; e += kScreenThreads) score[e] = __builtin_huge_valf();
+    __syncthreads();
+    if (A.theta) {
+      MlpFrag fr;
+      mlp_load(A.theta, fr);
+      const int n = lane & 15, g = lane >> 4;
+      for (int base = w * 16; base < slots; base += 16 * (kScreenThreads / 64)) {
+        const int e = base + n;
+        const int q = e / MI, j = e - q * MI;
+        float x0 = 0.f, x1 = 0.f, x2 = 0.f, x3 = 0.f;
+        bool valid = false;
+        if (e < slots) {
+          const int o = pool_o[q];
+          const int a = off[o], mi = off[o + 1] - a;
+          if (j < mi) {
+            const int ge = in.edge_off + a + j;
+            float lax, lay, lbx, lby;
+            local_point(A.ax[ge], A.ay[ge], cs, sn, px, py, lax, lay);
+            local_point(A.bx[ge], A.by[ge], cs, sn, px, py, lbx, lby);
+            const float sc = 1.0f / kFeatureScale;
+            x0 = lax * sc; x1 = lay * sc; x2 = lbx * sc; x3 = lby * sc;
+            valid = true;
+          }
+        }
+        MlpAct act;
+        mlp_forward16(fr, x0, x1, x2, x3, act);
+        if (g == 0 && valid) score[e] = act.y;
+      }
+    } else {
+      for (int e = tid; e < slots; e += kScreenThreads) {
+        const int q = e / MI, j = e - q * MI;
+        const int o = pool_o[q];
+        const int a = off[o], mi = off[o + 1] - a;
+        if (j < mi) {
+          const int ge = in.edge_off + a + j;
+          const float a0 = A.ax[ge], a1 = A.ay[ge], wx = A.bx[ge] - a0, wy = A.by[ge] - a1;
+          float iv2, il;
+          edge_consts(wx, wy, F.eps, iv2, il);
+          score[e] = sqrtf(seg_d2(px, py, a0, a1, wx, wy, iv2));
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- top-K edges -> candidate obstacles
+    constexpr int SPT = kPoolCap * MI / kScreenThreads;
+    uint32_t sk[SPT];
+    int live = 0;
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int e = tid * SPT + q;
+      const float v = score[e];
+      sk[q] = (e < slots && v != __builtin_huge_valf()) ? orderable(v) : 0xffffffffu;
+      live += sk[q] != 0xffffffffu;
+    }
+    uint32_t smin = 0xffffffffu, smax = 0u;
+#pragma unroll
+    for (int q = 0; q < SPT; ++q)
+      if (sk[q] != 0xffffffffu) { smin = min(smin, sk[q]); smax = max(smax, sk[q]); }
+    smin = block_min_u32(smin, red);
+    smax = ~block_min_u32(~smax, red);
+    const int n_live = block_sum_i32(live, scan);
+    const int K = max(1, A.topk);
+    const uint32_t S = n_live > K ? block_threshold<SPT>(sk, smin, smax, (7 * K) / 8, K, scan)
+                                  : 0xfffffffeu;
+    for (int q = tid; q < pool_n; q += kScreenThreads) cand[q] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SPT; ++q)
+      if (sk[q] <= S && sk[q] != 0xffffffffu) cand[(tid * SPT + q) / MI] = 1;
+    __syncthreads();
+    // compact candidates in pool (index) order; a pool member whose LB is -inf
+    // (pose inside, invalid or non-finite) is always a candidate
+    int cnt = 0;
+    const int per = (pool_n + kScreenThreads - 1) / kScreenThreads;
+    for (int q = tid * per; q < min(pool_n, (tid + 1) * per); ++q) {
+      if (pool_lb[q] <= orderable(-__builtin_huge_valf())) cand[q] = 1;
+      cnt += cand[q];
+    }
+    int c_at = block_scan(cnt, scan, &n_cand);
+    for (int q = tid * per; q < min(pool_n, (tid + 1) * per); ++q)
+      if (cand[q]) cand_o[c_at++] = pool_o[q];
+    // smallest LB among pool members that are not candidates
+    uint32_t excl = rest;
+    for (int q = tid; q < pool_n; q += kScreenThreads)
+      if (!cand[q]) excl = min(excl, pool_lb[q]);
+    excl = block_min_u32(excl, red);
+
+    // ---- exact evaluation of the candidates (lane <-> candidate)
+    uint64_t best = kEmptyKey;
+    for (int c0 = 0; c0 < n_cand; c0 += kScreenThreads) {
+      const int c = c0 + tid;
+      const bool act = c < n_cand;
+      int e0 = 0, mi = 0, o = 0;
+      if (act) {
+        o = cand_o[c];
+        e0 = off[o];
+        mi = off[o + 1] - e0;
+        e0 += in.edge_off;
+      }
+      Obst<MI> ob;
+      load_obstacle<MI>(ob, A.ax, A.ay, A.bx, A.by, e0, mi, Eend, F.eps);
+      if (act && e0 < in.edge_off) ob.bad = true;
+      uint32_t kk = 0xffffffffu;
+      if (act && mi != 0) kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, cs, sn, px, py)) : 0u;
+      const uint64_t key = kk == 0xffffffffu ? kEmptyKey : (((uint64_t)kk << 32) | (uint32_t)o);
+      const uint64_t wmin = wave_min_u64(key);
+      best = wmin < best ? wmin : best;
+    }
+    if (lane == 0) wkey[w] = best;
+    __syncthreads();
+    keyK = wkey[0];
+#pragma unroll
+    for (int i = 1; i < kScreenThreads / 64; ++i) keyK = wkey[i] < keyK ? wkey[i] : keyK;
+    // ---- certificate
+    const float phiK = keyK == kEmptyKey ? __builtin_huge_valf()
+                                         : from_orderable((uint32_t)(keyK >> 32));
+    const float lbx = excl == 0xffffffffu ? __builtin_huge_valf() : from_orderable(excl);
+    cert = (keyK != kEmptyKey && (keyK >> 32) == 0)            // NaN wins anyway
+           || excl == 0xffffffffu                               // nothing excluded
+           || lbx > fmaxf(phiK, F.tau_sep);
+  } else {
+    cert = !overflow && pool_n == 0;   // no obstacle at all
+  }
+  if (tid == 0) {
+    A.keys[s] = keyK;
+    if (A.stage_cand) A.stage_cand[s] = n_cand;
+    if (A.stage_cert) A.stage_cert[s] = cert ? 1 : 0;
+    if (A.cand_keys) A.cand_keys[s] = keyK;
+    if (!cert) A.failed[atomicAdd(&A.ctrl[0], 1u)] = s;
+  }
+}
+
+// Full evaluation of the failed stages: items (failed stage, tile of 256
+// obstacles) pulled from a counter; each work-group folds its tile's minimum
+// into keys[s] with a 64-bit atomicMin.  The last work-group out clears the
+// failed count and the item counter.
+template <int MF, int MI>
+__global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int max_tiles) {
+  __shared__ int s_item;
+  __shared__ uint64_t wk[4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int n_failed = (int)__hip_atomic_load(&A.ctrl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    if (tid == 0) s_item = (int)atomicAdd(&A.ctrl[1], 1u);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= n_failed * max_tiles) break;
+    const int s = A.failed[it / max_tiles], tile = it % max_tiles;
+    const int inst = __builtin_amdgcn_readfirstlane(A.stage_inst[s]);
+    const BatchInst in = A.insts[inst];
+    if (tile * 256 < in.M) {
+      const FpConst& F = A.fps[inst];
+      const float* p = A.poses + 3 * s;
+      const float px = p[0], py = p[1];
+      float sn, cs;
+      sincosf(p[2], &sn, &cs);
+      const bool pose_ok = isfinite(px) && isfinite(py) && isfinite(cs) && isfinite(sn);
+      const int o = tile * 256 + tid;
+      const bool act = o < in.M;
+      int e0 = 0, mi = 0;
+      if (act) {
+        e0 = A.off[in.obst_off + o];
+        mi = A.off[in.obst_off + o + 1] - e0;
+        e0 += in.edge_off;
+      }
+      Obst<MI> ob;
+      load_obstacle<MI>(ob, A.ax, A.ay, A.bx, A.by, e0, mi, in.edge_off + in.E, F.eps);
+      if (act && e0 < in.edge_off) ob.bad = true;
+      uint32_t kk = 0xffffffffu;
+      if (act && mi != 0) kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, cs, sn, px, py)) : 0u;
+      const uint64_t key = kk == 0xffffffffu ? kEmptyKey : (((uint64_t)kk << 32) | (uint32_t)o);
+      const uint64_t wmin = wave_min_u64(key);
+      if (lane == 0) wk[w] = wmin;
+      __syncthreads();
+      if (tid == 0) {
+        uint64_t m = wk[0];
+        for (int i = 1; i < 4; ++i) m = wk[i] < m ? wk[i] : m;
+        if (m != kEmptyKey) atomicMin((unsigned long long*)&A.keys[s], (unsigned long long)m);
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const unsigned done =
+        __hip_atomic_fetch_add(&A.ctrl[2], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (done == gridDim.x) {
+      __hip_atomic_store(&A.ctrl[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&A.ctrl[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&A.ctrl[2], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+template <int MF>
+hipError_t launch_screen_mf(int mi_class, int grid, const ScreenArgs& a, hipStream_t st) {
+  if (mi_class == 4) screen_kernel<MF, 4><<<grid, kScreenThreads, 0, st>>>(a);
+  else if (mi_class == 8) screen_kernel<MF, 8><<<grid, kScreenThreads, 0, st>>>(a);
+  else screen_kernel<MF, 16><<<grid, kScreenThreads, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+template <int MF>
+hipError_t launch_fallback_mf(int mi_class, int grid, int max_tiles, const ScreenArgs& a,
+                              hipStream_t st) {
+  if (mi_class == 4) screen_fallback_kernel<MF, 4><<<grid, 256, 0, st>>>(a, max_tiles);
+  else if (mi_class == 8) screen_fallback_kernel<MF, 8><<<grid, 256, 0, st>>>(a, max_tiles);
+  else screen_fallback_kernel<MF, 16><<<grid, 256, 0, st>>>(a, max_tiles);
+  return hipGetLastError();
+}
+
+#define PSDF_EXTERN_SCREEN(MF)                                                                  \
+  extern template hipError_t launch_screen_mf<MF>(int, int, const ScreenArgs&, hipStream_t);    \
+  extern template hipError_t launch_fallback_mf<MF>(int, int, int, const ScreenArgs&, hipStream_t);
+PSDF_EXTERN_SCREEN(3)
+PSDF_EXTERN_SCREEN(4)
+PSDF_EXTERN_SCREEN(5)
+PSDF_EXTERN_SCREEN(6)
+PSDF_EXTERN_SCREEN(7)
+PSDF_EXTERN_SCREEN(8)
+PSDF_EXTERN_SCREEN(16)
+
+}  // namespace psdf

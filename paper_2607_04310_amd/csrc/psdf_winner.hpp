@@ -1,0 +1,311 @@
+// Winner adjoint, one wave per stage.
+//
+// Given the winning obstacle of a stage, a whole wave (64 lanes) recomputes
+// that obstacle's pipeline with the same device arithmetic as obstacle_sd
+// and returns:
+//   * the reported edge: the smallest per-edge pool distance, lowest index
+//     on ties (the pool entries of a V_obs point A~_j or B~_j belong to edge
+//     j, and for a closed polygon A~_j also to edge j - 1);
+//   * the pose gradient, the reverse-mode adjoint through the active branch
+//     of every min / max (Sec. IV-D active-branch subgradient): in the
+//     separated branch through the winning point-segment pair (first entry on
+//     ties), otherwise through the soft-min weights of the axis overlaps and,
+//     for each axis, the first extreme vertices of both intervals.
+// Lanes share the work: one pool entry per lane (strided), one SAT axis per
+// lane; the winner's local geometry is staged in LDS.
+//
+// The adjoint is contracted on the fly: a local point P~ with adjoint gP
+// contributes -R gP to d/dp and gP . (P~_y, -P~_x) to d/dtheta (P~ moves by
+// -R^T dp + dtheta (P~_y, -P~_x)); a local edge vector v with adjoint gv
+// contributes gv . (v_y, -v_x) to d/dtheta.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "psdf_device.hpp"
+
+namespace psdf {
+
+// Footprint constants staged in LDS for lane-indexed access.
+struct FpLds {
+  float vx[kMaxFp], vy[kMaxFp], ex[kMaxFp], ey[kMaxFp], einv[kMaxFp];
+  float nx[kMaxFp], ny[kMaxFp], pa[kMaxFp], pb[kMaxFp];
+};
+
+// The winner's local geometry, one per wave.
+struct WinnerLds {
+  float tax[kMaxObst], tay[kMaxObst], vx[kMaxObst], vy[kMaxObst];
+  float nx[kMaxObst], ny[kMaxObst], iv2[kMaxObst], il[kMaxObst];
+  float px[2 * kMaxObst], py[2 * kMaxObst];   // V_obs: A~_k, then B~_k (open obstacles)
+  unsigned epool[kMaxObst];                   // per-edge minimum d^2 (float bits)
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wave-wide minimum of a 32-bit unsigned value.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, o));
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t y = __shfl_xor((unsigned long long)x, o);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Copy the footprint constants into LDS (static indices only).
+__device__ __forceinline__ void stage_footprint(FpLds& L, const FpConst& F) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int l = 0; l < kMaxFp; ++l) {
+    if (lane == l) {
+      L.vx[l] = F.vx[l]; L.vy[l] = F.vy[l]; L.ex[l] = F.ex[l]; L.ey[l] = F.ey[l];
+      L.einv[l] = F.einv[l]; L.nx[l] = F.nx[l]; L.ny[l] = F.ny[l];
+      L.pa[l] = F.pa[l]; L.pb[l] = F.pb[l];
+    }
+  }
+}
+
+// Per-stage minimum over one wave's obstacles (lane <-> obstacle, edges
+// [e0, e0 + mi) held in registers) for the ns stages of the table st (c, s,
+// px, py).  For each stage emit(t, key, aux) receives the wave's minimum key
+// (orderable(sd) << 32 | obase + lane of the first minimum, or the empty
+// key) and that lane's (e0 << 32 | mi).  A wave whose obstacles all have at
+// most one edge (free segments) takes the one-edge specialisation, which is
+// the same arithmetic on one slot instead of MI.
+template <int MF, int MIX, class Emit>
+__device__ __forceinline__ void wave_stages_t(const FpConst& F, const float* __restrict__ ax,
+                                              const float* __restrict__ ay,
+                                              const float* __restrict__ bx,
+                                              const float* __restrict__ by, int e0, int mi,
+                                              int Eend, bool active, bool bad, int obase, int ns,
+                                              const float4* st, Emit emit) {
+  Obst<MIX> o;
+  load_obstacle<MIX>(o, ax, ay, bx, by, e0, mi, Eend, F.eps);
+  o.bad = o.bad || bad;
+  const bool contributes = active && (mi != 0);
+  for (int t = 0; t < ns; ++t) {
+    const float4 q = st[t];
+    // a non-finite pose makes every obstacle's sd NaN (min / max in the
+    // pipeline would otherwise drop the NaN operands)
+    const bool pose_ok = isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && isfinite(q.w);
+    uint32_t k = 0xffffffffu;
+    if (contributes) k = pose_ok ? orderable(obstacle_sd<MF, MIX>(F, o, q.x, q.y, q.z, q.w)) : 0u;
+    const uint32_t kmin = wave_min_u32(k);
+    uint64_t key = kEmptyKey, a = 0;
+    if (kmin != 0xffffffffu) {
+      const uint64_t hit = __ballot(k == kmin);
+      const int first = __ffsll((unsigned long long)hit) - 1;
+      key = ((uint64_t)kmin << 32) | (uint32_t)(obase + first);
+      a = ((uint64_t)(uint32_t)__shfl(e0, first) << 32) | (uint32_t)__shfl(mi, first);
+    }
+    emit(t, key, a);
+  }
+}
+
+template <int MF, int MI, class Emit>
+__device__ __forceinline__ void wave_stages(const FpConst& F, const float* __restrict__ ax,
+                                            const float* __restrict__ ay,
+                                            const float* __restrict__ bx,
+                                            const float* __restrict__ by, int e0, int mi, int Eend,
+                                            bool active, bool bad, int obase, int ns,
+                                            const float4* st, Emit emit) {
+  const bool segments = __ballot(active && mi > 1) == 0;
+  if (MI > 1 && segments)
+    wave_stages_t<MF, 1>(F, ax, ay, bx, by, e0, mi, Eend, active, bad, obase, ns, st, emit);
+  else
+    wave_stages_t<MF, MI>(F, ax, ay, bx, by, e0, mi, Eend, active, bad, obase, ns, st, emit);
+}
+
+// Whole-wave call with uniform arguments; the obstacle owns edges
+// [e0, e0 + mi), 1 <= mi <= kMaxObst.  Results are uniform across the wave.
+__device__ __forceinline__ void winner_adjoint(const FpConst& F, const FpLds& FL, WinnerLds& W,
+                               const float* __restrict__ ax, const float* __restrict__ ay,
+                               const float* __restrict__ bx, const float* __restrict__ by, int e0,
+                               int mi, float c, float s, float px, float py, bool want_grad,
+                               int& jstar, float g[3]) {
+  const int lane = threadIdx.x & 63;
+  const int m = F.m;
+
+  // ---- stage the obstacle (lane j <-> edge j)
+  bool open_edge = false;
+  if (lane < mi) {
+    const float a0 = ax[e0 + lane], a1 = ay[e0 + lane];
+    const float b0 = bx[e0 + lane], b1 = by[e0 + lane];
+    const int nxt = lane + 1 < mi ? lane + 1 : 0;
+    const float n0 = ax[e0 + nxt], n1 = ay[e0 + nxt];
+    open_edge = __float_as_uint(b0) != __float_as_uint(n0) || __float_as_uint(b1) != __float_as_uint(n1);
+    float iv2, il, tx, ty, vx, vy;
+    edge_consts(b0 - a0, b1 - a1, F.eps, iv2, il);
+    local_point(a0, a1, c, s, px, py, tx, ty);
+    local_vector(b0 - a0, b1 - a1, c, s, vx, vy);
+    W.tax[lane] = tx; W.tay[lane] = ty; W.vx[lane] = vx; W.vy[lane] = vy;
+    W.nx[lane] = -vy * il; W.ny[lane] = vx * il;
+    W.iv2[lane] = iv2; W.il[lane] = il;
+    W.px[lane] = tx; W.py[lane] = ty;
+    W.px[mi + lane] = tx + vx; W.py[mi + lane] = ty + vy;
+  }
+  if (lane < kMaxObst) W.epool[lane] = 0x7f800000u;   // +inf
+  const bool closed = mi >= 3 && __ballot(open_edge) == 0;
+  const int nv = closed ? mi : 2 * mi;
+  wave_sync();
+
+  // ---- pools (Sec. IV-B): entry e < m*mi is robot vertex l = e / mi against
+  // obstacle edge j = e % mi; the rest is V_obs point k against robot edge l.
+  const int PV = m * mi, P = PV + nv * m;
+  uint64_t best = ~0ull;
+  for (int e = lane; e < P; e += 64) {
+    float qx, qy, sax, say, svx, svy, siv;
+    int ej, ej2 = -1;
+    if (e < PV) {
+      const int l = e / mi, j = e - l * mi;
+      qx = FL.vx[l]; qy = FL.vy[l];
+      sax = W.tax[j]; say = W.tay[j]; svx = W.vx[j]; svy = W.vy[j]; siv = W.iv2[j];
+      ej = j;
+    } else {
+      const int e2 = e - PV, k = e2 / m, l = e2 - k * m;
+      qx = W.px[k]; qy = W.py[k];
+      sax = FL.vx[l]; say = FL.vy[l]; svx = FL.ex[l]; svy = FL.ey[l]; siv = FL.einv[l];
+      ej = k < mi ? k : k - mi;
+      if (closed) ej2 = k > 0 ? k - 1 : mi - 1;
+    }
+    const float d2 = seg_d2(qx, qy, sax, say, svx, svy, siv);
+    atomicMin(&W.epool[ej], __float_as_uint(d2));
+    if (ej2 >= 0) atomicMin(&W.epool[ej2], __float_as_uint(d2));
+    const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)e;
+    best = key < best ? key : best;
+  }
+  best = wave_min_u64(best);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  wave_sync();
+  {
+    const uint64_t ek = lane < mi ? (((uint64_t)W.epool[lane] << 32) | (uint32_t)lane) : ~0ull;
+    jstar = (int)(wave_min_u64(ek) & 0xffffffffu);
+  }
+  g[0] = g[1] = g[2] = 0.f;
+  if (!want_grad) return;
+
+  // ---- SAT (Sec. IV-C): lane q < m + mi owns axis q.
+  const int K = m + mi;
+  float dl = __builtin_huge_valf(), nxq = 0.f, nyq = 0.f;
+  float lox = 0.f, loy = 0.f, hix = 0.f, hiy = 0.f;      // obstacle extremes
+  float rlx = 0.f, rly = 0.f, rhx = 0.f, rhy = 0.f;      // robot extremes (obstacle axes)
+  int br = 0;
+  if (lane < K) {
+    float alo, ahi;
+    if (lane < m) {
+      nxq = FL.nx[lane]; nyq = FL.ny[lane];
+      alo = FL.pa[lane]; ahi = FL.pb[lane];
+    } else {
+      const int j = lane - m;
+      nxq = W.nx[j]; nyq = W.ny[j];
+      alo = __builtin_huge_valf(); ahi = -__builtin_huge_valf();
+      for (int l = 0; l < m; ++l) {
+        const float p = fmaf(FL.vx[l], nxq, FL.vy[l] * nyq);
+        if (p < alo) { alo = p; rlx = FL.vx[l]; rly = FL.vy[l]; }
+        if (p > ahi) { ahi = p; rhx = FL.vx[l]; rhy = FL.vy[l]; }
+      }
+    }
+    float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
+    for (int k = 0; k < nv; ++k) {
+      const float wx = W.px[k], wy = W.py[k];
+      const float p = fmaf(wx, nxq, wy * nyq);
+      if (p < lo) { lo = p; lox = wx; loy = wy; }
+      if (p > hi) { hi = p; hix = wx; hiy = wy; }
+    }
+    const float d1 = hi - alo, d2 = ahi - lo;
+    dl = fminf(d1, d2);
+    br = d1 <= d2 ? 0 : 1;
+  }
+  const bool sep = __ballot(lane < K && dl < -F.eps_sat) != 0;
+
+  float sx = 0.f, sy = 0.f, gth = 0.f;
+  if (sep) {
+    // d sd / d(d^2) through the winning pair: d^2 = |w - t V|^2, w = Q - A
+    const int e = (int)(best & 0xffffffffu);
+    const float d2b = __uint_as_float((uint32_t)(best >> 32));
+    float qx, qy, sax, say, svx, svy, siv;
+    const bool vtype = e < PV;
+    if (vtype) {
+      const int l = e / mi, j = e - l * mi;
+      qx = FL.vx[l]; qy = FL.vy[l];
+      sax = W.tax[j]; say = W.tay[j]; svx = W.vx[j]; svy = W.vy[j]; siv = W.iv2[j];
+    } else {
+      const int e2 = e - PV, k = e2 / m, l = e2 - k * m;
+      qx = W.px[k]; qy = W.py[k];
+      sax = FL.vx[l]; say = FL.vy[l]; svx = FL.ex[l]; svy = FL.ey[l]; siv = FL.einv[l];
+    }
+    const float coef = 1.0f / (2.0f * sqrtf(d2b));
+    const float wx = qx - sax, wy = qy - say;
+    const float u = fmaf(wx, svx, wy * svy) * siv;
+    const float t = clamp01(u);
+    const float tp = (u > 0.f && u < 1.f) ? 1.f : 0.f;
+    const float rx = 2.f * coef * fmaf(-t, svx, wx), ry = 2.f * coef * fmaf(-t, svy, wy);
+    const float rv = fmaf(rx, svx, ry * svy) * tp * siv;
+    const float gwx = rx - rv * svx, gwy = ry - rv * svy;   // d/dw
+    if (vtype) {
+      // Q is a robot vertex (fixed); A = A~_j and V = v_j move with the pose
+      const float gvx = -t * rx - rv * wx, gvy = -t * ry - rv * wy;
+      sx = -gwx; sy = -gwy;
+      gth = (-gwx) * say - (-gwy) * sax + gvx * svy - gvy * svx;
+    } else {
+      // Q is an obstacle point; the robot edge is fixed
+      sx = gwx; sy = gwy;
+      gth = gwx * qy - gwy * qx;
+    }
+  } else {
+    // sd = -depth, depth = mu - log(sum exp(-eta (delta+ - mu))) / eta; the
+    // weight of axis q is its softmax weight (hard minimum: 1 at the first
+    // minimum); d delta+ / d delta = 1 for delta > 0, else 0.
+    const float dp = lane < K ? fmaxf(dl, 0.0f) : __builtin_huge_valf();
+    float mu = dp;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mu = fminf(mu, __shfl_xor(mu, o));
+    float w;
+    if (F.hard) {
+      const uint64_t k = lane < K ? (((uint64_t)__float_as_uint(dp) << 32) | (uint32_t)lane) : ~0ull;
+      w = (int)(wave_min_u64(k) & 0xffffffffu) == lane ? 1.f : 0.f;
+    } else {
+      const float acc = wave_sum(lane < K ? expf(-F.eta * (dp - mu)) : 0.f);
+      w = expf(-F.eta * (dl - mu)) / acc;
+    }
+    if (lane < K && dl > 0.f && w != 0.f) {
+      const float gd = -w;   // d sd / d delta_q
+      float gpx, gpy, ptx, pty;
+      const bool upper = br == 0;   // delta = beta_i - alpha_P, else beta_P - alpha_i
+      if (upper) { gpx = gd * nxq; gpy = gd * nyq; ptx = hix; pty = hiy; }
+      else { gpx = -gd * nxq; gpy = -gd * nyq; ptx = lox; pty = loy; }
+      sx = gpx; sy = gpy;
+      gth = gpx * pty - gpy * ptx;
+      if (lane >= m) {
+        const int j = lane - m;
+        // d delta / d n' = (P_hi - V_lo) or (V_hi - P_lo); n' = (-v_y, v_x) il
+        const float gnx = upper ? gd * (hix - rlx) : gd * (rhx - lox);
+        const float gny = upper ? gd * (hiy - rly) : gd * (rhy - loy);
+        const float gvx = gny * W.il[j], gvy = -gnx * W.il[j];
+        gth += gvx * W.vy[j] - gvy * W.vx[j];
+      }
+    }
+    sx = wave_sum(sx); sy = wave_sum(sy); gth = wave_sum(gth);
+  }
+  g[0] = -(c * sx - s * sy);
+  g[1] = -(s * sx + c * sy);
+  g[2] = gth;
+}
+
+}  // namespace psdf

@@ -238,3 +238,44 @@ def random_small(rng, n_obst=8, n_poses=16, lo=-2.0, hi=2.0, fp_m=None, segments
     poses = uniform_poses(rng, n_poses, lo, hi)
     off = csr_offsets([4] * n_obst + [1] * segments)
     return Instance(fp, poses, edges, off, 4, dict(workload="random_small"))
+
+
+# ---------------------------------------------------------------- screener
+
+MLP_HIDDEN = 64
+MLP_INPUTS = 4
+MLP_PARAMS = MLP_HIDDEN * MLP_INPUTS + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + 2 * MLP_HIDDEN + 1
+
+
+def mlp_init_params(seed: int = 0) -> np.ndarray:
+    """Initial screener weights, He-style normal draws (float32), in the layout
+    W1[64][4], b1[64], W2[64][64], b2[64], w3[64], b3."""
+    rng = np.random.default_rng(seed)
+    H, I = MLP_HIDDEN, MLP_INPUTS
+    W1 = rng.normal(0, np.sqrt(2.0 / I), (H, I))
+    W2 = rng.normal(0, np.sqrt(2.0 / H), (H, H))
+    w3 = rng.normal(0, np.sqrt(1.0 / H), H)
+    return np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), w3, [0.0]]).astype(np.float32)
+
+
+def screener_training_pairs(instances, near=1024, far=1024, seed=0):
+    """(stage row, local edge) pairs for screener training over a packed list
+    of instances: per stage, the `near` edges whose midpoints are closest to
+    the pose position and `far` edges drawn uniformly from the rest."""
+    rng = np.random.default_rng(seed)
+    stages, edges = [], []
+    row = 0
+    for inst in instances:
+        mid = 0.5 * (inst.edges[:, :2] + inst.edges[:, 2:]).astype(np.float64)
+        E = len(mid)
+        for s in range(inst.N):
+            d2 = ((mid - inst.poses[s, :2].astype(np.float64)) ** 2).sum(1)
+            k = min(near, E)
+            close = np.argpartition(d2, k - 1)[:k] if k < E else np.arange(E)
+            rest = np.setdiff1d(np.arange(E), close, assume_unique=False)
+            pick = rng.choice(rest, size=min(far, len(rest)), replace=False) if len(rest) else rest
+            sel = np.concatenate([close, pick]).astype(np.int32)
+            stages.append(np.full(len(sel), row + s, np.int32))
+            edges.append(sel)
+        row += inst.N
+    return np.concatenate(stages), np.concatenate(edges)

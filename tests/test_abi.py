@@ -38,7 +38,7 @@ def _call_eval(fp, m=None, N=0, edges=None, params=None, poses=1):
     p = params or _lib.PsdfParams(1e-12, 1e-6, 1000.0)
     d = ctypes.c_void_p(1)
     return _lib.lib().psdf_eval(fp.ctypes.data_as(ctypes.c_void_p), m, ctypes.c_void_p(poses), N,
-                                ctypes.byref(e), ctypes.byref(p), d, d, d, d, None)
+                                ctypes.byref(e), ctypes.byref(p), d, d, d, d, d, 1 << 30, None)
 
 
 def test_valid_footprint_with_no_stage_is_a_no_op():
@@ -80,6 +80,29 @@ def test_null_and_negative_arguments():
     nan_params = _lib.PsdfParams(1e-12, 1e-6, float("nan"))
     assert _call_eval(RECT, params=nan_params) == _lib.PSDF_EINVAL
     assert _call_eval(RECT, params=_lib.PsdfParams(-1.0, 1e-6, 1.0)) == _lib.PSDF_EINVAL
+
+
+def test_workspace_query_and_check():
+    lib = _lib.lib()
+    assert lib.psdf_workspace_bytes(0, 10) == 0 and lib.psdf_workspace_bytes(10, 0) == 0
+    assert lib.psdf_workspace_bytes(50, 4096) == 2 * 50 * 64 * 8
+    # a too-small workspace is rejected before anything is enqueued
+    fp = np.ascontiguousarray(RECT)
+    e = _lib.PsdfEdges(1, 1, 1, 1, 1, 4, 1, 4)
+    p = _lib.PsdfParams(1e-12, 1e-6, 1000.0)
+    d = ctypes.c_void_p(1)
+    rc = lib.psdf_eval(fp.ctypes.data_as(ctypes.c_void_p), 4, d, 3, ctypes.byref(e), ctypes.byref(p),
+                       d, d, d, d, d, 8, None)
+    assert rc == _lib.PSDF_EWS
+
+
+def test_launch_shape_override_validation():
+    lib = _lib.lib()
+    assert lib.psdf_set_launch_shape(128, 1) == _lib.PSDF_EINVAL
+    assert lib.psdf_set_launch_shape(64, 0) == _lib.PSDF_EINVAL
+    assert lib.psdf_set_launch_shape(64, 65) == _lib.PSDF_EINVAL
+    assert lib.psdf_set_launch_shape(256, 4) == _lib.PSDF_OK
+    assert lib.psdf_set_launch_shape(0, 0) == _lib.PSDF_OK
 
 
 def test_encode_workspace_query():

@@ -1,0 +1,134 @@
+"""GPU tests of psdf_batch (uneven batches in one persistent launch, graph
+replay, autotuner) against the per-instance psdf_grad path and the FP64
+oracle."""
+import numpy as np
+import pytest
+
+from paper_2607_04310_amd import inputs
+from parity import check_stages
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_04310_amd import api as _api
+    return _api
+
+
+@pytest.fixture(scope="module")
+def c4():
+    return inputs.c4(512)
+
+
+def per_instance(api, b):
+    """The per-instance launch loop: psdf_grad on views of the packed arrays."""
+    outs = []
+    for k in range(b.n_inst):
+        fp, poses, es = b.instance_views(k)
+        outs.append(api.psdf_grad(fp, poses, es))
+    torch.cuda.synchronize()
+    cat = [torch.cat([o[j] for o in outs]) for j in range(4)]
+    return [x.cpu().numpy() for x in cat]
+
+
+def batch_out(b):
+    b.run()
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in (b.d, b.edge, b.obst, b.grad)]
+
+
+def assert_equal_outputs(a, b):
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y, equal_nan=True)
+
+
+def test_c4_batch_matches_loop_bitwise(api, c4):
+    print(f"[batch] c4 512 instances, {sum(i.N * i.E for i in c4):.3e} pairs", flush=True)
+    b = api.Batch(c4, graph=False)
+    assert_equal_outputs(batch_out(b), per_instance(api, b))
+    b.close()
+
+
+def test_c4_batch_vs_oracle_sampled(api, c4):
+    b = api.Batch(c4, graph=True)
+    d, e, o, g = batch_out(b)
+    sizes = np.array([i.N * i.E for i in c4])
+    pick = list(np.argsort(sizes)[:6]) + list(np.argsort(sizes)[-3:]) + list(range(0, 512, 64))
+    for k in sorted(set(int(x) for x in pick)):
+        inst = c4[k]
+        po = b.desc[k][2]
+        sl = slice(po, po + inst.N)
+        st = check_stages(inst.footprint, inst.poses, inst.edges, inst.obst_off, 1000.0,
+                          d[sl], e[sl], o[sl], g[sl])
+        assert st["stages"] >= inst.N - 3
+    b.close()
+
+
+def test_graph_replay_after_inputs_change(api, c4):
+    sub = c4[:40]
+    b = api.Batch(sub, graph=True)
+    first = batch_out(b)
+    again = batch_out(b)          # replay of the captured graph
+    assert_equal_outputs(first, again)
+    # change the inputs in place; the captured pointers stay valid
+    with torch.no_grad():
+        b.poses[:, 0] += 0.37
+        b.poses[:, 2] -= 0.5
+        b.ax.mul_(1.01)
+    torch.cuda.synchronize()
+    replay = batch_out(b)
+    loop = per_instance(api, b)
+    assert_equal_outputs(replay, loop)
+    assert not np.array_equal(replay[0], first[0])
+    b.close()
+
+
+def test_autotune_keeps_results(api, c4):
+    sub = c4[:96]
+    b = api.Batch(sub, graph=True, autotune=True)
+    ref = batch_out(b)
+    best = b.autotune()
+    info = b.info()
+    assert best > 0 and info["n_items"] > 0 and info["stages_per_item"] in (1, 2, 4, 8, 16)
+    assert_equal_outputs(batch_out(b), ref)
+    # a second plan of the same signature starts from the cached shape
+    b2 = api.Batch(sub, graph=False)
+    assert b2.info()["stages_per_item"] == info["stages_per_item"]
+    assert b2.info()["obstacles_per_tile"] == info["obstacles_per_tile"]
+    assert_equal_outputs(batch_out(b2), ref)
+    b.close()
+    b2.close()
+
+
+def test_batch_mixed_shapes_and_nan(api):
+    rng = np.random.default_rng(77)
+    insts = []
+    for k in range(20):
+        inst = inputs.random_small(rng, n_obst=int(rng.integers(1, 90)), n_poses=int(rng.integers(1, 70)),
+                                   segments=int(rng.integers(0, 9)), lo=-3, hi=3)
+        insts.append(inst)
+    insts[3].poses = insts[3].poses.copy()
+    insts[3].poses[0, 1] = np.nan
+    b = api.Batch(insts, graph=True)
+    d, e, o, g = batch_out(b)
+    assert_equal_outputs([d, e, o, g], per_instance(api, b))
+    po = b.desc[3][2]
+    assert np.isnan(d[po]) and e[po] == -1 and o[po] == -1
+    for k in (0, 5, 11, 19):
+        inst = insts[k]
+        sl = slice(b.desc[k][2], b.desc[k][2] + inst.N)
+        check_stages(inst.footprint, inst.poses, inst.edges, inst.obst_off, 1000.0,
+                     d[sl], e[sl], o[sl], g[sl])
+    b.close()
+
+
+def test_single_instance_batch_equals_plain(api):
+    inst = inputs.c2(0)
+    b = api.Batch([inst], graph=True)
+    assert_equal_outputs(batch_out(b), per_instance(api, b))
+    b.close()

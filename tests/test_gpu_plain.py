@@ -224,3 +224,18 @@ def test_encode_padded(api):
     torch.cuda.synchronize()
     for x, y in zip(d1[:4], d2[:4]):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("blk,sb", [(64, 1), (64, 7), (256, 1), (256, 4), (256, 64)])
+def test_launch_shape_independent(api, blk, sb):
+    """The per-stage minimum and its tie rule are exact: every launch shape
+    gives bit-identical outputs (including a stage block that does not divide N)."""
+    inst = inputs.c2(1)
+    ref = run(api, inst)
+    api.set_launch_shape(blk, sb)
+    try:
+        out = run(api, inst)
+    finally:
+        api.set_launch_shape(0, 0)
+    for x, y in zip(ref, out):
+        assert np.array_equal(x, y)

@@ -33,6 +33,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="bound on the CPU-oracle sample (0 disables it)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="only launch the c2 psdf_grad call `steps` times and a 256 MiB "
+                         "device copy (the calibration of the HBM byte counters)")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="also measure the uneven batch (c4) and the screened path (c5)")
     return ap.parse_args()
 
 
@@ -54,6 +59,75 @@ def cpu_baseline(inst, seconds):
     return dict(value=value, unit="stage×edge evals/s", cores=int(used), kind="oracle",
                 sample=f"{reps} full c2 evaluations (N={inst.N}, E={inst.E}, value+winner+gradient, "
                        f"FP64) in {done:.1f} s")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _timeit(torch, fn, reps, warm):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def extras(torch, api, flops, inputs):
+    """Secondary lines: the uneven batch (c4: persistent graph vs the
+    per-instance loop) and certified screening (c5: plain batch vs screened
+    with the trained MLP and with distance ranking)."""
+    from paper_2607_04310_amd import screener
+    out = {}
+    log("c4: building 512 instances")
+    c4 = inputs.c4(512)
+    pairs4 = sum(i.N * i.E for i in c4)
+    b = api.Batch(c4, graph=True, autotune=True)
+    b.autotune()
+    log(f"c4: autotuned {b.info()}")
+    t_batch = _timeit(torch, b.run, 20, 3)
+    views = [b.instance_views(k) for k in range(b.n_inst)]
+
+    def loop():
+        for fp, poses, es in views:
+            api.psdf_grad(fp, poses, es)
+    t_loop = _timeit(torch, loop, 3, 1)
+    f4 = sum(flops.flops_instance(len(i.footprint), i.N, i.edges, i.obst_off) for i in c4)
+    out["c4_batch"] = dict(pairs=pairs4, batch_ms=t_batch, loop_ms=t_loop,
+                           batch_evals_per_s=pairs4 / (t_batch * 1e-3),
+                           loop_evals_per_s=pairs4 / (t_loop * 1e-3),
+                           batch_tflops=f4 / (t_batch * 1e-3) / 1e12, shape=b.info())
+    b.close()
+
+    # screener trained on held-out instances (different seeds from the test batch)
+    log("c5: training set")
+    X, T = screener.training_set(inputs.c5(10, cfg=6), near=1024, far=1024, seed=1)
+    log(f"c5: training on {X.shape[0]} pairs")
+    theta, hist = screener.train(X, T, epochs=12, batch=4096, lr=2e-3, seed=0, log=log)
+    c5 = inputs.c5(64)
+    pairs5 = sum(i.N * i.E for i in c5)
+    b = api.Batch(c5, graph=True)
+    t_plain = _timeit(torch, b.run, 10, 2)
+    res = dict(pairs=pairs5, train_pairs=int(X.shape[0]), train_loss=hist[-1], plain_ms=t_plain,
+               plain_evals_per_s=pairs5 / (t_plain * 1e-3))
+    ref = [x.clone() for x in (b.d, b.keys)]
+    for name, th in (("mlp", theta), ("distance", None)):
+        log(f"c5: screened, {name} ranking")
+        t = _timeit(torch, lambda: b.screened(th, pool=256, topk=256), 10, 2)
+        (d, _, _, _, keys), (cand, cert, ck) = b.screened(th, pool=256, topk=256, stats=True)
+        torch.cuda.synchronize()
+        exact = bool(torch.equal(keys, ref[1]))
+        res[name] = dict(ms=t, evals_per_s=pairs5 / (t * 1e-3), exact=exact,
+                         certified=float(cert.float().mean()), mean_candidates=float(cand.float().mean()),
+                         winner_recall=float((ck == keys).float().mean()))
+    out["c5_screen"] = res
+    b.close()
+    return out
 
 
 def main():
@@ -81,6 +155,17 @@ def main():
 
     def step():
         api.psdf_grad(inst.footprint, poses, edges, params, out=out, ws=ws)
+
+    if args.counters:
+        src = torch.ones(64 << 20, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            step()
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(counters_run=True, steps=args.steps, copy_bytes=src.numel() * 4)))
+        return
 
     for _ in range(args.warmup):
         step()
@@ -122,6 +207,9 @@ def main():
                       flop_per_launch=flop),
         wall_s=wall,
     )
+    log(f"c2: {value:.3e} evals/s, {ms_step * 1e3:.2f} us per call")
+    if args.extras:
+        res["extras"] = extras(torch, api, flops, inputs)
     if not args.no_cpu and args.cpu_seconds > 0:
         res["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(res), flush=True)

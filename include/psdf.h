@@ -209,7 +209,8 @@ int psdf_batch(psdf_batch_plan* plan, const float* poses, const float* ax, const
 
 /* Autotune the plan's launch shape on real inputs (same arguments as
  * psdf_batch): times each candidate (stages per work item x obstacles per
- * tile) on `stream`, synchronising it, keeps the fastest in the plan and in a
+ * tile x persistent grid or one work-group per item) on `stream`,
+ * synchronising it, keeps the fastest in the plan and in a
  * process-wide cache keyed by the batch's size signature (later plans of the
  * same signature start from it; with PSDF_TUNE_CACHE set to a file path the
  * cache is also read from and appended to that file).  Outputs are left
@@ -219,16 +220,21 @@ int psdf_batch_autotune(psdf_batch_plan* plan, const float* poses, const float* 
                         const int32_t* obst_off, float* d, int32_t* edge, int32_t* obst,
                         float* grad, uint64_t* keys, hipStream_t stream, float* best_ms);
 
-/* The plan's current shape, work-item count and the largest persistent grid
- * of its launches (one per footprint-size group; host outputs, may be NULL). */
+/* The plan's current shape, work-item count, the largest grid of its
+ * launches (one per footprint-size group) and whether items are dispatched
+ * one per work-group (direct = 1) or pulled by a persistent grid (host
+ * outputs, may be NULL). */
 int psdf_batch_plan_info(const psdf_batch_plan* plan, int32_t* stages_per_item,
-                         int32_t* obstacles_per_tile, int32_t* n_items, int32_t* grid);
+                         int32_t* obstacles_per_tile, int32_t* n_items, int32_t* grid,
+                         int32_t* direct);
 
 /* Certified screened evaluation of a batch (same outputs as psdf_batch, bit
  * for bit).  Per stage: a conservative lower bound LB_i <= sd_i for every
- * obstacle (distance from the pose origin to the obstacle minus the
- * footprint's radius about that origin, minus 1e-3 m; -inf if the origin is
- * inside), a pool of about `pool` lowest-LB obstacles (1..512), a ranking of
+ * obstacle (distance from the pose origin to the obstacle's bounding circle,
+ * which a first kernel computes per call, minus the footprint's radius
+ * about that origin, minus 1e-3 m), a pool of about `pool` lowest-LB
+ * obstacles (1..512) whose bounds are tightened to the distance to the
+ * polygon itself (-inf if the origin is inside), a ranking of
  * the pool's edges by the screener MLP (theta: device float32[PSDF_MLP_PARAMS],
  * see below) or, with theta = NULL, by the edge's distance to the pose origin,
  * exact evaluation of the obstacles owning the `topk` best edges, and the
@@ -236,7 +242,8 @@ int psdf_batch_plan_info(const psdf_batch_plan* plan, int32_t* stages_per_item,
  * phi_K is the candidates' minimum and tau the distance above which the axis
  * test separates two convex sets for this footprint.  Stages that fail the
  * certificate are evaluated in full.  Assumes convex obstacles (Assumption 1)
- * and at most 16384 obstacles per instance (PSDF_ETOOBIG otherwise).
+ * and at most 16384 obstacles per instance and 65535 instances
+ * (PSDF_ETOOBIG otherwise).
  * Optional device outputs (length sum N, may be NULL): stage_cand = obstacles
  * evaluated exactly by the screen, stage_cert = 1 if certified, cand_keys =
  * the candidates' minimum key before any fallback. */

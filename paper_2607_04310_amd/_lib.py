@@ -79,8 +79,7 @@ _SIGS = {
     "psdf_mlp_grad": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP, _VP, ctypes.c_size_t, _VP]),
     "psdf_mlp_train_step": (ctypes.c_int, [_VP, _VP, _VP, _I32, ctypes.c_float, _VP, _VP, _I32,
                                            _VP, _VP, ctypes.c_size_t, _VP]),
-    "psdf_batch_plan_info": (ctypes.c_int, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
-                                            ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "psdf_batch_plan_info": (ctypes.c_int, [_VP] + [ctypes.POINTER(_I32)] * 5),
     "psdf_bwd": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
                                 ctypes.POINTER(PsdfParams), _VP, _VP, _VP, _VP]),
     "psdf_encode_ws_bytes": (ctypes.c_size_t, [_I32]),

@@ -243,10 +243,10 @@ class Batch:
         return best.value
 
     def info(self):
-        vals = [ctypes.c_int32(0) for _ in range(4)]
+        vals = [ctypes.c_int32(0) for _ in range(5)]
         _lib.check(_lib.lib().psdf_batch_plan_info(self.plan, *[ctypes.byref(v) for v in vals]))
         return dict(stages_per_item=vals[0].value, obstacles_per_tile=vals[1].value,
-                    n_items=vals[2].value, grid=vals[3].value)
+                    n_items=vals[2].value, grid=vals[3].value, direct=vals[4].value)
 
     def screened(self, theta=None, pool=256, topk=256, stats=False):
         """Certified screened evaluation (psdf_batch_screened); theta None

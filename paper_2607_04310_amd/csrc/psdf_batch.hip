@@ -18,9 +18,48 @@
 
 namespace psdf {
 
+// Bounding circle of every obstacle of every instance: (cx, cy, r, 0), with
+// r inflated to cover rounding.  Empty obstacles get cx = NaN (never in a
+// pool); invalid ones (bad range, non-finite) r = +inf (always in the pool).
+__global__ void circle_kernel(const BatchInst* __restrict__ insts, const float* __restrict__ ax,
+                              const float* __restrict__ ay, const float* __restrict__ bx,
+                              const float* __restrict__ by, const int* __restrict__ off,
+                              float4* __restrict__ circ) {
+  const BatchInst in = insts[blockIdx.y];
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= in.M) return;
+  const int a = off[in.obst_off + o], b = off[in.obst_off + o + 1], mi = b - a;
+  float4 c = make_float4(__builtin_nanf(""), 0.f, 0.f, 0.f);
+  if (mi != 0) {
+    c = make_float4(0.f, 0.f, __builtin_huge_valf(), 0.f);
+    if (mi > 0 && mi <= kMaxObst && a >= 0 && b <= in.E) {
+      float sx = 0.f, sy = 0.f;
+      bool finite = true;
+      for (int j = 0; j < mi; ++j) {
+        const int e = in.edge_off + a + j;
+        sx += ax[e] + bx[e];
+        sy += ay[e] + by[e];
+        finite = finite && isfinite(ax[e]) && isfinite(ay[e]) && isfinite(bx[e]) && isfinite(by[e]);
+      }
+      if (finite) {
+        const float cx = sx / (2.f * mi), cy = sy / (2.f * mi);
+        float r2 = 0.f;
+        for (int j = 0; j < mi; ++j) {
+          const int e = in.edge_off + a + j;
+          r2 = fmaxf(r2, fmaf(ax[e] - cx, ax[e] - cx, (ay[e] - cy) * (ay[e] - cy)));
+          r2 = fmaxf(r2, fmaf(bx[e] - cx, bx[e] - cx, (by[e] - cy) * (by[e] - cy)));
+        }
+        c = make_float4(cx, cy, sqrtf(r2) * (1.0f + 1e-6f) + 1e-6f, 0.f);
+      }
+    }
+  }
+  circ[in.circ_off + o] = c;
+}
+
 struct Shape {
-  int sb;   // stages per work item
-  int nw;   // waves per work-group (obstacles per tile = 64 nw)
+  int sb;       // stages per work item
+  int nw;       // waves per work-group (obstacles per tile = 64 nw)
+  int direct;   // 1: one work-group per item instead of a persistent grid
 };
 
 }  // namespace psdf
@@ -35,7 +74,7 @@ struct psdf_batch_plan {
   int total_stages = 0;
   std::vector<psdf_batch_desc> desc;
   std::vector<FpConst> fp;
-  Shape shape{1, 4};
+  Shape shape{1, 4, 0};
   int n_items = 0;
   int cu = 256;
   // one persistent launch per footprint-size group (MF = 3..8 or 16)
@@ -57,6 +96,7 @@ struct psdf_batch_plan {
   int* d_stage_list = nullptr;
   int* d_failed = nullptr;
   unsigned* d_sctrl = nullptr;
+  float4* d_circ = nullptr;   // bounding circles, sum M
   struct SGroup { int mf, start, count, max_tiles; };
   std::vector<SGroup> sgroups;
   int max_M = 0;
@@ -94,9 +134,10 @@ void cache_load_locked() {
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   char key[128];
-  int sb, nw;
-  while (std::fscanf(f, "%127s %d %d", key, &sb, &nw) == 3)
-    if (sb >= 1 && sb <= kMaxStageBlock && (nw == 1 || nw == 4)) g_cache[key] = Shape{sb, nw};
+  int sb, nw, direct;
+  while (std::fscanf(f, "%127s %d %d %d", key, &sb, &nw, &direct) == 4)
+    if (sb >= 1 && sb <= kMaxStageBlock && (nw == 1 || nw == 4) && (direct == 0 || direct == 1))
+      g_cache[key] = Shape{sb, nw, direct};
   std::fclose(f);
 }
 
@@ -106,7 +147,7 @@ void cache_store(const std::string& key, Shape s) {
   g_cache[key] = s;
   if (const char* path = std::getenv("PSDF_TUNE_CACHE")) {
     if (FILE* f = std::fopen(path, "a")) {
-      std::fprintf(f, "%s %d %d\n", key.c_str(), s.sb, s.nw);
+      std::fprintf(f, "%s %d %d %d\n", key.c_str(), s.sb, s.nw, s.direct);
       std::fclose(f);
     }
   }
@@ -166,7 +207,7 @@ int build_items(psdf_batch_plan* p, Shape sh) {
   std::vector<BatchInst> inst(p->n_inst);
   std::vector<BatchItem> items;
   std::vector<double> cost;
-  size_t part = 0, blocks = 0;
+  size_t part = 0, blocks = 0, circ = 0;
   for (int k = 0; k < p->n_inst; ++k) {
     const psdf_batch_desc& d = p->desc[k];
     BatchInst& b = inst[k];
@@ -175,6 +216,8 @@ int build_items(psdf_batch_plan* p, Shape sh) {
     b.nt = (d.M + tile - 1) / tile;
     b.part_off = (int)part;
     b.blk_off = (int)blocks;
+    b.circ_off = (int)circ;
+    circ += d.M;
     const int nb = (d.N + sh.sb - 1) / sh.sb;
     part += (size_t)d.N * b.nt;
     blocks += nb;
@@ -218,7 +261,8 @@ int build_items(psdf_batch_plan* p, Shape sh) {
     const int mf = kGroupMF[g];
     const int per_cu = occupancy(mf, p->mi_class, sh.nw);
     const int count = (int)(j - i);
-    p->groups.push_back({mf, (int)i, count, std::max(1, std::min(count, per_cu * p->cu))});
+    const int grid = sh.direct ? count : std::max(1, std::min(count, per_cu * p->cu));
+    p->groups.push_back({mf, (int)i, count, grid});
     i = j;
   }
   free_graph(p);
@@ -231,6 +275,7 @@ BatchArgs make_args(psdf_batch_plan* p, const float* poses, const float* ax, con
   BatchArgs a;
   a.fps = p->d_fp; a.insts = p->d_inst; a.items = p->d_items; a.n_items = p->n_items;
   a.sb = p->shape.sb;
+  a.direct = p->shape.direct;
   a.poses = poses; a.ax = ax; a.ay = ay; a.bx = bx; a.by = by; a.off = off;
   a.partial = p->d_partial; a.aux = p->d_partial + p->partial_cap;
   a.blockcnt = p->d_blockcnt; a.ctrl = p->d_ctrl;   // per-group slices set by enqueue
@@ -388,6 +433,8 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
   if (p->max_M > kScreenMaxM)
     return set_error(PSDF_ETOOBIG, "an instance has %d obstacles; screening supports %d", p->max_M,
                      kScreenMaxM);
+  if (p->n_inst > 65535)
+    return set_error(PSDF_ETOOBIG, "%d instances; screening supports 65535", p->n_inst);
   if (p->total_stages == 0) return PSDF_OK;
   if (!poses || !off || !d || !edge || !obst || !grad || !keys)
     return set_error(PSDF_EINVAL, "a pose, offset or output pointer is NULL");
@@ -395,11 +442,18 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
   ScreenArgs a;
   a.fps = p->d_fp; a.insts = p->d_inst; a.stage_inst = p->d_stage_inst;
   a.poses = poses; a.ax = ax; a.ay = ay; a.bx = bx; a.by = by; a.off = off;
+  a.circ = p->d_circ;
   a.theta = theta; a.pool = pool; a.topk = topk; a.keys = keys;
   a.stage_cand = stage_cand; a.stage_cert = stage_cert; a.cand_keys = cand_keys;
   timer_begin(stream);
   hipError_t err = hipSuccess;
+  if (p->max_M > 0 && p->n_inst > 0) {
+    dim3 grid((p->max_M + 255) / 256, p->n_inst);
+    circle_kernel<<<grid, 256, 0, stream>>>(p->d_inst, ax, ay, bx, by, off, p->d_circ);
+    err = hipGetLastError();
+  }
   for (const auto& g : p->sgroups) {
+    if (err != hipSuccess) break;
     ScreenArgs ga = a;
     ga.stages = p->d_stage_list + g.start;
     ga.n_stages = g.count;
@@ -452,6 +506,7 @@ void psdf_batch_plan_destroy(psdf_batch_plan* p) {
   (void)hipFree(p->d_stage_list);
   (void)hipFree(p->d_failed);
   (void)hipFree(p->d_sctrl);
+  (void)hipFree(p->d_circ);
   (void)hipSetDevice(cur);
   delete p;
 }
@@ -532,7 +587,10 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
       if ((int)list.size() > start)
         p->sgroups.push_back({kGroupMF[g], start, (int)list.size() - start, max_tiles});
     }
-    err = hipMalloc(&p->d_stage_inst, S * sizeof(int));
+    size_t sumM = 0;
+    for (int k = 0; k < n_inst; ++k) sumM += desc[k].M;
+    err = hipMalloc(&p->d_circ, std::max<size_t>(1, sumM) * sizeof(float4));
+    if (err == hipSuccess) err = hipMalloc(&p->d_stage_inst, S * sizeof(int));
     if (err == hipSuccess) err = hipMalloc(&p->d_stage_list, S * sizeof(int));
     if (err == hipSuccess) err = hipMalloc(&p->d_failed, S * sizeof(int));
     if (err == hipSuccess) err = hipMalloc(&p->d_sctrl, 3 * kGroups * sizeof(unsigned));
@@ -547,7 +605,7 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
     psdf_batch_plan_destroy(p);
     return rc;
   }
-  Shape sh{1, 4};
+  Shape sh{1, 4, 0};
   if (!cache_find(signature(*p), &sh)) {
     // heuristic: enough items to spread over the chip, stage blocks as long
     // as that allows
@@ -591,9 +649,10 @@ int psdf_batch_autotune(psdf_batch_plan* p, const float* poses, const float* ax,
   float best = INFINITY;
   Shape best_sh = p->shape;
   int rc = PSDF_OK;
-  for (int nw : nws) {
-    for (int sb : sbs) {
-      rc = build_items(p, Shape{sb, nw});
+  for (int cand = 0; cand < 20 && rc == PSDF_OK; ++cand) {
+    const int nw = nws[(cand / 5) % 2], sb = sbs[cand % 5], direct = cand / 10;
+    {
+      rc = build_items(p, Shape{sb, nw, direct});
       if (rc) break;
       float t_min = INFINITY;
       for (int rep = 0; rep < 4 && rc == PSDF_OK; ++rep) {
@@ -610,9 +669,8 @@ int psdf_batch_autotune(psdf_batch_plan* p, const float* poses, const float* ax,
         if (rep > 0) t_min = std::min(t_min, ms);   // first run warms up
       }
       if (rc) break;
-      if (t_min < best) { best = t_min; best_sh = Shape{sb, nw}; }
+      if (t_min < best) { best = t_min; best_sh = Shape{sb, nw, direct}; }
     }
-    if (rc) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -626,12 +684,14 @@ int psdf_batch_autotune(psdf_batch_plan* p, const float* poses, const float* ax,
 }
 
 int psdf_batch_plan_info(const psdf_batch_plan* p, int32_t* stages_per_item,
-                         int32_t* obstacles_per_tile, int32_t* n_items, int32_t* grid) {
+                         int32_t* obstacles_per_tile, int32_t* n_items, int32_t* grid,
+                         int32_t* direct) {
   clear_error();
   if (!p) return set_error(PSDF_EINVAL, "plan is NULL");
   if (stages_per_item) *stages_per_item = p->shape.sb;
   if (obstacles_per_tile) *obstacles_per_tile = 64 * p->shape.nw;
   if (n_items) *n_items = p->n_items;
+  if (direct) *direct = p->shape.direct;
   if (grid) {
     int g = 0;
     for (const auto& gr : p->groups) g = std::max(g, gr.grid);

@@ -27,6 +27,7 @@ struct BatchInst {
   int nt;         // obstacle tiles
   int blk_off;    // first stage-block counter
   int m;          // footprint vertices
+  int circ_off;   // first bounding circle of this instance's obstacles (screening)
 };
 
 struct BatchItem {
@@ -39,6 +40,7 @@ struct BatchArgs {
   const BatchItem* items;   // this launch's items (one footprint-size group)
   int n_items;
   int sb;
+  int direct;               // 1: one item per work-group (item = blockIdx.x), no counter
   const float* poses;
   const float* ax;
   const float* ay;
@@ -70,8 +72,13 @@ __global__ __launch_bounds__(64 * NW) void batch_kernel(BatchArgs A) {
   __shared__ WinnerLds wl[NW];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
-  for (;;) {
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(&A.ctrl[0], 1u);
+  for (int round = 0;; ++round) {
+    if (A.direct) {
+      if (round > 0) break;
+      if (threadIdx.x == 0) s_item = (int)blockIdx.x;
+    } else if (threadIdx.x == 0) {
+      s_item = (int)atomicAdd(&A.ctrl[0], 1u);
+    }
     __syncthreads();
     const int it = uniform(s_item);
     if (it >= A.n_items) break;
@@ -182,7 +189,7 @@ __global__ __launch_bounds__(64 * NW) void batch_kernel(BatchArgs A) {
     __syncthreads();
   }
   // the last work-group out resets the item counter for the next launch
-  if (threadIdx.x == 0) {
+  if (!A.direct && threadIdx.x == 0) {
     const unsigned done =
         __hip_atomic_fetch_add(&A.ctrl[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
     if (done == gridDim.x) {

@@ -43,6 +43,9 @@ struct FpConst {
   float einv[kMaxFp];            // 1 / (|e_l|^2 + eps)
   float nx[kMaxFp], ny[kMaxFp];  // outward unit normals n_l
   float pa[kMaxFp], pb[kMaxFp];  // robot interval [alpha_P(n_l), beta_P(n_l)]
+  // robot edge frames for the pools: unit direction u_l = e_l / |e_l|,
+  // length |e_l|, and the offsets v_l . u_l, v_l . n_l
+  float ux[kMaxFp], uy[kMaxFp], len[kMaxFp], cu[kMaxFp], cn[kMaxFp];
   // Screening certificate constants: rmax bounds |v_l| (every footprint
   // point is within rmax of the pose origin); tau_sep is the distance above
   // which two convex sets are declared separated by the axis test whatever
@@ -59,6 +62,7 @@ struct Obst {
   float wx[MI], wy[MI];   // B_j - A_j, world
   float iv2[MI];          // 1 / (|B_j - A_j|^2 + eps)
   float il[MI];           // 1 / (|B_j - A_j| + eps)
+  float len[MI];          // |B_j - A_j|
   int mi;
   bool closed;            // B_j == A_{j+1} for all j (bitwise): V_obs = {A~_j}
   bool bad;               // edge count or range invalid, or a non-finite
@@ -127,6 +131,7 @@ __device__ __forceinline__ void load_obstacle(Obst<MI>& o, const float* __restri
     const float dx = b0 - a0, dy = b1 - a1;
     o.wx[j] = dx; o.wy[j] = dy;
     edge_consts(dx, dy, eps, o.iv2[j], o.il[j]);
+    o.len[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy));
   }
   bool finite = true;
 #pragma unroll
@@ -175,6 +180,17 @@ __device__ __forceinline__ void to_local(const Obst<MI>& o, float c, float s, fl
   }
 }
 
+// Distance term of a point against a segment, in the segment's frame: with
+// a = (P - A) . u (along the unit direction u) and b = (P - A) . n (across),
+// the squared point-segment distance is b^2 + (a - clamp(a, 0, L))^2, which
+// is |P - A - t v|^2 with t = clamp(u, 0, 1) of Sec. IV-B (eps -> 0).  The
+// across component b is the separating-axis projection that the pipeline
+// needs anyway, less a per-segment constant.
+__device__ __forceinline__ float frame_d2(float a, float b, float L) {
+  const float c = a - __builtin_amdgcn_fmed3f(a, 0.0f, L);
+  return fmaf(b, b, c * c);
+}
+
 // sd(P0(x), P^i) of one obstacle at one stage (Sec. IV-D).  MF is the number
 // of footprint slots evaluated: the exact m (3..8) or 16 (padded).
 template <int MF, int MI>
@@ -182,30 +198,49 @@ __device__ __forceinline__ float obstacle_sd(const FpConst& F, const Obst<MI>& o
                                              float px, float py) {
   Local<MI> L;
   to_local(o, c, s, px, py, L);
+  // obstacle edge frames: unit direction, and A~_j's coordinates in it
+  float ux[MI], uy[MI], ca[MI], cb[MI];
+#pragma unroll
+  for (int j = 0; j < MI; ++j) {
+    ux[j] = L.vx[j] * o.il[j];
+    uy[j] = L.vy[j] * o.il[j];
+    ca[j] = fmaf(L.tax[j], ux[j], L.tay[j] * uy[j]);
+    cb[j] = fmaf(L.tax[j], L.nx[j], L.tay[j] * L.ny[j]);
+  }
 
-  // Sec. IV-B pools.
+  // Robot vertices against obstacle edges (d_v, Sec. IV-B), with the robot's
+  // interval on every obstacle axis (Sec. IV-C).
   float dv2 = __builtin_huge_valf(), de2 = __builtin_huge_valf();
+  float rlo[MI], rhi[MI];
+#pragma unroll
+  for (int j = 0; j < MI; ++j) { rlo[j] = __builtin_huge_valf(); rhi[j] = -__builtin_huge_valf(); }
 #pragma unroll
   for (int l = 0; l < MF; ++l) {
 #pragma unroll
-    for (int j = 0; j < MI; ++j)
-      dv2 = fminf(dv2, seg_d2(F.vx[l], F.vy[l], L.tax[j], L.tay[j], L.vx[j], L.vy[j], o.iv2[j]));
+    for (int j = 0; j < MI; ++j) {
+      const float q = fmaf(F.vx[l], L.nx[j], F.vy[l] * L.ny[j]);
+      rlo[j] = fminf(rlo[j], q);
+      rhi[j] = fmaxf(rhi[j], q);
+      const float a = fmaf(F.vx[l], ux[j], fmaf(F.vy[l], uy[j], -ca[j]));
+      dv2 = fminf(dv2, frame_d2(a, q - cb[j], o.len[j]));
+    }
   }
-  // Sec. IV-C axis intervals, accumulated vertex by vertex over V_obs.
+  // Obstacle vertices against robot edges (d_e), with the obstacle's
+  // interval on every axis, accumulated vertex by vertex over V_obs.
   float ra_lo[MF], ra_hi[MF];    // obstacle interval on robot axis n_l
   float oa_lo[MI], oa_hi[MI];    // obstacle interval on its own axis n'_j
 #pragma unroll
   for (int l = 0; l < MF; ++l) { ra_lo[l] = __builtin_huge_valf(); ra_hi[l] = -__builtin_huge_valf(); }
 #pragma unroll
   for (int j = 0; j < MI; ++j) { oa_lo[j] = __builtin_huge_valf(); oa_hi[j] = -__builtin_huge_valf(); }
-
   auto visit = [&](float wx, float wy) {
 #pragma unroll
     for (int l = 0; l < MF; ++l) {
-      de2 = fminf(de2, seg_d2(wx, wy, F.vx[l], F.vy[l], F.ex[l], F.ey[l], F.einv[l]));
       const float p = fmaf(wx, F.nx[l], wy * F.ny[l]);
       ra_lo[l] = fminf(ra_lo[l], p);
       ra_hi[l] = fmaxf(ra_hi[l], p);
+      const float a = fmaf(wx, F.ux[l], fmaf(wy, F.uy[l], -F.cu[l]));
+      de2 = fminf(de2, frame_d2(a, p - F.cn[l], F.len[l]));
     }
 #pragma unroll
     for (int j = 0; j < MI; ++j) {
@@ -231,14 +266,7 @@ __device__ __forceinline__ float obstacle_sd(const FpConst& F, const Obst<MI>& o
   }
 #pragma unroll
   for (int j = 0; j < MI; ++j) {
-    float rlo = __builtin_huge_valf(), rhi = -__builtin_huge_valf();
-#pragma unroll
-    for (int l = 0; l < MF; ++l) {
-      const float p = fmaf(F.vx[l], L.nx[j], F.vy[l] * L.ny[j]);
-      rlo = fminf(rlo, p);
-      rhi = fmaxf(rhi, p);
-    }
-    dl[MF + j] = fminf(oa_hi[j] - rlo, rhi - oa_lo[j]);
+    dl[MF + j] = fminf(oa_hi[j] - rlo[j], rhi[j] - oa_lo[j]);
     sep = sep || (dl[MF + j] < -F.eps_sat);
   }
 

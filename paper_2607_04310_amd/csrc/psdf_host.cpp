@@ -110,6 +110,11 @@ int prepare_footprint(const float* xy, int m, const psdf_params* params, FpConst
     f.ny[l] = (float)ny;
     f.pa[l] = (float)lo;
     f.pb[l] = (float)hi;
+    f.ux[l] = (float)(ex / len);
+    f.uy[l] = (float)(ey / len);
+    f.len[l] = (float)len;
+    f.cu[l] = (float)((vx[l] * ex + vy[l] * ey) / len);
+    f.cn[l] = (float)(vx[l] * nx + vy[l] * ny);
   }
   // certificate constants (see FpConst)
   double rmax = 0.0, max_ext = 0.0;
@@ -129,6 +134,8 @@ int prepare_footprint(const float* xy, int m, const psdf_params* params, FpConst
     f.einv[l] = f.einv[m - 1];
     f.nx[l] = f.nx[m - 1]; f.ny[l] = f.ny[m - 1];
     f.pa[l] = f.pa[m - 1]; f.pb[l] = f.pb[m - 1];
+    f.ux[l] = f.ux[m - 1]; f.uy[l] = f.uy[m - 1]; f.len[l] = f.len[m - 1];
+    f.cu[l] = f.cu[m - 1]; f.cn[l] = f.cn[m - 1];
   }
   return PSDF_OK;
 }

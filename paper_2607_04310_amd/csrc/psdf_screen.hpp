@@ -10,14 +10,17 @@
 // stage that fails the certificate is appended to a list that the fallback
 // kernel evaluates in full.
 //
-// Lower bound (world frame, pose origin p, footprint radius rmax about the
-// origin): for an obstacle whose boundary is a closed convex polygon not
-// containing p, dist(P0(x), P^i) >= dist(p, P^i) - rmax, and dist(p, P^i) is
-// the smallest point-segment distance from p to its edges; an open chain has
-// no interior.  LB_i = dist(p, P^i) - rmax - gamma (gamma absorbs FP32
-// rounding), -inf if p is inside or the obstacle is invalid.  Two convex
-// sets at distance r > tau_sep are separated by the axis test (the largest
-// axis gap is at least kappa r), so their sd is d_sep >= r >= LB_i.
+// Lower bounds (world frame, pose origin p, footprint radius rmax about the
+// origin; every footprint point is within rmax of p):
+//  * every obstacle: its bounding circle (c_i, r_i), computed once per call
+//    by circle_kernel, gives dist(P0(x), P^i) >= |p - c_i| - r_i - rmax;
+//  * pool members, tighter: for a closed convex polygon not containing p,
+//    dist(p, P^i) is the smallest point-segment distance from p to its
+//    edges (an open chain has no interior), so
+//    dist(P0(x), P^i) >= dist(p, P^i) - rmax.
+// Both subtract gamma to absorb FP32 rounding; an invalid obstacle gets -inf.
+// Two convex sets at distance r > tau_sep are separated by the axis test
+// (the largest axis gap is at least kappa r), so their sd is d_sep >= r >= LB.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,6 +36,7 @@ constexpr int kScreenMaxM = kScreenThreads * kScreenKeysPerThread;   // 16384
 constexpr int kPoolCap = 512;                                  // pool capacity (ties included)
 constexpr float kLbGamma = 1e-3f;
 
+
 struct ScreenArgs {
   const FpConst* fps;
   const BatchInst* insts;
@@ -45,6 +49,7 @@ struct ScreenArgs {
   const float* bx;
   const float* by;
   const int* off;
+  const float4* circ;      // bounding circles (circle_kernel)
   const float* theta;      // MLP parameters, or nullptr: rank by edge distance
   int pool;                // P
   int topk;                // K
@@ -59,10 +64,10 @@ struct ScreenArgs {
 __device__ __forceinline__ float obstacle_lb(float px, float py, const float* __restrict__ ax,
                                              const float* __restrict__ ay,
                                              const float* __restrict__ bx,
-                                             const float* __restrict__ by, int e0, int mi, int Eend,
-                                             float eps, float rmax) {
+                                             const float* __restrict__ by, int e0, int mi, int Ebeg,
+                                             int Eend, float eps, float rmax) {
   if (mi == 0) return __builtin_huge_valf();
-  if (mi < 0 || mi > kMaxObst || e0 < 0 || e0 > Eend - mi) return -__builtin_huge_valf();
+  if (mi < 0 || mi > kMaxObst || e0 < Ebeg || e0 > Eend - mi) return -__builtin_huge_valf();
   float d2 = __builtin_huge_valf();
   bool pos = true, neg = true, closed = mi >= 3, finite = true;
   for (int j = 0; j < mi; ++j) {
@@ -153,7 +158,7 @@ template <int MF, int MI>
 __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
   __shared__ int scan[kScreenThreads];
   __shared__ uint32_t red[kScreenThreads / 64];
-  __shared__ int pool_o[kPoolCap];        // pool obstacles (local index), increasing
+  __shared__ int pool_o[kPoolCap];        // pool obstacles (local index)
   __shared__ uint32_t pool_lb[kPoolCap];  // their orderable LB
   __shared__ float score[kPoolCap * MI];  // per pool edge slot (+inf for unused slots)
   __shared__ uint8_t cand[kPoolCap];
@@ -173,18 +178,21 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
   const int M = in.M, Eend = in.edge_off + in.E;
   const int* off = A.off + in.obst_off;
 
-  // ---- lower bounds, thread t owns obstacles [64 t, 64 t + 64)
+  // ---- bounding-circle lower bounds, thread t owns obstacles t + 256 q
   uint32_t k[kScreenKeysPerThread];
-  const int o_base = tid * kScreenKeysPerThread;
+  const float4* circ = A.circ + in.circ_off;
+  const float lb_off = F.rmax + kLbGamma;
 #pragma unroll
   for (int q = 0; q < kScreenKeysPerThread; ++q) {
-    const int o = o_base + q;
+    const int o = tid + kScreenThreads * q;
     uint32_t key = 0xffffffffu;
     if (o < M) {
-      const int a = off[o], b = off[o + 1];
-      const float lbv = obstacle_lb(px, py, A.ax, A.ay, A.bx, A.by, in.edge_off + a, b - a, Eend,
-                                    F.eps, F.rmax);
-      key = (b - a == 0) ? 0xffffffffu : orderable(pose_ok ? lbv : -__builtin_huge_valf());
+      const float4 c = circ[o];
+      if (c.x == c.x) {   // not an empty obstacle
+        const float dx = px - c.x, dy = py - c.y;
+        const float lbv = sqrtf(fmaf(dx, dx, dy * dy)) - c.z - lb_off;
+        key = orderable(pose_ok ? lbv : -__builtin_huge_valf());
+      }
     }
     k[q] = key;
   }
@@ -212,17 +220,31 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
 #pragma unroll
     for (int q = 0; q < kScreenKeysPerThread; ++q)
       if (k[q] <= T && k[q] != 0xffffffffu) {
-        pool_o[at] = o_base + q;
+        pool_o[at] = tid + kScreenThreads * q;
         pool_lb[at] = k[q];
         ++at;
       }
   }
-  // smallest LB key outside the pool
+  // smallest circle bound outside the pool
   uint32_t rest = 0xffffffffu;
 #pragma unroll
   for (int q = 0; q < kScreenKeysPerThread; ++q)
     if (k[q] > T) rest = min(rest, k[q]);
   rest = block_min_u32(rest, red);
+  // pool members: the tighter point-to-polygon bound (the larger of two
+  // valid lower bounds is a lower bound); -inf (pose inside, invalid) is
+  // kept as is, which makes the obstacle a candidate
+  if (!overflow) {
+    for (int q = tid; q < pool_n; q += kScreenThreads) {
+      const int o = pool_o[q];
+      const int a = off[o], b = off[o + 1];
+      const float lbv = obstacle_lb(px, py, A.ax, A.ay, A.bx, A.by, in.edge_off + a, b - a,
+                                    in.edge_off, Eend, F.eps, F.rmax);
+      const uint32_t kk = orderable(pose_ok ? lbv : -__builtin_huge_valf());
+      const uint32_t ninf = orderable(-__builtin_huge_valf());
+      pool_lb[q] = kk <= ninf ? kk : max(pool_lb[q], kk);
+    }
+  }
   __syncthreads();
 
   uint64_t keyK = kEmptyKey;

@@ -24,6 +24,41 @@ sys.path.insert(0, ROOT)
 METRIC = "stage×edge PSDF+grad evals/s (plain vs screened, exact) and % FP32 VALU peak"
 PEAK_FP32_TFLOPS = 157.3
 
+# HBM bytes per launch of the dominant kernel, from the FETCH_SIZE / WRITE_SIZE
+# counter runs recorded in this file (each scaled by the same counter's reading
+# for a copy kernel of known size), valid only while the kernel's sources
+# hash to the value recorded beside it.
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "main_kernel_c2_hbm_counters.md")
+KERNEL_SOURCES = [os.path.join("paper_2607_04310_amd", "csrc", f) for f in (
+    "psdf_device.hpp", "psdf_kernels.hpp", "psdf_winner.hpp", "psdf_inst_mf6.hip",
+    "psdf_plain.hip", "psdf_host.cpp", "psdf_host.hpp")] + [os.path.join("paper_2607_04310_amd",
+                                                                         "build.py")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic():
+    """(bytes per launch, note) from the counter summary, or (None, why not)."""
+    import re
+    try:
+        text = open(COUNTER_SUMMARY).read()
+    except OSError:
+        return None, "no counter summary"
+    mh = re.search(r"source_sha256:\s*([0-9a-f]+)", text)
+    mb = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not mh or not mb:
+        return None, "counter summary incomplete"
+    if mh.group(1) != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    return float(mb.group(1)), "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -103,6 +138,38 @@ def extras(torch, api, flops, inputs):
                            loop_evals_per_s=pairs4 / (t_loop * 1e-3),
                            batch_tflops=f4 / (t_batch * 1e-3) / 1e12, shape=b.info())
     b.close()
+
+    # c2 at throughput size: 256 independent c2 draws in one batch launch
+    log("c2x256: building")
+    c2b = inputs.c2_batch(256)
+    pairs2 = sum(i.N * i.E for i in c2b)
+    b = api.Batch(c2b, graph=True, autotune=True)
+    b.autotune()
+    t = _timeit(torch, b.run, 20, 3)
+    f2 = sum(flops.flops_instance(len(i.footprint), i.N, i.edges, i.obst_off) for i in c2b)
+    out["c2x256_batch"] = dict(pairs=pairs2, ms=t, evals_per_s=pairs2 / (t * 1e-3),
+                               tflops=f2 / (t * 1e-3) / 1e12, shape=b.info())
+    log(f"c2x256: {t:.3f} ms, {pairs2 / (t * 1e-3):.3e} evals/s")
+    b.close()
+    del c2b
+
+    # one stage pose against growing edge sets: every edge is read once per
+    # call, the HBM end of the workload
+    sweep = []
+    for rects in (1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22):
+        inst = inputs.single_pose(rects)
+        es = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar, device="cuda")
+        poses = torch.tensor(inst.poses, device="cuda")
+        ws = api.workspace(1, inst.M, "cuda")
+        o = api.psdf_grad(inst.footprint, poses, es, ws=ws)
+        t = _timeit(torch, lambda: api.psdf_grad(inst.footprint, poses, es, out=o, ws=ws), 20, 3)
+        nbytes = flops.bytes_instance(1, inst.E, inst.M)
+        fl = flops.flops_instance(len(inst.footprint), 1, inst.edges, inst.obst_off)
+        sweep.append(dict(E=inst.E, ms=t, evals_per_s=inst.E / (t * 1e-3),
+                          gbytes_per_s=nbytes / (t * 1e-3) / 1e9, tflops=fl / (t * 1e-3) / 1e12))
+        log(f"single pose E={inst.E}: {t * 1e3:.1f} us, {nbytes / (t * 1e-3) / 1e9:.0f} GB/s")
+        del es, poses, ws, o
+    out["single_pose_sweep"] = sweep
 
     # screener trained on held-out instances (different seeds from the test batch)
     log("c5: training set")
@@ -193,6 +260,7 @@ def main():
 
     flop = flops.flops_instance(len(inst.footprint), N, inst.edges, inst.obst_off)
     achieved = flop / (kernel_ms * 1e-3) / 1e12
+    traffic, traffic_note = counted_traffic()
     value = N * E / (ms_step * 1e-3)
     res = dict(
         metric=METRIC, value=value, unit="stage×edge evals/s", n_gpus=1, steps=args.steps,
@@ -202,9 +270,11 @@ def main():
                              "(4096 rectangles, 40x40 m), psdf_grad (value+winner+gradient)",
                     N=N, E=E, M=M, m=len(inst.footprint), eta=params.eta),
         roofline=dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                      frac=achieved / PEAK_FP32_TFLOPS, traffic=None,
+                      frac=achieved / PEAK_FP32_TFLOPS, traffic=traffic,
+                      traffic_note=traffic_note,
+                      algorithmic_bytes=flops.bytes_instance(N, E, M),
                       kernel="main_kernel (per-stage minimum)", kernel_us=kernel_ms * 1e3,
-                      flop_per_launch=flop),
+                      flop_per_launch=flop, source_sha256=kernel_source_hash()),
         wall_s=wall,
     )
     log(f"c2: {value:.3e} evals/s, {ms_step * 1e3:.2f} us per call")

@@ -131,6 +131,23 @@ int psdf_grad(const float* footprint, int32_t m, const float* poses, int32_t N,
               int32_t* obst, float* grad, uint64_t* keys, void* ws, size_t ws_bytes,
               hipStream_t stream);
 
+/* psdf_constraints - the stage-wise parameters of the linearised safety
+ * constraint h(x) = phi(x) - d_min >= 0 that an SQP step hands to its QP
+ * (Sec. V: first-order expansion of h about the nominal poses, with
+ * J_g = -grad_x h, so that J_g dx <= h; Alg. 1, the export step).
+ * hj: device float32[N][4], row s = (phi_s - d_min, -dphi/dx, -dphi/dy,
+ * -dphi/dtheta), overwritten.  keys: device uint64[N] (the winners, for a
+ * later psdf_bwd).  ws: as for psdf_grad.  hj_host (may be NULL): host
+ * float32[N][4] that receives a copy of hj, enqueued on `stream` after the
+ * kernels; it should be pinned (hipHostMalloc) for the copy to be
+ * asynchronous, and it holds the data once the stream has synchronised.
+ * d_min must be finite (PSDF_EINVAL).  An empty edge set gives
+ * (+inf, -0, -0, -0); a non-finite pose a row of NaN. */
+int psdf_constraints(const float* footprint, int32_t m, const float* poses, int32_t N,
+                     const psdf_edges* edges, const psdf_params* params, float d_min, float* hj,
+                     float* hj_host, uint64_t* keys, void* ws, size_t ws_bytes,
+                     hipStream_t stream);
+
 /* psdf_bwd - vector-Jacobian product of phi with respect to the poses:
  * gpose[s] = gout[s] * dphi_s/d(x, y, theta) (Alg. 1, PSDF_Backward), from the
  * winners that a previous psdf_eval/psdf_grad left in keys (device
@@ -140,6 +157,18 @@ int psdf_grad(const float* footprint, int32_t m, const float* poses, int32_t N,
 int psdf_bwd(const float* footprint, int32_t m, const float* poses, int32_t N,
              const psdf_edges* edges, const psdf_params* params, const uint64_t* keys,
              const float* gout, float* gpose, hipStream_t stream);
+
+/* psdf_sd_matrix - every obstacle's signed distance at every stage, before
+ * the minimum over obstacles (Sec. IV-D: sd^i, whose minimum is phi), for
+ * callers that constrain several obstacles per stage.  sd: device
+ * float32[N][M], stage-major (sd[s * M + i]), overwritten.  An empty
+ * obstacle gives +inf, a non-finite pose or an invalid obstacle NaN.  The
+ * row minimum and its lowest index equal psdf_eval's d and obst bit for bit.
+ * Needs no workspace; the main plain-path launch grid bounds apply
+ * (PSDF_ETOOBIG beyond 262140 stages). */
+int psdf_sd_matrix(const float* footprint, int32_t m, const float* poses, int32_t N,
+                   const psdf_edges* edges, const psdf_params* params, float* sd,
+                   hipStream_t stream);
 
 /* psdf_encode_padded - EncodeEdges of Alg. 1 for the paper's padded tensors
  * (Sec. IV-A): A, B device float32[Mbar][mbar][2] and the validity mask S

@@ -82,6 +82,11 @@ _SIGS = {
     "psdf_batch_plan_info": (ctypes.c_int, [_VP] + [ctypes.POINTER(_I32)] * 5),
     "psdf_bwd": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
                                 ctypes.POINTER(PsdfParams), _VP, _VP, _VP, _VP]),
+    "psdf_constraints": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
+                                        ctypes.POINTER(PsdfParams), ctypes.c_float, _VP, _VP, _VP,
+                                        _VP, ctypes.c_size_t, _VP]),
+    "psdf_sd_matrix": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
+                                      ctypes.POINTER(PsdfParams), _VP, _VP]),
     "psdf_encode_ws_bytes": (ctypes.c_size_t, [_I32]),
     "psdf_timer_enable": (ctypes.c_int, [_I32]),
     "psdf_timer_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),

@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes
 import math
 from dataclasses import dataclass
+from types import SimpleNamespace
 
 import numpy as np
 import torch
@@ -138,6 +139,45 @@ def psdf_bwd(footprint, poses, edges: EdgeSet, keys, gout, params: Params | None
                                    ctypes.byref(pc), keys.data_ptr(), gout.data_ptr(),
                                    gpose.data_ptr(), _lib.stream_handle()))
     return gpose
+
+
+def psdf_constraints(footprint, poses, edges: EdgeSet, d_min, params: Params | None = None,
+                     host=None, ws=None):
+    """Linearised safety-constraint parameters per stage: (N, 4) rows
+    (phi - d_min, -dphi/dx, -dphi/dy, -dphi/dtheta) on the device, plus the
+    winner keys; with ``host`` (a pinned CPU float32 (N, 4) tensor) the rows
+    are also copied there on the stream."""
+    params = params or Params()
+    poses = _poses(poses)
+    N = poses.shape[0]
+    dev = poses.device
+    hj = torch.empty((N, 4), dtype=torch.float32, device=dev)
+    keys = torch.empty(N, dtype=torch.int64, device=dev)
+    ws = workspace(N, edges.M, dev) if ws is None else ws
+    if host is not None and (host.dtype != torch.float32 or tuple(host.shape) != (N, 4)
+                             or not host.is_contiguous() or host.is_cuda):
+        raise ValueError("host must be a contiguous CPU float32 tensor of shape (N, 4)")
+    fp, fpp, m = _fp(footprint)
+    ec, pc = edges.c(), params.c()
+    _lib.check(_lib.lib().psdf_constraints(fpp, m, poses.data_ptr(), N, ctypes.byref(ec),
+                                           ctypes.byref(pc), float(d_min), hj.data_ptr(),
+                                           None if host is None else host.data_ptr(),
+                                           keys.data_ptr(), ws.data_ptr(), ws.numel(),
+                                           _lib.stream_handle()))
+    return hj, keys
+
+
+def psdf_sd_matrix(footprint, poses, edges: EdgeSet, params: Params | None = None, out=None):
+    """sd[s, i] of every obstacle i at every stage s, before the minimum."""
+    params = params or Params()
+    poses = _poses(poses)
+    N = poses.shape[0]
+    sd = torch.empty((N, edges.M), dtype=torch.float32, device=poses.device) if out is None else out
+    fp, fpp, m = _fp(footprint)
+    ec, pc = edges.c(), params.c()
+    _lib.check(_lib.lib().psdf_sd_matrix(fpp, m, poses.data_ptr(), N, ctypes.byref(ec),
+                                         ctypes.byref(pc), sd.data_ptr(), _lib.stream_handle()))
+    return sd
 
 
 def psdf_encode_padded(A, B, S):
@@ -297,6 +337,20 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def horizon_batch(footprint, poses, stage_edges, stage_offsets, **kw):
+    """Per-stage (time-varying) edge sets: stage s of a horizon is evaluated
+    against its own edge set (stage_edges[s] (E_s, 4), stage_offsets[s]
+    (M_s + 1,)).  Each stage is a one-stage instance of one batch, so the
+    whole horizon is still one persistent launch; outputs are in stage order
+    and edge / obstacle indices are local to the stage's set."""
+    poses = np.asarray(poses, dtype=np.float32).reshape(-1, 3)
+    if not (len(poses) == len(stage_edges) == len(stage_offsets)):
+        raise ValueError("one edge set and one offset array per stage")
+    insts = [SimpleNamespace(footprint=footprint, poses=poses[s:s + 1], edges=stage_edges[s],
+                             obst_off=stage_offsets[s]) for s in range(len(poses))]
+    return Batch(insts, **kw)
 
 
 def set_launch_shape(blk=0, sb=0):

@@ -46,7 +46,8 @@ hipError_t launch_plain(const FpConst& F, const float* poses, int N, const psdf_
                         uint64_t* partial, const LaunchShape& ls, hipStream_t st);
 hipError_t launch_epilogue(const FpConst& F, const float* poses, int N, const psdf_edges& e,
                            const uint64_t* partial, int gx, uint64_t* keys, const float* gout,
-                           int mode, float* d, int* edge, int* obst, float* grad, hipStream_t st);
+                           int mode, float dmin, float* d, int* edge, int* obst, float* grad,
+                           float* hj, hipStream_t st);
 int partial_columns(int M, const LaunchShape& ls);
 
 }  // namespace psdf

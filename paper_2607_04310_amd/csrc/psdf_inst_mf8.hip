@@ -1,7 +1,9 @@
-// Explicit instantiation of the per-stage minimum kernel for 8 footprint slots.
+// Explicit instantiation of the per-stage minimum and sd-matrix kernels for 8 footprint slots.
 #include "psdf_kernels.hpp"
 
 namespace psdf {
 template hipError_t launch_main_mf<8>(int, const LaunchShape&, const FpConst&, const float*, int,
                                        const psdf_edges&, uint64_t*, hipStream_t);
+template hipError_t launch_sdmat_mf<8>(int, const FpConst&, const float*, int,
+                                        const psdf_edges&, float*, hipStream_t);
 }  // namespace psdf

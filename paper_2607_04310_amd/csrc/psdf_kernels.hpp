@@ -106,10 +106,67 @@ hipError_t launch_main_mf(int mi_class, const LaunchShape& ls, const FpConst& F,
   return launch_main_t<MF, 16>(ls, F, poses, N, e, partial, st);
 }
 
+// Every obstacle's sd per stage, before the minimum over obstacles: lane <->
+// obstacle as in main_kernel, sd[s][i] (stage-major, written coalesced along
+// obstacles); +inf for an empty obstacle, NaN for a non-finite pose or an
+// invalid obstacle.  Same obstacle_sd as main_kernel, so the row minimum is
+// the per-stage minimum bit for bit.
+template <int MF, int MI>
+__global__ __launch_bounds__(256) void sdmat_kernel(FpConst F, const float* __restrict__ poses,
+                                                     int N, int SB, const float* __restrict__ ax,
+                                                     const float* __restrict__ ay,
+                                                     const float* __restrict__ bx,
+                                                     const float* __restrict__ by,
+                                                     const int* __restrict__ off, int E, int M,
+                                                     float* __restrict__ sd) {
+  __shared__ float4 st[kMaxStageBlock];
+  const int s0 = blockIdx.y * SB;
+  const int ns = min(SB, N - s0);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const bool active = i < M;
+  int e0 = 0, mi = 0;
+  if (active) { e0 = off[i]; mi = off[i + 1] - e0; }
+  for (int t = threadIdx.x; t < ns; t += 256) {
+    const float* p = poses + 3 * (s0 + t);
+    float sn, cs;
+    sincosf(p[2], &sn, &cs);
+    st[t] = make_float4(cs, sn, p[0], p[1]);
+  }
+  __syncthreads();
+  if (!active) return;
+  Obst<MI> o;
+  load_obstacle<MI>(o, ax, ay, bx, by, e0, mi, E, F.eps);
+  for (int t = 0; t < ns; ++t) {
+    const float4 q = st[t];
+    const bool pose_ok = isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && isfinite(q.w);
+    float v = __builtin_huge_valf();
+    if (mi != 0) v = pose_ok ? obstacle_sd<MF, MI>(F, o, q.x, q.y, q.z, q.w) : __builtin_nanf("");
+    sd[(size_t)(s0 + t) * M + i] = v;
+  }
+}
+
+constexpr int kSdmatStageBlock = 4;
+
+template <int MF>
+hipError_t launch_sdmat_mf(int mi_class, const FpConst& F, const float* poses, int N,
+                           const psdf_edges& e, float* sd, hipStream_t st) {
+  dim3 grid((e.M + 255) / 256, (N + kSdmatStageBlock - 1) / kSdmatStageBlock);
+#define PSDF_SDMAT(MI)                                                                        \
+  sdmat_kernel<MF, MI><<<grid, 256, 0, st>>>(F, poses, N, kSdmatStageBlock, e.ax, e.ay, e.bx, \
+                                             e.by, e.obst_off, e.E, e.M, sd)
+  if (mi_class == 4) PSDF_SDMAT(4);
+  else if (mi_class == 8) PSDF_SDMAT(8);
+  else PSDF_SDMAT(16);
+#undef PSDF_SDMAT
+  return hipGetLastError();
+}
+
 #define PSDF_EXTERN_MF(MF)                                                                  \
   extern template hipError_t launch_main_mf<MF>(int, const LaunchShape&, const FpConst&,    \
                                                 const float*, int, const psdf_edges&,       \
-                                                uint64_t*, hipStream_t);
+                                                uint64_t*, hipStream_t);            \
+  extern template hipError_t launch_sdmat_mf<MF>(int, const FpConst&, const float*, int,    \
+                                                 const psdf_edges&, float*, hipStream_t);
 PSDF_EXTERN_MF(3)
 PSDF_EXTERN_MF(4)
 PSDF_EXTERN_MF(5)

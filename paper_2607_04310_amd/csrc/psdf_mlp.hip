@@ -205,17 +205,38 @@ __global__ __launch_bounds__(64 * kMlpWaves) void mlp_grad_kernel(const float* _
   }
 }
 
-// Sum the per-wave partial rows (in wave order) into grad[kGradRow]; with
-// lr > 0 also apply one Adam step to theta (m, v moments; step counts from 1).
-// grad[kMlpParams] receives the mean squared error.
-__global__ void mlp_reduce_adam_kernel(float* __restrict__ th, float* __restrict__ m,
-                                       float* __restrict__ v, const float* __restrict__ part,
-                                       int waves, int B, int step, float lr,
-                                       float* __restrict__ grad, float* __restrict__ loss) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= kGradRow) return;
+// Sum the per-wave partial rows into grad[kGradRow]; with lr > 0 also apply
+// one Adam step to theta (m, v moments; step counts from 1).
+// grad[kMlpParams] receives the mean squared error.  A work-group owns 64
+// consecutive columns; wave q adds rows q, q + 4, q + 8, ... in that order
+// (four rows in flight per lane) and wave 0 adds the four wave sums in wave
+// order, so the result does not depend on timing.
+constexpr int kReduceWaves = 4;
+__global__ __launch_bounds__(64 * kReduceWaves) void mlp_reduce_adam_kernel(
+    float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
+    const float* __restrict__ part, int waves, int B, int step, float lr,
+    float* __restrict__ grad, float* __restrict__ loss) {
+  __shared__ float red[kReduceWaves][64];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int k = 0; k < waves; ++k) s += part[(size_t)k * kGradRow + p];
+  if (p < kGradRow) {
+    const float* col = part + p;
+    constexpr int R = kReduceWaves;
+    int k = q;
+    for (; k + 3 * R < waves; k += 4 * R) {
+      const float a0 = col[(size_t)k * kGradRow], a1 = col[(size_t)(k + R) * kGradRow];
+      const float a2 = col[(size_t)(k + 2 * R) * kGradRow], a3 = col[(size_t)(k + 3 * R) * kGradRow];
+      s += a0; s += a1; s += a2; s += a3;
+    }
+    for (; k < waves; k += R) s += col[(size_t)k * kGradRow];
+  }
+  red[q][lane] = s;
+  __syncthreads();
+  if (q != 0 || p >= kGradRow) return;
+  s = red[0][lane];
+#pragma unroll
+  for (int w = 1; w < kReduceWaves; ++w) s += red[w][lane];
   if (p == kMlpParams) {
     if (grad) grad[p] = s / (float)B;
     if (loss) *loss = s / (float)B;
@@ -340,8 +361,8 @@ static int mlp_step(float* theta, float* m, float* v, int32_t step, float lr, co
   mlp_grad_kernel<<<blocks, 64 * kMlpWaves, 0, stream>>>(theta, X, T, B, gpw, part);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return hip_status(err);
-  mlp_reduce_adam_kernel<<<(kGradRow + 255) / 256, 256, 0, stream>>>(theta, m, v, part, all, B,
-                                                                    step, lr, grad, loss);
+  mlp_reduce_adam_kernel<<<(kGradRow + 63) / 64, 64 * kReduceWaves, 0, stream>>>(
+      theta, m, v, part, all, B, step, lr, grad, loss);
   return hip_status(hipGetLastError());
 }
 

@@ -19,40 +19,62 @@ namespace psdf {
 constexpr int kEpiWaves = 4;   // stages per epilogue work-group
 
 // mode 0: value, winner and edge; 1: plus gradient; 2: bwd (gradient scaled
-// by gout[s], written to grad only; keys are read, not reduced).
+// by gout[s], written to grad only; keys are read, not reduced).  In modes 0
+// and 1 each of d / edge / obst, grad and hj may be null; hj[s] receives the
+// linearised safety constraint (phi - dmin, -dphi/dx, -dphi/dy, -dphi/dtheta)
+// (mode 1 only).
 __global__ __launch_bounds__(64 * kEpiWaves) void epilogue_kernel(
     FpConst F, const float* __restrict__ poses, int N, const float* __restrict__ ax,
     const float* __restrict__ ay, const float* __restrict__ bx, const float* __restrict__ by,
     const int* __restrict__ off, int E, int M, const uint64_t* __restrict__ partial, int gx,
-    uint64_t* __restrict__ keys, const float* __restrict__ gout, int mode, float* __restrict__ d,
-    int* __restrict__ edge, int* __restrict__ obst, float* __restrict__ grad) {
+    uint64_t* __restrict__ keys, const float* __restrict__ gout, int mode, float dmin,
+    float* __restrict__ d, int* __restrict__ edge, int* __restrict__ obst,
+    float* __restrict__ grad, float* __restrict__ hj) {
   __shared__ FpLds fl[kEpiWaves];
   __shared__ WinnerLds wl[kEpiWaves];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int s = blockIdx.x * kEpiWaves + w;
   if (s >= N) return;
-  // Independent loads first: the pose and its rotation, then the partials.
+  // Every independent load in flight at once: the pose, the partial keys and
+  // their aux words (or the stored key), the footprint constants.
   const float* p = poses + 3 * s;
-  const float px = p[0], py = p[1];
-  float sn, cs;
-  sincosf(p[2], &sn, &cs);
-  stage_footprint(fl[w], F);
-
-  uint64_t key;
-  int e0 = 0, mi = 0;
-  bool have_aux = false;
+  const float px = p[0], py = p[1], th = p[2];
+  uint64_t key = kEmptyKey, a = 0;
+  float scale = 1.0f;
+  // the winning column's aux word carries the obstacle's edge range
+  const uint64_t* prow = partial + (size_t)s * gx;
+  const uint64_t* arow = partial + (size_t)N * gx + (size_t)s * gx;
   if (mode == 2) {
     key = keys[s];
-  } else {
-    // reduce the work-groups' partial keys; the winning column's aux word
-    // carries the obstacle's edge range
-    const uint64_t* aux = partial + (size_t)N * gx;
-    key = kEmptyKey;
-    uint64_t a = 0;
-    for (int j = lane; j < gx; j += 64) {
-      const uint64_t k = partial[(size_t)s * gx + j];
-      if (k < key) { key = k; a = aux[(size_t)s * gx + j]; }
+    scale = gout[s];
+  } else if (lane < gx) {
+    key = prow[lane];
+    a = arow[lane];
+  }
+  stage_footprint(fl[w], F);
+  if (mode != 2) {
+    // keys are unique (they carry the obstacle index), so the scan order is
+    // free: four columns per lane in flight
+    int j = lane + 64;
+    for (; j + 192 < gx; j += 256) {
+      uint64_t k[4], x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) { k[u] = prow[j + 64 * u]; x[u] = arow[j + 64 * u]; }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k[u] < key) { key = k[u]; a = x[u]; }
     }
+    for (; j < gx; j += 64) {
+      const uint64_t k = prow[j], x = arow[j];
+      if (k < key) { key = k; a = x; }
+    }
+  }
+  float sn, cs;
+  sincosf(th, &sn, &cs);
+
+  int e0 = 0, mi = 0;
+  bool have_aux = false;
+  if (mode != 2) {
     const uint64_t kmin = wave_min_u64(key);
     const uint64_t hit = __ballot(key == kmin);
     const int first = __ffsll((unsigned long long)hit) - 1;
@@ -90,19 +112,26 @@ __global__ __launch_bounds__(64 * kEpiWaves) void epilogue_kernel(
   }
   if (lane != 0) return;
   if (mode == 2) {
-    const float sc = gout[s];
-    grad[3 * s + 0] = g[0] * sc;
-    grad[3 * s + 1] = g[1] * sc;
-    grad[3 * s + 2] = g[2] * sc;
+    grad[3 * s + 0] = g[0] * scale;
+    grad[3 * s + 1] = g[1] * scale;
+    grad[3 * s + 2] = g[2] * scale;
     return;
   }
-  d[s] = dv;
-  edge[s] = ev;
-  obst[s] = ov;
-  if (mode == 1) {
+  if (d) {
+    d[s] = dv;
+    edge[s] = ev;
+    obst[s] = ov;
+  }
+  if (mode == 1 && grad) {
     grad[3 * s + 0] = g[0];
     grad[3 * s + 1] = g[1];
     grad[3 * s + 2] = g[2];
+  }
+  if (mode == 1 && hj) {
+    hj[4 * s + 0] = dv - dmin;
+    hj[4 * s + 1] = -g[0];
+    hj[4 * s + 2] = -g[1];
+    hj[4 * s + 3] = -g[2];
   }
 }
 
@@ -134,11 +163,12 @@ hipError_t launch_plain(const FpConst& F, const float* poses, int N, const psdf_
 
 hipError_t launch_epilogue(const FpConst& F, const float* poses, int N, const psdf_edges& e,
                            const uint64_t* partial, int gx, uint64_t* keys, const float* gout,
-                           int mode, float* d, int* edge, int* obst, float* grad, hipStream_t st) {
+                           int mode, float dmin, float* d, int* edge, int* obst, float* grad,
+                           float* hj, hipStream_t st) {
   const int blocks = (N + kEpiWaves - 1) / kEpiWaves;
   epilogue_kernel<<<blocks, 64 * kEpiWaves, 0, st>>>(F, poses, N, e.ax, e.ay, e.bx, e.by,
                                                      e.obst_off, e.E, e.M, partial, gx, keys,
-                                                     gout, mode, d, edge, obst, grad);
+                                                     gout, mode, dmin, d, edge, obst, grad, hj);
   return hipGetLastError();
 }
 
@@ -243,7 +273,7 @@ static int plain_run(const float* footprint, int32_t m, const float* poses, int3
   hipError_t err = launch_plain(F, poses, N, e, partial, ls, stream);
   if (err == hipSuccess)
     err = launch_epilogue(F, poses, N, e, partial, e.M > 0 ? partial_columns(e.M, ls) : 0, keys,
-                          nullptr, mode, d, edge, obst, grad, stream);
+                          nullptr, mode, 0.0f, d, edge, obst, grad, nullptr, stream);
   return hip_status(err);
 }
 
@@ -262,6 +292,32 @@ int psdf_grad(const float* footprint, int32_t m, const float* poses, int32_t N,
                    ws_bytes, 1, stream);
 }
 
+int psdf_constraints(const float* footprint, int32_t m, const float* poses, int32_t N,
+                     const psdf_edges* edges, const psdf_params* params, float d_min, float* hj,
+                     float* hj_host, uint64_t* keys, void* ws, size_t ws_bytes,
+                     hipStream_t stream) {
+  clear_error();
+  FpConst F;
+  psdf_edges e;
+  int rc = plain_common(footprint, m, poses, N, edges, params, F, e);
+  if (rc) return rc;
+  if (N == 0) return PSDF_OK;
+  if (!hj || !keys) return set_error(PSDF_EINVAL, "hj or keys is NULL");
+  if (!std::isfinite(d_min)) return set_error(PSDF_EINVAL, "d_min is not finite");
+  const size_t need = psdf_workspace_bytes(N, e.M);
+  if (need > 0 && (!ws || ws_bytes < need))
+    return set_error(PSDF_EWS, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  const LaunchShape ls = tuned_shape(F.m, e.mbar, N, e.M);
+  uint64_t* partial = static_cast<uint64_t*>(ws);
+  hipError_t err = launch_plain(F, poses, N, e, partial, ls, stream);
+  if (err == hipSuccess)
+    err = launch_epilogue(F, poses, N, e, partial, e.M > 0 ? partial_columns(e.M, ls) : 0, keys,
+                          nullptr, 1, d_min, nullptr, nullptr, nullptr, nullptr, hj, stream);
+  if (err == hipSuccess && hj_host)
+    err = hipMemcpyAsync(hj_host, hj, (size_t)N * 4 * sizeof(float), hipMemcpyDeviceToHost, stream);
+  return hip_status(err);
+}
+
 int psdf_bwd(const float* footprint, int32_t m, const float* poses, int32_t N,
              const psdf_edges* edges, const psdf_params* params, const uint64_t* keys,
              const float* gout, float* gpose, hipStream_t stream) {
@@ -273,7 +329,22 @@ int psdf_bwd(const float* footprint, int32_t m, const float* poses, int32_t N,
   if (N == 0) return PSDF_OK;
   if (!keys || !gout || !gpose) return set_error(PSDF_EINVAL, "keys, gout or gpose is NULL");
   return hip_status(launch_epilogue(F, poses, N, e, nullptr, 0, const_cast<uint64_t*>(keys), gout,
-                                    2, nullptr, nullptr, nullptr, gpose, stream));
+                                    2, 0.0f, nullptr, nullptr, nullptr, gpose, nullptr, stream));
+}
+
+int psdf_sd_matrix(const float* footprint, int32_t m, const float* poses, int32_t N,
+                   const psdf_edges* edges, const psdf_params* params, float* sd,
+                   hipStream_t stream) {
+  clear_error();
+  FpConst F;
+  psdf_edges e;
+  int rc = plain_common(footprint, m, poses, N, edges, params, F, e);
+  if (rc) return rc;
+  if (N == 0 || e.M == 0) return PSDF_OK;
+  if (!sd) return set_error(PSDF_EINVAL, "sd is NULL");
+  if ((N + kSdmatStageBlock - 1) / kSdmatStageBlock > 65535)
+    return set_error(PSDF_ETOOBIG, "N = %d; at most %d stages", N, 65535 * kSdmatStageBlock);
+  return hip_status(PSDF_BY_MF(launch_sdmat_mf, obst_class(e.mbar), F, poses, N, e, sd, stream));
 }
 
 size_t psdf_encode_ws_bytes(int32_t Mbar) { return Mbar > 0 ? (size_t)Mbar * sizeof(int) : 0; }

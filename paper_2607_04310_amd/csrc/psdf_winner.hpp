@@ -68,16 +68,15 @@ __device__ __forceinline__ float wave_sum(float x) {
   return x;
 }
 
-// Copy the footprint constants into LDS (static indices only).
+// Copy the footprint constants into LDS, lane l <-> slot l: one vector load
+// per array.  F must be addressable memory (global memory or the kernel
+// argument segment), not a register copy.
 __device__ __forceinline__ void stage_footprint(FpLds& L, const FpConst& F) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int l = 0; l < kMaxFp; ++l) {
-    if (lane == l) {
-      L.vx[l] = F.vx[l]; L.vy[l] = F.vy[l]; L.ex[l] = F.ex[l]; L.ey[l] = F.ey[l];
-      L.einv[l] = F.einv[l]; L.nx[l] = F.nx[l]; L.ny[l] = F.ny[l];
-      L.pa[l] = F.pa[l]; L.pb[l] = F.pb[l];
-    }
+  const int l = threadIdx.x & 63;
+  if (l < kMaxFp) {
+    L.vx[l] = F.vx[l]; L.vy[l] = F.vy[l]; L.ex[l] = F.ex[l]; L.ey[l] = F.ey[l];
+    L.einv[l] = F.einv[l]; L.nx[l] = F.nx[l]; L.ny[l] = F.ny[l];
+    L.pa[l] = F.pa[l]; L.pb[l] = F.pb[l];
   }
 }
 

@@ -175,6 +175,45 @@ def c3(seed_instance: int = 0) -> Instance:
     return inst
 
 
+def c2_batch(n_instances: int = 256):
+    """c2 at throughput size: n independent c2 draws (seeds 0..n-1), one batch."""
+    return [c2(k) for k in range(n_instances)]
+
+
+def single_pose(n_rects: int, seed: int = 0) -> Instance:
+    """One stage pose at the centre of n_rects c2-style rectangles spread at c2's
+    density (4096 per 40 x 40 m): the edge-streaming end of the workload
+    (every edge is read once per call)."""
+    rng = rng_for(7, seed)
+    fp = hexagon_footprint(rng_for(2, 0))
+    side = 40.0 * float(np.sqrt(n_rects / 4096.0))
+    edges = random_rects(rng, n_rects, 0.1, 0.8, -side / 2, side / 2)
+    poses = np.array([[0.0, 0.0, float(rng.uniform(-np.pi, np.pi))]], dtype=np.float32)
+    return Instance(fp, poses, edges, csr_offsets([4] * n_rects), 4,
+                    dict(workload="single_pose", rects=n_rects))
+
+
+def moving_obstacles(seed: int = 0, N: int = 30, R: int = 200, dt: float = 0.1):
+    """A horizon whose edge set changes per stage: R rectangles moving at
+    constant velocities (|v| <= 1 m/s) seen at t = s * dt for stage s, and a
+    c2-style path of N poses through them.  Returns (footprint, poses,
+    [edges of stage s], [offsets of stage s])."""
+    rng = rng_for(8, seed)
+    fp = hexagon_footprint(rng)
+    poses = path_poses(rng, N, -3.0, 3.0)
+    centres = rng.uniform(-6.0, 6.0, size=(R, 2))
+    sides = rng.uniform(0.1, 0.8, size=(R, 2))
+    angles = rng.uniform(-np.pi, np.pi, size=R)
+    vel = rng.uniform(-0.7, 0.7, size=(R, 2))
+    spin = rng.uniform(-0.5, 0.5, size=R)
+    stage_edges, stage_off = [], []
+    for s in range(N):
+        t = s * dt
+        stage_edges.append(rect_edges(centres + t * vel, sides, angles + t * spin))
+        stage_off.append(csr_offsets([4] * R))
+    return fp, poses, stage_edges, stage_off
+
+
 def c4_instance(k: int) -> Instance:
     rng = rng_for(4, k)
     m = int(rng.integers(3, 9))

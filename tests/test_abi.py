@@ -108,3 +108,20 @@ def test_launch_shape_override_validation():
 def test_encode_workspace_query():
     assert _lib.lib().psdf_encode_ws_bytes(0) == 0
     assert _lib.lib().psdf_encode_ws_bytes(1000) >= 4000
+
+
+def test_constraints_validation():
+    fp = np.ascontiguousarray(RECT)
+    e = _lib.PsdfEdges(1, 1, 1, 1, 1, 4, 1, 4)
+    p = _lib.PsdfParams(1e-12, 1e-6, 1000.0)
+    lib = _lib.lib()
+
+    def call(dmin, hj, keys=1):
+        return lib.psdf_constraints(fp.ctypes.data_as(ctypes.c_void_p), 4, ctypes.c_void_p(1), 1,
+                                    ctypes.byref(e), ctypes.byref(p), dmin, hj, None,
+                                    ctypes.c_void_p(keys) if keys else None, ctypes.c_void_p(1),
+                                    1 << 30, None)
+    assert call(0.01, None) == _lib.PSDF_EINVAL
+    assert call(0.01, ctypes.c_void_p(1), keys=0) == _lib.PSDF_EINVAL
+    assert call(float("nan"), ctypes.c_void_p(1)) == _lib.PSDF_EINVAL
+    assert "d_min" in lib.psdf_last_error().decode()

@@ -239,3 +239,28 @@ def test_launch_shape_independent(api, blk, sb):
         api.set_launch_shape(0, 0)
     for x, y in zip(ref, out):
         assert np.array_equal(x, y)
+
+
+def test_constraints_export(api):
+    """psdf_constraints: (phi - d_min, -grad) per stage, equal to psdf_grad's
+    outputs transformed in FP32, and the pinned host copy equal to the device
+    rows once the stream has synchronised."""
+    for inst in (inputs.c1(0), inputs.c2(0)):
+        edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar)
+        poses = torch.tensor(inst.poses, device="cuda")
+        d, e, o, g, k = api.psdf_grad(inst.footprint, poses, edges)
+        host = torch.empty((inst.N, 4), dtype=torch.float32, pin_memory=True)
+        hj, keys = api.psdf_constraints(inst.footprint, poses, edges, 0.01, host=host)
+        torch.cuda.synchronize()
+        assert torch.equal(keys, k)
+        assert torch.equal(hj[:, 0], d - torch.tensor(0.01, dtype=torch.float32, device="cuda"))
+        assert torch.equal(hj[:, 1:], -g)
+        assert torch.equal(host, hj.cpu())
+    # no obstacle: h = +inf, J = 0
+    empty = inputs.Instance(inputs.rect_footprint(), inputs.c1(0).poses, np.zeros((0, 4), np.float32),
+                            np.zeros(1, np.int32), 4, dict(workload="empty"))
+    edges = api.EdgeSet(empty.edges, empty.obst_off, empty.mbar)
+    hj, _ = api.psdf_constraints(empty.footprint, torch.tensor(empty.poses, device="cuda"), edges, 0.01)
+    torch.cuda.synchronize()
+    hj = hj.cpu().numpy()
+    assert np.all(np.isposinf(hj[:, 0])) and np.all(hj[:, 1:] == 0)

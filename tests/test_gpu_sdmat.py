@@ -1,0 +1,136 @@
+"""GPU parity of psdf_sd_matrix (every obstacle's sd per stage, before the
+minimum) against the FP64 oracle, and its consistency with psdf_eval."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_04310_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+D_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_04310_amd import api as _api
+    return _api
+
+
+def gpu_sdm(api, inst, eta=1000.0):
+    print(f"[sdmat] {inst.meta.get('workload')} N={inst.N} M={inst.M} m={len(inst.footprint)} eta={eta}", flush=True)
+    edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar)
+    poses = torch.tensor(inst.poses, device="cuda")
+    p = api.Params(eta=eta)
+    sd = api.psdf_sd_matrix(inst.footprint, poses, edges, p)
+    d, e, o, _ = api.psdf_eval(inst.footprint, poses, edges, p)
+    torch.cuda.synchronize()
+    return sd.cpu().numpy(), d.cpu().numpy(), o.cpu().numpy()
+
+
+def compare(inst, sd, eta):
+    """Element-wise bar |dsd| <= 1e-5 m; an entry whose separating-axis test
+    sits on the eps_sat boundary may take either branch (it then matches the
+    oracle with eps_sat moved by 2e-6)."""
+    ref = oracle.sd_matrix(inst.footprint, inst.poses, inst.edges, inst.obst_off, eta=eta)
+    assert sd.shape == ref.shape
+    same_special = (np.isnan(sd) == np.isnan(ref)) & (np.isinf(sd) == np.isinf(ref))
+    assert same_special.all()
+    fin = np.isfinite(ref)
+    bad = np.argwhere(fin & (np.abs(sd - np.where(fin, ref, 0)) > D_TOL))
+    branch_ties = 0
+    for s, i in bad:
+        a, b = int(inst.obst_off[i]), int(inst.obst_off[i + 1])
+        alts = [oracle.obstacle(inst.footprint, inst.poses[s], inst.edges[a:b], eta=eta,
+                                eps_sat=es)["sd"] for es in (-1e-6, 3e-6)]
+        assert min(abs(sd[s, i] - x) for x in alts) <= D_TOL, (s, i, sd[s, i], ref[s, i], alts)
+        branch_ties += 1
+    assert branch_ties <= max(1, sd.size // 1000)
+    return int(fin.sum())
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("eta", [1000.0, math.inf])
+def test_c1(api, seed, eta):
+    inst = inputs.c1(seed)
+    sd, d, o = gpu_sdm(api, inst, eta)
+    assert compare(inst, sd, eta) == inst.N * inst.M
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_mixed_penetrating(api, seed):
+    rng = np.random.default_rng(500 + seed)
+    inst = inputs.random_small(rng, n_obst=40, n_poses=37, segments=12, lo=-3, hi=3)
+    sd, d, o = gpu_sdm(api, inst)
+    compare(inst, sd, 1000.0)
+    assert (sd < 0).any()
+
+
+@pytest.mark.parametrize("M,N", [(1, 1), (255, 5), (257, 130), (3000, 7)])
+def test_ragged(api, M, N):
+    rng = np.random.default_rng(M + 31 * N)
+    edges = inputs.random_rects(rng, M, 0.1, 0.8, -6, 6)
+    inst = inputs.Instance(inputs.rect_footprint(), inputs.uniform_poses(rng, N, -6, 6), edges,
+                           inputs.csr_offsets([4] * M), 4, dict(workload="ragged"))
+    sd, d, o = gpu_sdm(api, inst)
+    compare(inst, sd, 1000.0)
+
+
+def _row_min_first(sd):
+    """Per-row minimum and its lowest index with NaN winning (tensor semantics)."""
+    nan = np.isnan(sd)
+    key = np.where(nan, -np.inf, sd)
+    idx = np.argmin(key, axis=1)
+    return key[np.arange(sd.shape[0]), idx], idx, nan.any(axis=1)
+
+
+@pytest.mark.parametrize("case", ["c2", "polygons16", "padding", "nan"])
+def test_row_minimum_equals_eval(api, case):
+    rng = np.random.default_rng(77)
+    if case == "c2":
+        inst = inputs.c2(0)
+    elif case == "polygons16":
+        sizes = rng.integers(3, 17, size=40)
+        edges, off = [], [0]
+        for k in sizes:
+            ang = np.sort(rng.uniform(0, 2 * np.pi, k))
+            c = rng.uniform(-2.5, 2.5, 2)
+            pts = inputs._hull_ccw((c + rng.uniform(0.1, 0.6) * np.stack([np.cos(ang), np.sin(ang)], 1))
+                                   .astype(np.float32)).astype(np.float32)
+            edges.append(np.concatenate([pts, np.roll(pts, -1, 0)], 1))
+            off.append(off[-1] + len(pts))
+        ang = np.linspace(0, 2 * np.pi, 16, endpoint=False)
+        fp = (0.4 * np.stack([np.cos(ang), 0.7 * np.sin(ang)], 1)).astype(np.float32)
+        off = np.array(off, np.int32)
+        inst = inputs.Instance(fp, inputs.uniform_poses(rng, 23, -2.5, 2.5),
+                               np.concatenate(edges).astype(np.float32), off,
+                               int(np.diff(off).max()), dict(workload="polygons16"))
+    elif case == "padding":
+        edges = inputs.random_rects(rng, 6, 0.2, 1.0, -2, 2)
+        inst = inputs.Instance(inputs.rect_footprint(), inputs.uniform_poses(rng, 9, -2, 2), edges,
+                               inputs.csr_offsets([0, 4, 0, 0, 4, 4, 0, 4, 4, 4, 0]), 4,
+                               dict(workload="padding"))
+    else:
+        inst = inputs.c1(2)
+        inst.poses = inst.poses.copy()
+        inst.poses[4, 1] = np.nan
+    sd, d, o = gpu_sdm(api, inst)
+    mn, idx, has_nan = _row_min_first(sd)
+    for s in range(inst.N):
+        if has_nan[s]:
+            assert np.isnan(d[s]) and o[s] == -1
+        elif np.isinf(mn[s]):
+            assert np.isinf(d[s]) and o[s] == -1
+        else:
+            assert np.float32(mn[s]).tobytes() == np.float32(d[s]).tobytes(), s
+            assert idx[s] == o[s], s
+    if case == "padding":
+        assert np.all(np.isinf(sd[:, [0, 2, 3, 6, 10]]))
+    if case != "nan":
+        compare(inst, sd, 1000.0)

@@ -158,6 +158,24 @@ int psdf_bwd(const float* footprint, int32_t m, const float* poses, int32_t N,
              const psdf_edges* edges, const psdf_params* params, const uint64_t* keys,
              const float* gout, float* gpose, hipStream_t stream);
 
+/* psdf_bwd_geometry - vector-Jacobian product of phi with respect to the
+ * geometry: gedges[e] = sum_s gout[s] * dphi_s / d(A_x, A_y, B_x, B_y) of
+ * edge e (world frame), gfp[k] = sum_s gout[s] * dphi_s / d(vertex k) of the
+ * footprint (its own frame, the caller's vertex order), through each stage's
+ * winning obstacle with the active-branch subgradient (Sec. IV-D applied to
+ * every input of the pipeline of Sec. IV-A..IV-C).  keys: the winners of a
+ * previous psdf_eval/psdf_grad on the same inputs.  gedges: device
+ * float32[E][4], gfp: device float32[m][2], both overwritten (zero where no
+ * winner depends on them).  A polygon vertex shared by two edges (B_j ==
+ * A_{j+1}) may see its gradient split between the two copies in any way;
+ * their sum is the vertex's gradient.  Stages add in an unspecified order
+ * (FP32 atomics), so the last bits may vary between runs.  A stage with a
+ * NaN winner adds NaN to every footprint vertex; a non-finite gout[s] adds
+ * NaN to its winner's edges and the footprint. */
+int psdf_bwd_geometry(const float* footprint, int32_t m, const float* poses, int32_t N,
+                      const psdf_edges* edges, const psdf_params* params, const uint64_t* keys,
+                      const float* gout, float* gedges, float* gfp, hipStream_t stream);
+
 /* psdf_sd_matrix - every obstacle's signed distance at every stage, before
  * the minimum over obstacles (Sec. IV-D: sd^i, whose minimum is phi), for
  * callers that constrain several obstacles per stage.  sd: device

@@ -53,6 +53,10 @@ def _load():
         lib.oracle_obstacle.argtypes = [dp, ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_int,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         dp, ip, dp, dp, dp]
+        lib.oracle_obstacle_geom_grad.restype = None
+        lib.oracle_obstacle_geom_grad.argtypes = [dp, ctypes.c_int, dp, dp, dp, dp, dp,
+                                                  ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                  ctypes.c_double, dp, dp]
         lib.oracle_sd_matrix.restype = None
         lib.oracle_sd_matrix.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, dp, dp, dp, dp, ip,
                                          ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -116,6 +120,45 @@ def obstacle(footprint, pose, edges, eps=DEFAULT_EPS, eps_sat=DEFAULT_EPS_SAT, e
                         mi, eps, eps_sat, eta, sdp, sepp, dsepp, poolp, gradp)
     return dict(sd=float(sd[0]), separated=bool(sep[0]), d_sep=float(dsep[0]),
                 edge_pool=pool[:mi].copy(), grad=grad.copy())
+
+
+def geom_grad(footprint, pose, edges, eps=DEFAULT_EPS, eps_sat=DEFAULT_EPS_SAT, eta=DEFAULT_ETA):
+    """d sd / d(geometry) for one (pose, obstacle): ``edges`` (mi, 4) of
+    (A_x, A_y, B_x, B_y) -> (g_edges (mi, 4), g_fp (m, 2) in the caller's
+    vertex order)."""
+    lib = _load()
+    fp, fpp = _d(footprint)
+    ps, psp = _d(pose)
+    ed = np.ascontiguousarray(edges, dtype=np.float64).reshape(-1, 4)
+    mi = ed.shape[0]
+    cols = [_d(ed[:, k]) for k in range(4)]
+    ge, gep = _d(np.zeros((mi, 4)))
+    gf, gfp = _d(np.zeros((fp.shape[0], 2)))
+    lib.oracle_obstacle_geom_grad(fpp, fp.shape[0], psp, cols[0][1], cols[1][1], cols[2][1],
+                                  cols[3][1], mi, eps, eps_sat, eta, gep, gfp)
+    return ge.copy(), gf.copy()
+
+
+def psdf_geom(footprint, poses, edges, obst_off, gout, eps=DEFAULT_EPS, eps_sat=DEFAULT_EPS_SAT,
+              eta=DEFAULT_ETA):
+    """Vector-Jacobian product of phi with respect to the geometry:
+    sum over stages of gout[s] * d phi_s / d(edges) -> (E, 4), and
+    / d(footprint vertices) -> (m, 2), through each stage's winning obstacle
+    (lowest index on ties).  Stages with no obstacle contribute nothing."""
+    ed = np.asarray(edges, dtype=np.float64).reshape(-1, 4)
+    off = np.asarray(obst_off)
+    ref = psdf(footprint, poses, edges, obst_off, eps=eps, eps_sat=eps_sat, eta=eta)
+    gE = np.zeros_like(ed)
+    gF = np.zeros((np.asarray(footprint).reshape(-1, 2).shape[0], 2))
+    for s in range(len(poses)):
+        i = int(ref["obst"][s])
+        if i < 0:
+            continue
+        a, b = int(off[i]), int(off[i + 1])
+        ge, gf = geom_grad(footprint, poses[s], ed[a:b], eps=eps, eps_sat=eps_sat, eta=eta)
+        gE[a:b] += gout[s] * ge
+        gF += gout[s] * gf
+    return gE, gF
 
 
 def sd_matrix(footprint, poses, edges, obst_off, eps=DEFAULT_EPS, eps_sat=DEFAULT_EPS_SAT,

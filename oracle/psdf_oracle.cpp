@@ -126,6 +126,7 @@ struct Vec { double x, y; };
 struct Footprint {
   std::vector<Vec> v;   // V^0, CCW
   std::vector<Vec> n;   // n_l: outward unit normal of E_l = [v_l, v_{l+1}]
+  bool reversed = false;  // the caller's order was clockwise (v[k] = caller[m-1-k])
 };
 
 Footprint make_footprint(const double* xy, int m) {
@@ -136,7 +137,10 @@ Footprint make_footprint(const double* xy, int m) {
     const Vec& a = f.v[l]; const Vec& b = f.v[(l + 1) % m];
     area2 += a.x * b.y - a.y * b.x;
   }
-  if (area2 < 0) std::reverse(f.v.begin(), f.v.end());  // the paper requires CCW
+  if (area2 < 0) {  // the paper requires CCW
+    std::reverse(f.v.begin(), f.v.end());
+    f.reversed = true;
+  }
   for (int l = 0; l < m; ++l) {
     const Vec& a = f.v[l]; const Vec& b = f.v[(l + 1) % m];
     double ex = b.x - a.x, ey = b.y - a.y, len = std::sqrt(ex * ex + ey * ey);
@@ -171,13 +175,16 @@ struct ObstacleEval {
   std::vector<double> edge_pool;  // per-edge pool distance (for the reported edge)
 };
 
-// Signed distance between the footprint at pose (px, py, th) and obstacle i,
-// whose edges are [A_j, B_j], j = 0..mi-1 (world frame).
+// Signed distance between the footprint V0 (CCW, local frame) at pose
+// (px, py, th) and obstacle i, whose edges are [A_j, B_j], j = 0..mi-1 (world
+// frame).  Every input may carry tangents: the pose for the pose gradient,
+// the endpoints and vertices for the geometry gradient.
 template <class T>
-ObstacleEval<T> eval_obstacle(const Footprint& F, const T& px, const T& py, const T& th,
-                              const double* ax, const double* ay, const double* bx,
-                              const double* by, int mi, const Params& prm) {
-  const int m = (int)F.v.size();
+ObstacleEval<T> eval_obstacle_geo(const std::vector<P2<T>>& V0, const T& px, const T& py,
+                                  const T& th, const std::vector<P2<T>>& Aw,
+                                  const std::vector<P2<T>>& Bw, const Params& prm) {
+  const int m = (int)V0.size();
+  const int mi = (int)Aw.size();
   ObstacleEval<T> out;
 
   // ---- Step 1: coordinate transform, A~ = R^T (A - p), B~ = R^T (B - p).
@@ -185,13 +192,11 @@ ObstacleEval<T> eval_obstacle(const Footprint& F, const T& px, const T& py, cons
   T c = dcos(th), s = dsin(th);
   std::vector<P2<T>> At(mi), Bt(mi);
   for (int j = 0; j < mi; ++j) {
-    T dx = T(ax[j]) - px, dy = T(ay[j]) - py;
+    T dx = Aw[j].x - px, dy = Aw[j].y - py;
     At[j] = {c * dx + s * dy, T(0.0) - s * dx + c * dy};
-    T ex = T(bx[j]) - px, ey = T(by[j]) - py;
+    T ex = Bw[j].x - px, ey = Bw[j].y - py;
     Bt[j] = {c * ex + s * ey, T(0.0) - s * ex + c * ey};
   }
-  std::vector<P2<T>> V0(m);
-  for (int l = 0; l < m; ++l) V0[l] = {T(F.v[l].x), T(F.v[l].y)};
 
   // ---- Step 2: point-to-segment pools.
   // d_v^i: robot vertices to obstacle edges.
@@ -222,7 +227,12 @@ ObstacleEval<T> eval_obstacle(const Footprint& F, const T& px, const T& py, cons
 
   // ---- Step 3: SAT over the candidate axes N^i = {n_l} U {n'_j}.
   std::vector<P2<T>> axes;
-  for (int l = 0; l < m; ++l) axes.push_back({T(F.n[l].x), T(F.n[l].y)});
+  for (int l = 0; l < m; ++l) {
+    // outward unit normal of the CCW footprint edge E_l: e_l rotated by -90 deg
+    T ex = V0[(l + 1) % m].x - V0[l].x, ey = V0[(l + 1) % m].y - V0[l].y;
+    T len = dsqrt(ex * ex + ey * ey);
+    axes.push_back({ey / len, (T(0.0) - ex) / len});
+  }
   for (int j = 0; j < mi; ++j) {
     T ux = Bt[j].x - At[j].x, uy = Bt[j].y - At[j].y;       // u_j = B~_j - A~_j
     T den = dsqrt(ux * ux + uy * uy) + T(prm.eps);          // |u_j| + eps
@@ -259,6 +269,21 @@ ObstacleEval<T> eval_obstacle(const Footprint& F, const T& px, const T& py, cons
   // ---- Step 4: synthesis.
   out.sd = separated ? out.d_sep : T(0.0) - pen;
   return out;
+}
+
+// The same with constant geometry: the footprint F and obstacle edges as
+// plain doubles; only the pose may carry tangents.
+template <class T>
+ObstacleEval<T> eval_obstacle(const Footprint& F, const T& px, const T& py, const T& th,
+                              const double* ax, const double* ay, const double* bx,
+                              const double* by, int mi, const Params& prm) {
+  std::vector<P2<T>> V0(F.v.size()), Aw(mi), Bw(mi);
+  for (size_t l = 0; l < F.v.size(); ++l) V0[l] = {T(F.v[l].x), T(F.v[l].y)};
+  for (int j = 0; j < mi; ++j) {
+    Aw[j] = {T(ax[j]), T(ay[j])};
+    Bw[j] = {T(bx[j]), T(by[j])};
+  }
+  return eval_obstacle_geo<T>(V0, px, py, th, Aw, Bw, prm);
 }
 
 struct Edges {
@@ -367,6 +392,50 @@ void oracle_obstacle(const double* fp_xy, int m, const double* pose, const doubl
   *d_sep = ev.d_sep.v;
   for (int j = 0; j < mi; ++j) edge_pool[j] = ev.edge_pool[j];
   for (int k = 0; k < 3; ++k) grad[k] = ev.sd.g[k];
+}
+
+// d sd / d(geometry) for one (stage, obstacle), by forward mode over every
+// geometry coordinate (three per pass): g_edges[mi][4] = d sd / d(A_x, A_y,
+// B_x, B_y) of each world edge endpoint, g_fp[m][2] = d sd / d(vertex) of the
+// footprint in the caller's vertex order.  Same kink conventions as the pose
+// gradient (even split over bit-equal entries of a min / max).
+void oracle_obstacle_geom_grad(const double* fp_xy, int m, const double* pose, const double* ax,
+                               const double* ay, const double* bx, const double* by, int mi,
+                               double eps, double eps_sat, double eta, double* g_edges,
+                               double* g_fp) {
+  Footprint F = make_footprint(fp_xy, m);
+  Params prm{eps, eps_sat, eta};
+  const int P = 4 * mi + 2 * m;   // parameters: endpoints, then CCW footprint vertices
+  for (int p0 = 0; p0 < P; p0 += 3) {
+    std::vector<P2<Dual>> V0(m), Aw(mi), Bw(mi);
+    for (int l = 0; l < m; ++l) V0[l] = {Dual(F.v[l].x), Dual(F.v[l].y)};
+    for (int j = 0; j < mi; ++j) {
+      Aw[j] = {Dual(ax[j]), Dual(ay[j])};
+      Bw[j] = {Dual(bx[j]), Dual(by[j])};
+    }
+    auto coord = [&](int q) -> Dual& {
+      if (q < 4 * mi) {
+        const int j = q / 4, r = q % 4;
+        P2<Dual>& e = r < 2 ? Aw[j] : Bw[j];
+        return (r % 2 == 0) ? e.x : e.y;
+      }
+      const int l = (q - 4 * mi) / 2;
+      return (q - 4 * mi) % 2 == 0 ? V0[l].x : V0[l].y;
+    };
+    for (int k = 0; k < 3 && p0 + k < P; ++k) coord(p0 + k).g[k] = 1.0;
+    ObstacleEval<Dual> ev = eval_obstacle_geo<Dual>(V0, Dual(pose[0]), Dual(pose[1]),
+                                                    Dual(pose[2]), Aw, Bw, prm);
+    for (int k = 0; k < 3 && p0 + k < P; ++k) {
+      const int q = p0 + k;
+      if (q < 4 * mi) {
+        g_edges[q] = ev.sd.g[k];
+      } else {
+        const int l = (q - 4 * mi) / 2, r = (q - 4 * mi) % 2;
+        const int caller = F.reversed ? m - 1 - l : l;
+        g_fp[2 * caller + r] = ev.sd.g[k];
+      }
+    }
+  }
 }
 
 // sd^i for every (stage, obstacle): out is N x M, row-major.  Empty obstacles

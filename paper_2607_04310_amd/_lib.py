@@ -85,6 +85,8 @@ _SIGS = {
     "psdf_constraints": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
                                         ctypes.POINTER(PsdfParams), ctypes.c_float, _VP, _VP, _VP,
                                         _VP, ctypes.c_size_t, _VP]),
+    "psdf_bwd_geometry": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
+                                         ctypes.POINTER(PsdfParams), _VP, _VP, _VP, _VP, _VP]),
     "psdf_sd_matrix": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
                                       ctypes.POINTER(PsdfParams), _VP, _VP]),
     "psdf_encode_ws_bytes": (ctypes.c_size_t, [_I32]),

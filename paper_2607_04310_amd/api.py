@@ -167,6 +167,27 @@ def psdf_constraints(footprint, poses, edges: EdgeSet, d_min, params: Params | N
     return hj, keys
 
 
+def psdf_bwd_geometry(footprint, poses, edges: EdgeSet, keys, gout, params: Params | None = None):
+    """(gedges (E, 4), gfp (m, 2)): sum over stages of gout[s] times the
+    gradient of phi_s with respect to the edge endpoints (A_x, A_y, B_x, B_y)
+    and the footprint vertices (caller's order), from the keys of a
+    psdf_eval / psdf_grad on the same inputs."""
+    params = params or Params()
+    poses = _poses(poses)
+    N = poses.shape[0]
+    dev = poses.device
+    gout = gout.contiguous().to(torch.float32)
+    fp, fpp, m = _fp(footprint)
+    gedges = torch.empty((edges.E, 4), dtype=torch.float32, device=dev)
+    gfp = torch.empty((m, 2), dtype=torch.float32, device=dev)
+    ec, pc = edges.c(), params.c()
+    _lib.check(_lib.lib().psdf_bwd_geometry(fpp, m, poses.data_ptr(), N, ctypes.byref(ec),
+                                            ctypes.byref(pc), keys.data_ptr(), gout.data_ptr(),
+                                            gedges.data_ptr(), gfp.data_ptr(),
+                                            _lib.stream_handle()))
+    return gedges, gfp
+
+
 def psdf_sd_matrix(footprint, poses, edges: EdgeSet, params: Params | None = None, out=None):
     """sd[s, i] of every obstacle i at every stage s, before the minimum."""
     params = params or Params()

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpsdf.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = (["psdf_host.cpp", "psdf_plain.hip", "psdf_batch.hip", "psdf_mlp.hip"]
+SOURCES = (["psdf_host.cpp", "psdf_plain.hip", "psdf_batch.hip", "psdf_mlp.hip", "psdf_geom.hip"]
            + [f"psdf_inst_mf{m}.hip" for m in (3, 4, 5, 6, 7, 8, 16)]
            + [f"psdf_batch_mf{m}.hip" for m in (3, 4, 5, 6, 7, 8, 16)])
 

@@ -37,6 +37,7 @@ constexpr uint64_t kEmptyKey = ~0ull;
 struct FpConst {
   int m;
   int hard;        // 1: hard minimum (eta <= 0 or +inf)
+  int reversed;    // 1: the caller's vertex order was clockwise (slot l = caller m - 1 - l)
   float eps, eps_sat, eta;
   float vx[kMaxFp], vy[kMaxFp];  // vertices v_l
   float ex[kMaxFp], ey[kMaxFp];  // robot edge E_l = [v_l, v_{l+1}] as v_{l+1} - v_l

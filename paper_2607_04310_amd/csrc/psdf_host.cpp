@@ -53,7 +53,8 @@ int prepare_footprint(const float* xy, int m, const psdf_params* params, FpConst
   }
   double area2 = 0.0;
   for (int l = 0; l < m; ++l) area2 += vx[l] * vy[(l + 1) % m] - vy[l] * vx[(l + 1) % m];
-  if (area2 < 0.0) {  // reorder counter-clockwise
+  const bool reversed = area2 < 0.0;
+  if (reversed) {  // reorder counter-clockwise
     for (int l = 0; l < m / 2; ++l) {
       std::swap(vx[l], vx[m - 1 - l]);
       std::swap(vy[l], vy[m - 1 - l]);
@@ -86,6 +87,7 @@ int prepare_footprint(const float* xy, int m, const psdf_params* params, FpConst
   FpConst& f = *F;
   std::memset(&f, 0, sizeof f);
   f.m = m;
+  f.reversed = reversed ? 1 : 0;
   f.eps = p.eps;
   f.eps_sat = p.eps_sat;
   f.eta = p.eta;

@@ -13,6 +13,11 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 D_TOL = 1e-5
+# Far entries carry the FP32 rounding of the transform R^T (A - p), a few ulps
+# of the distance itself (ulp(39 m) = 3.8e-6 m): the bar is 1e-5 m plus
+# 1e-6 of |sd|, which leaves the 1e-5 m bar untouched for entries within a
+# few metres, the ones that can be a stage's minimum.
+D_REL = 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -35,7 +40,7 @@ def gpu_sdm(api, inst, eta=1000.0):
 
 
 def compare(inst, sd, eta):
-    """Element-wise bar |dsd| <= 1e-5 m; an entry whose separating-axis test
+    """Element-wise bar |dsd| <= 1e-5 m + 1e-6 |sd|; an entry whose separating-axis test
     sits on the eps_sat boundary may take either branch (it then matches the
     oracle with eps_sat moved by 2e-6)."""
     ref = oracle.sd_matrix(inst.footprint, inst.poses, inst.edges, inst.obst_off, eta=eta)
@@ -43,13 +48,14 @@ def compare(inst, sd, eta):
     same_special = (np.isnan(sd) == np.isnan(ref)) & (np.isinf(sd) == np.isinf(ref))
     assert same_special.all()
     fin = np.isfinite(ref)
-    bad = np.argwhere(fin & (np.abs(sd - np.where(fin, ref, 0)) > D_TOL))
+    tol = D_TOL + D_REL * np.abs(np.where(fin, ref, 0))
+    bad = np.argwhere(fin & (np.abs(sd - np.where(fin, ref, 0)) > tol))
     branch_ties = 0
     for s, i in bad:
         a, b = int(inst.obst_off[i]), int(inst.obst_off[i + 1])
         alts = [oracle.obstacle(inst.footprint, inst.poses[s], inst.edges[a:b], eta=eta,
                                 eps_sat=es)["sd"] for es in (-1e-6, 3e-6)]
-        assert min(abs(sd[s, i] - x) for x in alts) <= D_TOL, (s, i, sd[s, i], ref[s, i], alts)
+        assert min(abs(sd[s, i] - x) for x in alts) <= tol[s, i], (s, i, sd[s, i], ref[s, i], alts)
         branch_ties += 1
     assert branch_ties <= max(1, sd.size // 1000)
     return int(fin.sum())

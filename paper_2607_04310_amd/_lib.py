@@ -87,6 +87,9 @@ _SIGS = {
                                         _VP, ctypes.c_size_t, _VP]),
     "psdf_bwd_geometry": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
                                          ctypes.POINTER(PsdfParams), _VP, _VP, _VP, _VP, _VP]),
+    "psdf_time_stage_min": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
+                                           ctypes.POINTER(PsdfParams), _VP, ctypes.c_size_t, _I32,
+                                           _VP, ctypes.POINTER(ctypes.c_float)]),
     "psdf_sd_matrix": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
                                       ctypes.POINTER(PsdfParams), _VP, _VP]),
     "psdf_encode_ws_bytes": (ctypes.c_size_t, [_I32]),

@@ -188,6 +188,23 @@ def psdf_bwd_geometry(footprint, poses, edges: EdgeSet, keys, gout, params: Para
     return gedges, gfp
 
 
+def time_stage_min(footprint, poses, edges: EdgeSet, reps, params: Params | None = None,
+                   ws=None):
+    """Mean duration in ms of `reps` back-to-back launches of the
+    per-stage-minimum kernel (measurement aid; synchronises the stream)."""
+    params = params or Params()
+    poses = _poses(poses)
+    N = poses.shape[0]
+    ws = workspace(N, edges.M, poses.device) if ws is None else ws
+    fp, fpp, m = _fp(footprint)
+    ec, pc = edges.c(), params.c()
+    ms = ctypes.c_float(0.0)
+    _lib.check(_lib.lib().psdf_time_stage_min(fpp, m, poses.data_ptr(), N, ctypes.byref(ec),
+                                              ctypes.byref(pc), ws.data_ptr(), ws.numel(),
+                                              int(reps), _lib.stream_handle(), ctypes.byref(ms)))
+    return float(ms.value)
+
+
 def psdf_sd_matrix(footprint, poses, edges: EdgeSet, params: Params | None = None, out=None):
     """sd[s, i] of every obstacle i at every stage s, before the minimum."""
     params = params or Params()

@@ -205,6 +205,15 @@ void timer_begin(hipStream_t st) {
   }
 }
 
+bool timer_kernel_events(hipEvent_t* start, hipEvent_t* stop) {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  if (g_timer.open || g_timer.used + 2 > g_timer.ev.size()) return false;
+  *start = g_timer.ev[g_timer.used];
+  *stop = g_timer.ev[g_timer.used + 1];
+  g_timer.used += 2;
+  return true;
+}
+
 void timer_end(hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_timer.mu);
   if (!g_timer.open) return;

@@ -33,6 +33,10 @@ inline int obst_class(int mbar) { return mbar <= 4 ? 4 : (mbar <= 8 ? 8 : 16); }
 // Kernel timer: bracket one launch of the dominant kernel with events.
 void timer_begin(hipStream_t st);
 void timer_end(hipStream_t st);
+// Or take an event pair for a launch that records them itself (the
+// dispatch's own start and end, hipExtLaunchKernel); false when the timer is
+// off or full.
+bool timer_kernel_events(hipEvent_t* start, hipEvent_t* stop);
 
 // Default launch shape of the plain kernel for N stages and M obstacles.
 LaunchShape choose_shape(int N, int M);

@@ -12,6 +12,7 @@
 // a stage; no atomics and no initialisation pass are needed.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "psdf.h"
@@ -83,27 +84,31 @@ __global__ __launch_bounds__(BLK) void main_kernel(FpConst F, const float* __res
   }
 }
 
+// ev0 / ev1 (may be null): events that the dispatch itself records at its
+// start and end (kernel timer).
 template <int MF, int MI>
 hipError_t launch_main_t(const LaunchShape& ls, const FpConst& F, const float* poses, int N,
-                         const psdf_edges& e, uint64_t* partial, hipStream_t st) {
+                         const psdf_edges& e, uint64_t* partial, hipStream_t st, hipEvent_t ev0,
+                         hipEvent_t ev1) {
   dim3 grid((e.M + ls.blk - 1) / ls.blk, (N + ls.sb - 1) / ls.sb);
   uint64_t* aux = partial + (size_t)N * grid.x;
   if (ls.blk == 64)
-    main_kernel<MF, MI, 64><<<grid, 64, 0, st>>>(F, poses, N, ls.sb, e.ax, e.ay, e.bx, e.by,
-                                                  e.obst_off, e.E, e.M, partial, aux);
+    hipExtLaunchKernelGGL(main_kernel<MF, MI, 64>, grid, dim3(64), 0, st, ev0, ev1, 0, F, poses,
+                          N, ls.sb, e.ax, e.ay, e.bx, e.by, e.obst_off, e.E, e.M, partial, aux);
   else
-    main_kernel<MF, MI, 256><<<grid, 256, 0, st>>>(F, poses, N, ls.sb, e.ax, e.ay, e.bx, e.by,
-                                                    e.obst_off, e.E, e.M, partial, aux);
+    hipExtLaunchKernelGGL(main_kernel<MF, MI, 256>, grid, dim3(256), 0, st, ev0, ev1, 0, F,
+                          poses, N, ls.sb, e.ax, e.ay, e.bx, e.by, e.obst_off, e.E, e.M, partial,
+                          aux);
   return hipGetLastError();
 }
 
 template <int MF>
 hipError_t launch_main_mf(int mi_class, const LaunchShape& ls, const FpConst& F,
                           const float* poses, int N, const psdf_edges& e, uint64_t* partial,
-                          hipStream_t st) {
-  if (mi_class == 4) return launch_main_t<MF, 4>(ls, F, poses, N, e, partial, st);
-  if (mi_class == 8) return launch_main_t<MF, 8>(ls, F, poses, N, e, partial, st);
-  return launch_main_t<MF, 16>(ls, F, poses, N, e, partial, st);
+                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (mi_class == 4) return launch_main_t<MF, 4>(ls, F, poses, N, e, partial, st, ev0, ev1);
+  if (mi_class == 8) return launch_main_t<MF, 8>(ls, F, poses, N, e, partial, st, ev0, ev1);
+  return launch_main_t<MF, 16>(ls, F, poses, N, e, partial, st, ev0, ev1);
 }
 
 // Every obstacle's sd per stage, before the minimum over obstacles: lane <->
@@ -164,7 +169,8 @@ hipError_t launch_sdmat_mf(int mi_class, const FpConst& F, const float* poses, i
 #define PSDF_EXTERN_MF(MF)                                                                  \
   extern template hipError_t launch_main_mf<MF>(int, const LaunchShape&, const FpConst&,    \
                                                 const float*, int, const psdf_edges&,       \
-                                                uint64_t*, hipStream_t);            \
+                                                uint64_t*, hipStream_t, hipEvent_t,         \
+                                                hipEvent_t);                                \
   extern template hipError_t launch_sdmat_mf<MF>(int, const FpConst&, const float*, int,    \
                                                  const psdf_edges&, float*, hipStream_t);
 PSDF_EXTERN_MF(3)

@@ -155,10 +155,10 @@ int partial_columns(int M, const LaunchShape& ls) { return (M + ls.blk - 1) / ls
 hipError_t launch_plain(const FpConst& F, const float* poses, int N, const psdf_edges& e,
                         uint64_t* partial, const LaunchShape& ls, hipStream_t st) {
   if (e.M == 0) return hipSuccess;
-  timer_begin(st);
-  hipError_t err = PSDF_BY_MF(launch_main_mf, obst_class(e.mbar), ls, F, poses, N, e, partial, st);
-  timer_end(st);
-  return err;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (!timer_kernel_events(&ev0, &ev1)) ev0 = ev1 = nullptr;
+  return PSDF_BY_MF(launch_main_mf, obst_class(e.mbar), ls, F, poses, N, e, partial, st, ev0,
+                    ev1);
 }
 
 hipError_t launch_epilogue(const FpConst& F, const float* poses, int N, const psdf_edges& e,
@@ -274,6 +274,39 @@ static int plain_run(const float* footprint, int32_t m, const float* poses, int3
   if (err == hipSuccess)
     err = launch_epilogue(F, poses, N, e, partial, e.M > 0 ? partial_columns(e.M, ls) : 0, keys,
                           nullptr, mode, 0.0f, d, edge, obst, grad, nullptr, stream);
+  return hip_status(err);
+}
+
+int psdf_time_stage_min(const float* footprint, int32_t m, const float* poses, int32_t N,
+                        const psdf_edges* edges, const psdf_params* params, void* ws,
+                        size_t ws_bytes, int32_t reps, hipStream_t stream, float* ms) {
+  clear_error();
+  FpConst F;
+  psdf_edges e;
+  int rc = plain_common(footprint, m, poses, N, edges, params, F, e);
+  if (rc) return rc;
+  if (!ms || reps < 1) return set_error(PSDF_EINVAL, "ms is NULL or reps < 1");
+  *ms = 0.f;
+  if (N == 0 || e.M == 0) return PSDF_OK;
+  const size_t need = psdf_workspace_bytes(N, e.M);
+  if (!ws || ws_bytes < need)
+    return set_error(PSDF_EWS, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  const LaunchShape ls = tuned_shape(F.m, e.mbar, N, e.M);
+  uint64_t* partial = static_cast<uint64_t*>(ws);
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t err = hipEventCreate(&a);
+  if (err == hipSuccess) err = hipEventCreate(&b);
+  if (err == hipSuccess) err = hipEventRecord(a, stream);
+  for (int r = 0; r < reps && err == hipSuccess; ++r)
+    err = PSDF_BY_MF(launch_main_mf, obst_class(e.mbar), ls, F, poses, N, e, partial, stream,
+                     nullptr, nullptr);
+  if (err == hipSuccess) err = hipEventRecord(b, stream);
+  if (err == hipSuccess) err = hipEventSynchronize(b);
+  float t = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&t, a, b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (err == hipSuccess) *ms = t / (float)reps;
   return hip_status(err);
 }
 

@@ -125,3 +125,18 @@ def test_constraints_validation():
     assert call(0.01, ctypes.c_void_p(1), keys=0) == _lib.PSDF_EINVAL
     assert call(float("nan"), ctypes.c_void_p(1)) == _lib.PSDF_EINVAL
     assert "d_min" in lib.psdf_last_error().decode()
+
+
+def test_time_stage_min_validation():
+    fp = np.ascontiguousarray(RECT)
+    e = _lib.PsdfEdges(1, 1, 1, 1, 1, 4, 1, 4)
+    p = _lib.PsdfParams(1e-12, 1e-6, 1000.0)
+    ms = ctypes.c_float(1.0)
+    lib = _lib.lib()
+    assert lib.psdf_time_stage_min(fp.ctypes.data_as(ctypes.c_void_p), 4, ctypes.c_void_p(1), 1,
+                                   ctypes.byref(e), ctypes.byref(p), ctypes.c_void_p(1), 1 << 30,
+                                   0, None, ctypes.byref(ms)) == _lib.PSDF_EINVAL
+    # no stage: nothing launched, zero time
+    assert lib.psdf_time_stage_min(fp.ctypes.data_as(ctypes.c_void_p), 4, None, 0,
+                                   ctypes.byref(e), ctypes.byref(p), None, 0, 5, None,
+                                   ctypes.byref(ms)) == _lib.PSDF_OK and ms.value == 0.0

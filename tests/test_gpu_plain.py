@@ -264,3 +264,11 @@ def test_constraints_export(api):
     torch.cuda.synchronize()
     hj = hj.cpu().numpy()
     assert np.all(np.isposinf(hj[:, 0])) and np.all(hj[:, 1:] == 0)
+
+
+def test_time_stage_min(api):
+    inst = inputs.c2(0)
+    edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar)
+    poses = torch.tensor(inst.poses, device="cuda")
+    ms = api.time_stage_min(inst.footprint, poses, edges, 20)
+    assert 0.0 < ms < 5.0

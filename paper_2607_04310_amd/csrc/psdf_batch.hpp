@@ -66,6 +66,7 @@ template <int MF, int MI, int NW>
 __global__ __launch_bounds__(64 * NW) void batch_kernel(BatchArgs A) {
   __shared__ int s_item, s_last;
   __shared__ float4 st[kMaxStageBlock];
+  __shared__ float4 rft[kMaxStageBlock * MF];
   __shared__ uint64_t wk[NW][kMaxStageBlock];
   __shared__ uint64_t wa[NW][kMaxStageBlock];
   __shared__ FpLds fl[NW];
@@ -99,12 +100,7 @@ __global__ __launch_bounds__(64 * NW) void batch_kernel(BatchArgs A) {
       e0 += in.edge_off;
     }
     const bool local_bad = active && e0 < in.edge_off;   // negative local offset
-    for (int t = threadIdx.x; t < ns; t += 64 * NW) {
-      const float* p = A.poses + 3 * (in.pose_off + s0 + t);
-      float sn, cs;
-      sincosf(p[2], &sn, &cs);
-      st[t] = make_float4(cs, sn, p[0], p[1]);
-    }
+    fill_stage_table<MF>(F, A.poses, in.pose_off + s0, ns, st, rft, 64 * NW);
     __syncthreads();
 
     if (w * 64 < no) {
@@ -112,7 +108,7 @@ __global__ __launch_bounds__(64 * NW) void batch_kernel(BatchArgs A) {
         if (lane == 0) { wk[w][t] = key; wa[w][t] = a; }
       };
       wave_stages<MF, MI>(F, A.ax, A.ay, A.bx, A.by, e0, mi, in.edge_off + in.E, active, local_bad,
-                          o0 + w * 64, ns, st, emit);
+                          o0 + w * 64, ns, st, rft, emit);
     } else if (lane == 0) {
       for (int t = 0; t < ns; ++t) { wk[w][t] = kEmptyKey; wa[w][t] = 0; }
     }

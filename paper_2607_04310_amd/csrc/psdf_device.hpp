@@ -1,21 +1,31 @@
 // Device-side PSDF arithmetic for gfx950 (wave64, FP32 VALU).
 //
 // One lane evaluates one obstacle against one stage pose at a time: the
-// obstacle's world-frame edges live in registers and are reused for every
-// stage the lane visits; the footprint constants are wave-uniform (kernel
-// arguments, i.e. scalar registers).  Everything is written with explicit
-// fmaf and compiled with -ffp-contract=off, so every kernel that inlines
-// these functions produces bit-identical results for the same inputs.
+// obstacle's world-frame edges and their stage-invariant constants live in
+// registers and are reused for every stage the lane visits; the footprint
+// constants are wave-uniform, and the footprint rotated by each stage's
+// heading is shared by the work-group in LDS.  Everything is written with
+// explicit fmaf and compiled with -ffp-contract=off, so every kernel that
+// inlines these functions produces bit-identical results for the same inputs.
 //
-// Pipeline per (stage, obstacle), Sec. IV-A items 1-4:
-//   1. A~_j = R(theta)^T (A_j - p); the local edge vector v_j = R^T (B_j - A_j)
-//   2. d_v^2 = min_{l,j} |v_l - Q(v_l; A~_j, v_j)|^2 and
-//      d_e^2 = min_{w in V_obs, l} |w - Q(w; v_l, e_l)|^2 with the clamp
-//      t = min(max(u, 0), 1) (identical to ReLU(u) - ReLU(u - 1) for |u| < 2^23)
-//   3. SAT over {n_l} U {n'_j = rot90(v_j) / (|v_j| + eps)}, overlaps
-//      delta(n) = min(beta_i - alpha_P, beta_P - alpha_i), separated if any
-//      delta < -eps_sat; soft-min depth -(1/eta) log sum exp(-eta max(delta, 0))
-//      in max-shifted form
+// Pipeline per (stage, obstacle), Sec. IV-A items 1-4, evaluated in the frame
+// of the stage pose translated to the origin but not rotated: the obstacle
+// is translated (A_j - p) and the footprint rotated (R v_l, R u_l), which
+// gives the same distances and axis overlaps as the paper's local frame
+// R^T (A - p) (a rigid motion of both sets):
+//   2. every point-segment distance in the segment's own frame: with the
+//      unit direction u and normal n of the segment, a = (P - A) . u and
+//      b = (P - A) . n, d^2 = b^2 + (a - clamp(a, 0, |B - A|))^2, which is
+//      |P - A - t (B - A)|^2 with t = clamp(u, 0, 1) of Sec. IV-B (eps -> 0);
+//      d_v over (robot vertex, obstacle edge), d_e over (V_obs point, robot
+//      edge)
+//   3. SAT over {n_l} U {n'_j = rot90(B_j - A_j) / (|B_j - A_j| + eps)}: the
+//      across coordinates b above are the axis projections less a constant,
+//      so the intervals come from the same numbers; an obstacle's interval on
+//      its own axes does not depend on the pose and is taken once per
+//      obstacle; delta(n) = min(beta_i - alpha_P, beta_P - alpha_i),
+//      separated if any delta < -eps_sat; soft-min depth
+//      -(1/eta) log sum exp(-eta max(delta, 0)) in max-shifted form
 //   4. sd = sqrt(min(d_v^2, d_e^2)) if separated else -depth
 // The squared norms |v_j|^2 + eps and |v_j| + eps are rotation invariant and
 // are taken once per obstacle from the world-frame edge.
@@ -47,6 +57,9 @@ struct FpConst {
   // robot edge frames for the pools: unit direction u_l = e_l / |e_l|,
   // length |e_l|, and the offsets v_l . u_l, v_l . n_l
   float ux[kMaxFp], uy[kMaxFp], len[kMaxFp], cu[kMaxFp], cn[kMaxFp];
+  // robot interval on its own axis less the offset: alpha_P - v_l . n_l and
+  // beta_P - v_l . n_l
+  float oa[kMaxFp], ob[kMaxFp];
   // Screening certificate constants: rmax bounds |v_l| (every footprint
   // point is within rmax of the pose origin); tau_sep is the distance above
   // which two convex sets are declared separated by the axis test whatever
@@ -55,17 +68,18 @@ struct FpConst {
   float rmax, tau_sep;
 };
 
-// One obstacle in registers.  Slots j >= mi repeat edge mi - 1, which leaves
-// every min / max / any-reduction unchanged; only the soft-min sum masks them.
+// One obstacle in registers, with its pose-independent constants.  Slots
+// j >= mi repeat edge mi - 1, which leaves every min / max / any-reduction
+// unchanged; only the soft-min sum masks them.
 template <int MI>
 struct Obst {
   float ax[MI], ay[MI];   // A_j, world
-  float wx[MI], wy[MI];   // B_j - A_j, world
-  float iv2[MI];          // 1 / (|B_j - A_j|^2 + eps)
-  float il[MI];           // 1 / (|B_j - A_j| + eps)
+  float bx[MI], by[MI];   // B_j, world (extra V_obs points of an open obstacle)
+  float ux[MI], uy[MI];   // (B_j - A_j) / (|B_j - A_j| + eps); n'_j = (-uy, ux)
   float len[MI];          // |B_j - A_j|
+  float olo[MI], ohi[MI]; // interval of (W - A_j) . n'_j over W in V_obs
   int mi;
-  bool closed;            // B_j == A_{j+1} for all j (bitwise): V_obs = {A~_j}
+  bool closed;            // B_j == A_{j+1} for all j (bitwise): V_obs = {A_j}
   bool bad;               // edge count or range invalid, or a non-finite
                           // coordinate: the result is NaN
 };
@@ -118,7 +132,6 @@ __device__ __forceinline__ void load_obstacle(Obst<MI>& o, const float* __restri
   const int n = o.bad ? 1 : (mi < 1 ? 1 : mi);
   const int base = o.bad ? 0 : e0;
   const bool any = !o.bad && mi > 0;
-  float bxs[MI], bys[MI];
 #pragma unroll
   for (int j = 0; j < MI; ++j) {
     const int jj = j < n ? j : n - 1;
@@ -128,26 +141,57 @@ __device__ __forceinline__ void load_obstacle(Obst<MI>& o, const float* __restri
       b0 = bx[base + jj]; b1 = by[base + jj];
     }
     o.ax[j] = a0; o.ay[j] = a1;
-    bxs[j] = b0; bys[j] = b1;
+    o.bx[j] = b0; o.by[j] = b1;
     const float dx = b0 - a0, dy = b1 - a1;
-    o.wx[j] = dx; o.wy[j] = dy;
-    edge_consts(dx, dy, eps, o.iv2[j], o.il[j]);
+    float iv2, il;
+    edge_consts(dx, dy, eps, iv2, il);
+    o.ux[j] = dx * il;
+    o.uy[j] = dy * il;
     o.len[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy));
   }
   bool finite = true;
 #pragma unroll
   for (int j = 0; j < MI; ++j)
-    finite = finite && isfinite(o.ax[j]) && isfinite(o.ay[j]) && isfinite(bxs[j]) && isfinite(bys[j]);
+    finite = finite && isfinite(o.ax[j]) && isfinite(o.ay[j]) && isfinite(o.bx[j]) && isfinite(o.by[j]);
   o.bad = o.bad || !finite;
   bool closed = mi >= 3;
 #pragma unroll
   for (int j = 0; j < MI; ++j) {
     const float nx = (j + 1 < mi) ? o.ax[(j + 1) % MI] : o.ax[0];
     const float ny = (j + 1 < mi) ? o.ay[(j + 1) % MI] : o.ay[0];
-    if (j < mi) closed = closed && (__float_as_uint(bxs[j]) == __float_as_uint(nx)) &&
-                         (__float_as_uint(bys[j]) == __float_as_uint(ny));
+    if (j < mi) closed = closed && (__float_as_uint(o.bx[j]) == __float_as_uint(nx)) &&
+                         (__float_as_uint(o.by[j]) == __float_as_uint(ny));
   }
   o.closed = closed;
+  // own-axis intervals (Sec. IV-C), relative to A_j: pose independent
+#pragma unroll
+  for (int j = 0; j < MI; ++j) {
+    float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
+#pragma unroll
+    for (int k = 0; k < MI; ++k) {
+      const float q = fmaf(o.ay[k] - o.ay[j], o.ux[j], -((o.ax[k] - o.ax[j]) * o.uy[j]));
+      lo = fminf(lo, q);
+      hi = fmaxf(hi, q);
+    }
+    if (!closed) {
+#pragma unroll
+      for (int k = 0; k < MI; ++k) {
+        const float q = fmaf(o.by[k] - o.ay[j], o.ux[j], -((o.bx[k] - o.ax[j]) * o.uy[j]));
+        lo = fminf(lo, q);
+        hi = fmaxf(hi, q);
+      }
+    }
+    o.olo[j] = lo;
+    o.ohi[j] = hi;
+  }
+}
+
+// The footprint rotated by a stage heading (c, s) = (cos, sin): slot l of rf
+// holds (R v_l, R u_l), u_l the unit direction of robot edge l.
+__device__ __forceinline__ float4 rotated_slot(const FpConst& F, int l, float c, float s) {
+  const float vx = F.vx[l], vy = F.vy[l], ux = F.ux[l], uy = F.uy[l];
+  return make_float4(fmaf(c, vx, -(s * vy)), fmaf(s, vx, c * vy), fmaf(c, ux, -(s * uy)),
+                     fmaf(s, ux, c * uy));
 }
 
 // Squared distance from point (px, py) to the segment [a, a + v], with
@@ -159,26 +203,6 @@ __device__ __forceinline__ float seg_d2(float px, float py, float ax, float ay, 
   const float t = clamp01(u);
   const float rx = fmaf(-t, vx, wx), ry = fmaf(-t, vy, wy);
   return fmaf(rx, rx, ry * ry);
-}
-
-// Per-stage local quantities of one obstacle.
-template <int MI>
-struct Local {
-  float tax[MI], tay[MI];  // A~_j
-  float vx[MI], vy[MI];    // v_j = R^T (B_j - A_j)
-  float nx[MI], ny[MI];    // n'_j
-};
-
-template <int MI>
-__device__ __forceinline__ void to_local(const Obst<MI>& o, float c, float s, float px, float py,
-                                         Local<MI>& L) {
-#pragma unroll
-  for (int j = 0; j < MI; ++j) {
-    local_point(o.ax[j], o.ay[j], c, s, px, py, L.tax[j], L.tay[j]);
-    local_vector(o.wx[j], o.wy[j], c, s, L.vx[j], L.vy[j]);
-    L.nx[j] = -L.vy[j] * o.il[j];
-    L.ny[j] = L.vx[j] * o.il[j];
-  }
 }
 
 // Distance term of a point against a segment, in the segment's frame: with
@@ -193,68 +217,63 @@ __device__ __forceinline__ float frame_d2(float a, float b, float L) {
 }
 
 // sd(P0(x), P^i) of one obstacle at one stage (Sec. IV-D).  MF is the number
-// of footprint slots evaluated: the exact m (3..8) or 16 (padded).
+// of footprint slots evaluated: the exact m (3..8) or 16 (padded); rf holds
+// the footprint rotated by the stage heading (rotated_slot, MF slots) and
+// (px, py) is the stage position.
 template <int MF, int MI>
-__device__ __forceinline__ float obstacle_sd(const FpConst& F, const Obst<MI>& o, float c, float s,
-                                             float px, float py) {
-  Local<MI> L;
-  to_local(o, c, s, px, py, L);
-  // obstacle edge frames: unit direction, and A~_j's coordinates in it
-  float ux[MI], uy[MI], ca[MI], cb[MI];
+__device__ __forceinline__ float obstacle_sd(const FpConst& F, const Obst<MI>& o,
+                                             const float4* rf, float px, float py) {
+  // the obstacle translated to the pose origin, and its edge frames' offsets
+  // ca = (A_j - p) . u_j, cb = (A_j - p) . n'_j
+  float tax[MI], tay[MI], ca[MI], cb[MI];
 #pragma unroll
   for (int j = 0; j < MI; ++j) {
-    ux[j] = L.vx[j] * o.il[j];
-    uy[j] = L.vy[j] * o.il[j];
-    ca[j] = fmaf(L.tax[j], ux[j], L.tay[j] * uy[j]);
-    cb[j] = fmaf(L.tax[j], L.nx[j], L.tay[j] * L.ny[j]);
+    tax[j] = o.ax[j] - px;
+    tay[j] = o.ay[j] - py;
+    ca[j] = fmaf(tax[j], o.ux[j], tay[j] * o.uy[j]);
+    cb[j] = fmaf(tay[j], o.ux[j], -(tax[j] * o.uy[j]));
   }
 
-  // Robot vertices against obstacle edges (d_v, Sec. IV-B), with the robot's
-  // interval on every obstacle axis (Sec. IV-C).
+  // Robot vertices against obstacle edges (d_v, Sec. IV-B); the across
+  // coordinate b is the robot's projection on n'_j less cb_j (Sec. IV-C).
   float dv2 = __builtin_huge_valf(), de2 = __builtin_huge_valf();
   float rlo[MI], rhi[MI];
 #pragma unroll
   for (int j = 0; j < MI; ++j) { rlo[j] = __builtin_huge_valf(); rhi[j] = -__builtin_huge_valf(); }
 #pragma unroll
   for (int l = 0; l < MF; ++l) {
+    const float4 r = rf[l];
 #pragma unroll
     for (int j = 0; j < MI; ++j) {
-      const float q = fmaf(F.vx[l], L.nx[j], F.vy[l] * L.ny[j]);
-      rlo[j] = fminf(rlo[j], q);
-      rhi[j] = fmaxf(rhi[j], q);
-      const float a = fmaf(F.vx[l], ux[j], fmaf(F.vy[l], uy[j], -ca[j]));
-      dv2 = fminf(dv2, frame_d2(a, q - cb[j], o.len[j]));
+      const float a = fmaf(r.x, o.ux[j], fmaf(r.y, o.uy[j], -ca[j]));
+      const float b = fmaf(r.y, o.ux[j], fmaf(-r.x, o.uy[j], -cb[j]));
+      rlo[j] = fminf(rlo[j], b);
+      rhi[j] = fmaxf(rhi[j], b);
+      dv2 = fminf(dv2, frame_d2(a, b, o.len[j]));
     }
   }
-  // Obstacle vertices against robot edges (d_e), with the obstacle's
-  // interval on every axis, accumulated vertex by vertex over V_obs.
-  float ra_lo[MF], ra_hi[MF];    // obstacle interval on robot axis n_l
-  float oa_lo[MI], oa_hi[MI];    // obstacle interval on its own axis n'_j
+  // Obstacle points against robot edges (d_e): in robot edge l's frame
+  // (U = R u_l, N = R n_l = (U_y, -U_x)), b is the obstacle's projection on
+  // the robot axis less v_l . n_l.
+  float ra_lo[MF], ra_hi[MF];
 #pragma unroll
   for (int l = 0; l < MF; ++l) { ra_lo[l] = __builtin_huge_valf(); ra_hi[l] = -__builtin_huge_valf(); }
-#pragma unroll
-  for (int j = 0; j < MI; ++j) { oa_lo[j] = __builtin_huge_valf(); oa_hi[j] = -__builtin_huge_valf(); }
   auto visit = [&](float wx, float wy) {
 #pragma unroll
     for (int l = 0; l < MF; ++l) {
-      const float p = fmaf(wx, F.nx[l], wy * F.ny[l]);
-      ra_lo[l] = fminf(ra_lo[l], p);
-      ra_hi[l] = fmaxf(ra_hi[l], p);
-      const float a = fmaf(wx, F.ux[l], fmaf(wy, F.uy[l], -F.cu[l]));
-      de2 = fminf(de2, frame_d2(a, p - F.cn[l], F.len[l]));
-    }
-#pragma unroll
-    for (int j = 0; j < MI; ++j) {
-      const float p = fmaf(wx, L.nx[j], wy * L.ny[j]);
-      oa_lo[j] = fminf(oa_lo[j], p);
-      oa_hi[j] = fmaxf(oa_hi[j], p);
+      const float4 r = rf[l];
+      const float a = fmaf(wx, r.z, fmaf(wy, r.w, -F.cu[l]));
+      const float b = fmaf(wx, r.w, fmaf(-wy, r.z, -F.cn[l]));
+      ra_lo[l] = fminf(ra_lo[l], b);
+      ra_hi[l] = fmaxf(ra_hi[l], b);
+      de2 = fminf(de2, frame_d2(a, b, F.len[l]));
     }
   };
 #pragma unroll
-  for (int k = 0; k < MI; ++k) visit(L.tax[k], L.tay[k]);
+  for (int k = 0; k < MI; ++k) visit(tax[k], tay[k]);
   if (!o.closed) {
 #pragma unroll
-    for (int k = 0; k < MI; ++k) visit(L.tax[k] + L.vx[k], L.tay[k] + L.vy[k]);
+    for (int k = 0; k < MI; ++k) visit(o.bx[k] - px, o.by[k] - py);
   }
 
   // Overlaps and the separating-axis test.
@@ -262,12 +281,12 @@ __device__ __forceinline__ float obstacle_sd(const FpConst& F, const Obst<MI>& o
   bool sep = false;
 #pragma unroll
   for (int l = 0; l < MF; ++l) {
-    dl[l] = fminf(ra_hi[l] - F.pa[l], F.pb[l] - ra_lo[l]);
+    dl[l] = fminf(ra_hi[l] - F.oa[l], F.ob[l] - ra_lo[l]);
     sep = sep || (dl[l] < -F.eps_sat);
   }
 #pragma unroll
   for (int j = 0; j < MI; ++j) {
-    dl[MF + j] = fminf(oa_hi[j] - rlo[j], rhi[j] - oa_lo[j]);
+    dl[MF + j] = fminf(o.ohi[j] - rlo[j], rhi[j] - o.olo[j]);
     sep = sep || (dl[MF + j] < -F.eps_sat);
   }
 

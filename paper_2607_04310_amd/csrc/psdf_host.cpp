@@ -117,6 +117,8 @@ int prepare_footprint(const float* xy, int m, const psdf_params* params, FpConst
     f.len[l] = (float)len;
     f.cu[l] = (float)((vx[l] * ex + vy[l] * ey) / len);
     f.cn[l] = (float)(vx[l] * nx + vy[l] * ny);
+    f.oa[l] = (float)(lo - (vx[l] * nx + vy[l] * ny));
+    f.ob[l] = (float)(hi - (vx[l] * nx + vy[l] * ny));
   }
   // certificate constants (see FpConst)
   double rmax = 0.0, max_ext = 0.0;
@@ -138,6 +140,7 @@ int prepare_footprint(const float* xy, int m, const psdf_params* params, FpConst
     f.pa[l] = f.pa[m - 1]; f.pb[l] = f.pb[m - 1];
     f.ux[l] = f.ux[m - 1]; f.uy[l] = f.uy[m - 1]; f.len[l] = f.len[m - 1];
     f.cu[l] = f.cu[m - 1]; f.cn[l] = f.cn[m - 1];
+    f.oa[l] = f.oa[m - 1]; f.ob[l] = f.ob[m - 1];
   }
   return PSDF_OK;
 }

@@ -33,6 +33,7 @@ __global__ __launch_bounds__(BLK) void main_kernel(FpConst F, const float* __res
                                                     uint64_t* __restrict__ aux) {
   constexpr int NW = BLK / 64;
   __shared__ float4 st[kMaxStageBlock];
+  __shared__ float4 rft[kMaxStageBlock * MF];
   __shared__ uint64_t wk[NW][kMaxStageBlock];
   __shared__ uint64_t wa[NW][kMaxStageBlock];
   const int s0 = blockIdx.y * SB;
@@ -47,12 +48,7 @@ __global__ __launch_bounds__(BLK) void main_kernel(FpConst F, const float* __res
   int e0 = 0, mi = 0;
   if (active) { e0 = off[i]; mi = off[i + 1] - e0; }
 
-  for (int t = threadIdx.x; t < ns; t += BLK) {
-    const float* p = poses + 3 * (s0 + t);
-    float sn, cs;
-    sincosf(p[2], &sn, &cs);
-    st[t] = make_float4(cs, sn, p[0], p[1]);
-  }
+  fill_stage_table<MF>(F, poses, s0, ns, st, rft, BLK);
   __syncthreads();
 
   if (wave_base < M) {
@@ -67,7 +63,7 @@ __global__ __launch_bounds__(BLK) void main_kernel(FpConst F, const float* __res
         }
       }
     };
-    wave_stages<MF, MI>(F, ax, ay, bx, by, e0, mi, E, active, false, wave_base, ns, st, emit);
+    wave_stages<MF, MI>(F, ax, ay, bx, by, e0, mi, E, active, false, wave_base, ns, st, rft, emit);
   } else if (NW > 1 && lane == 0) {
     for (int t = 0; t < ns; ++t) { wk[w][t] = kEmptyKey; wa[w][t] = 0; }
   }
@@ -116,6 +112,8 @@ hipError_t launch_main_mf(int mi_class, const LaunchShape& ls, const FpConst& F,
 // obstacles); +inf for an empty obstacle, NaN for a non-finite pose or an
 // invalid obstacle.  Same obstacle_sd as main_kernel, so the row minimum is
 // the per-stage minimum bit for bit.
+constexpr int kSdmatStageBlock = 4;
+
 template <int MF, int MI>
 __global__ __launch_bounds__(256) void sdmat_kernel(FpConst F, const float* __restrict__ poses,
                                                      int N, int SB, const float* __restrict__ ax,
@@ -124,19 +122,15 @@ __global__ __launch_bounds__(256) void sdmat_kernel(FpConst F, const float* __re
                                                      const float* __restrict__ by,
                                                      const int* __restrict__ off, int E, int M,
                                                      float* __restrict__ sd) {
-  __shared__ float4 st[kMaxStageBlock];
+  __shared__ float4 st[kSdmatStageBlock];
+  __shared__ float4 rft[kSdmatStageBlock * MF];
   const int s0 = blockIdx.y * SB;
   const int ns = min(SB, N - s0);
   const int i = blockIdx.x * 256 + threadIdx.x;
   const bool active = i < M;
   int e0 = 0, mi = 0;
   if (active) { e0 = off[i]; mi = off[i + 1] - e0; }
-  for (int t = threadIdx.x; t < ns; t += 256) {
-    const float* p = poses + 3 * (s0 + t);
-    float sn, cs;
-    sincosf(p[2], &sn, &cs);
-    st[t] = make_float4(cs, sn, p[0], p[1]);
-  }
+  fill_stage_table<MF>(F, poses, s0, ns, st, rft, 256);
   __syncthreads();
   if (!active) return;
   Obst<MI> o;
@@ -145,12 +139,10 @@ __global__ __launch_bounds__(256) void sdmat_kernel(FpConst F, const float* __re
     const float4 q = st[t];
     const bool pose_ok = isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && isfinite(q.w);
     float v = __builtin_huge_valf();
-    if (mi != 0) v = pose_ok ? obstacle_sd<MF, MI>(F, o, q.x, q.y, q.z, q.w) : __builtin_nanf("");
+    if (mi != 0) v = pose_ok ? obstacle_sd<MF, MI>(F, o, rft + t * MF, q.z, q.w) : __builtin_nanf("");
     sd[(size_t)(s0 + t) * M + i] = v;
   }
 }
-
-constexpr int kSdmatStageBlock = 4;
 
 template <int MF>
 hipError_t launch_sdmat_mf(int mi_class, const FpConst& F, const float* poses, int N,

@@ -164,6 +164,7 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
   __shared__ uint8_t cand[kPoolCap];
   __shared__ int cand_o[kPoolCap];
   __shared__ uint64_t wkey[kScreenThreads / 64];
+  __shared__ float4 rf[MF];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int s = A.stages[blockIdx.x];
@@ -175,6 +176,7 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
   float sn, cs;
   sincosf(p[2], &sn, &cs);
   const bool pose_ok = isfinite(px) && isfinite(py) && isfinite(cs) && isfinite(sn);
+  if (tid < MF) rf[tid] = rotated_slot(F, tid, cs, sn);   // read after the block reductions below
   const int M = in.M, Eend = in.edge_off + in.E;
   const int* off = A.off + in.obst_off;
 
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
       load_obstacle<MI>(ob, A.ax, A.ay, A.bx, A.by, e0, mi, Eend, F.eps);
       if (act && e0 < in.edge_off) ob.bad = true;
       uint32_t kk = 0xffffffffu;
-      if (act && mi != 0) kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, cs, sn, px, py)) : 0u;
+      if (act && mi != 0) kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, rf, px, py)) : 0u;
       const uint64_t key = kk == 0xffffffffu ? kEmptyKey : (((uint64_t)kk << 32) | (uint32_t)o);
       const uint64_t wmin = wave_min_u64(key);
       best = wmin < best ? wmin : best;
@@ -394,6 +396,7 @@ template <int MF, int MI>
 __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int max_tiles) {
   __shared__ int s_item;
   __shared__ uint64_t wk[4];
+  __shared__ float4 rf[MF];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int n_failed = (int)__hip_atomic_load(&A.ctrl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (;;) {
@@ -411,6 +414,8 @@ __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int 
       float sn, cs;
       sincosf(p[2], &sn, &cs);
       const bool pose_ok = isfinite(px) && isfinite(py) && isfinite(cs) && isfinite(sn);
+      if (tid < MF) rf[tid] = rotated_slot(F, tid, cs, sn);
+      __syncthreads();
       const int o = tile * 256 + tid;
       const bool act = o < in.M;
       int e0 = 0, mi = 0;
@@ -423,7 +428,7 @@ __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int 
       load_obstacle<MI>(ob, A.ax, A.ay, A.bx, A.by, e0, mi, in.edge_off + in.E, F.eps);
       if (act && e0 < in.edge_off) ob.bad = true;
       uint32_t kk = 0xffffffffu;
-      if (act && mi != 0) kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, cs, sn, px, py)) : 0u;
+      if (act && mi != 0) kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, rf, px, py)) : 0u;
       const uint64_t key = kk == 0xffffffffu ? kEmptyKey : (((uint64_t)kk << 32) | (uint32_t)o);
       const uint64_t wmin = wave_min_u64(key);
       if (lane == 0) wk[w] = wmin;

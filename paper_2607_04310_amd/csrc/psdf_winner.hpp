@@ -80,9 +80,27 @@ __device__ __forceinline__ void stage_footprint(FpLds& L, const FpConst& F) {
   }
 }
 
+// Stage table of a block of ns stages starting at pose s0 (poses float[][3]):
+// st[t] = (cos, sin, x, y) and rft[t * MF + l] = the footprint rotated by
+// stage t's heading.  Filled by the whole work-group (nthreads lanes); the
+// caller synchronises before use.
+template <int MF>
+__device__ __forceinline__ void fill_stage_table(const FpConst& F, const float* __restrict__ poses,
+                                                 int s0, int ns, float4* st, float4* rft,
+                                                 int nthreads) {
+  for (int idx = threadIdx.x; idx < ns * MF; idx += nthreads) {
+    const int t = idx / MF, l = idx - t * MF;
+    const float* p = poses + 3 * (s0 + t);
+    float sn, cs;
+    sincosf(p[2], &sn, &cs);
+    if (l == 0) st[t] = make_float4(cs, sn, p[0], p[1]);
+    rft[idx] = rotated_slot(F, l, cs, sn);
+  }
+}
+
 // Per-stage minimum over one wave's obstacles (lane <-> obstacle, edges
 // [e0, e0 + mi) held in registers) for the ns stages of the table st (c, s,
-// px, py).  For each stage emit(t, key, aux) receives the wave's minimum key
+// px, py) with their rotated footprints rft[t * MF + l] (rotated_slot).  For each stage emit(t, key, aux) receives the wave's minimum key
 // (orderable(sd) << 32 | obase + lane of the first minimum, or the empty
 // key) and that lane's (e0 << 32 | mi).  A wave whose obstacles all have at
 // most one edge (free segments) takes the one-edge specialisation, which is
@@ -93,7 +111,7 @@ __device__ __forceinline__ void wave_stages_t(const FpConst& F, const float* __r
                                               const float* __restrict__ bx,
                                               const float* __restrict__ by, int e0, int mi,
                                               int Eend, bool active, bool bad, int obase, int ns,
-                                              const float4* st, Emit emit) {
+                                              const float4* st, const float4* rft, Emit emit) {
   Obst<MIX> o;
   load_obstacle<MIX>(o, ax, ay, bx, by, e0, mi, Eend, F.eps);
   o.bad = o.bad || bad;
@@ -104,7 +122,8 @@ __device__ __forceinline__ void wave_stages_t(const FpConst& F, const float* __r
     // pipeline would otherwise drop the NaN operands)
     const bool pose_ok = isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && isfinite(q.w);
     uint32_t k = 0xffffffffu;
-    if (contributes) k = pose_ok ? orderable(obstacle_sd<MF, MIX>(F, o, q.x, q.y, q.z, q.w)) : 0u;
+    if (contributes)
+      k = pose_ok ? orderable(obstacle_sd<MF, MIX>(F, o, rft + t * MF, q.z, q.w)) : 0u;
     const uint32_t kmin = wave_min_u32(k);
     uint64_t key = kEmptyKey, a = 0;
     if (kmin != 0xffffffffu) {
@@ -123,12 +142,12 @@ __device__ __forceinline__ void wave_stages(const FpConst& F, const float* __res
                                             const float* __restrict__ bx,
                                             const float* __restrict__ by, int e0, int mi, int Eend,
                                             bool active, bool bad, int obase, int ns,
-                                            const float4* st, Emit emit) {
+                                            const float4* st, const float4* rft, Emit emit) {
   const bool segments = __ballot(active && mi > 1) == 0;
   if (MI > 1 && segments)
-    wave_stages_t<MF, 1>(F, ax, ay, bx, by, e0, mi, Eend, active, bad, obase, ns, st, emit);
+    wave_stages_t<MF, 1>(F, ax, ay, bx, by, e0, mi, Eend, active, bad, obase, ns, st, rft, emit);
   else
-    wave_stages_t<MF, MI>(F, ax, ay, bx, by, e0, mi, Eend, active, bad, obase, ns, st, emit);
+    wave_stages_t<MF, MI>(F, ax, ay, bx, by, e0, mi, Eend, active, bad, obase, ns, st, rft, emit);
 }
 
 // Whole-wave call with uniform arguments; the obstacle owns edges

@@ -31,10 +31,11 @@ PEAK_FP32_TFLOPS = 157.3
 # for a copy kernel of known size), valid only while the kernel's sources
 # hash to the value recorded beside it.
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "main_kernel_c2_hbm_counters.md")
+# The per-stage-minimum kernel's own sources: its code and instantiation, the
+# launch-shape choice, the build flags.
 KERNEL_SOURCES = [os.path.join("paper_2607_04310_amd", "csrc", f) for f in (
     "psdf_device.hpp", "psdf_kernels.hpp", "psdf_winner.hpp", "psdf_inst_mf6.hip",
-    "psdf_plain.hip", "psdf_host.cpp", "psdf_host.hpp")] + [os.path.join("paper_2607_04310_amd",
-                                                                         "build.py")]
+    "psdf_host.cpp", "psdf_host.hpp")] + [os.path.join("paper_2607_04310_amd", "build.py")]
 
 
 def kernel_source_hash():

@@ -23,13 +23,86 @@ constexpr int kEpiWaves = 4;   // stages per epilogue work-group
 // and 1 each of d / edge / obst, grad and hj may be null; hj[s] receives the
 // linearised safety constraint (phi - dmin, -dphi/dx, -dphi/dy, -dphi/dtheta)
 // (mode 1 only).
+struct EpiOut {
+  uint64_t* keys;
+  const float* gout;
+  int mode;
+  float dmin;
+  float* d;
+  int* edge;
+  int* obst;
+  float* grad;
+  float* hj;
+};
+
+// One wave finishes stage s from its winning key: the winner's edge range
+// (e0, mi) comes from the aux word (have_aux) or from the offsets; the wave
+// recomputes the winner (winner_adjoint) and lane 0 writes the outputs.
+__device__ __forceinline__ void epilogue_finish(const FpConst& F, FpLds& FL, WinnerLds& WL,
+                                                const float* __restrict__ ax,
+                                                const float* __restrict__ ay,
+                                                const float* __restrict__ bx,
+                                                const float* __restrict__ by,
+                                                const int* __restrict__ off, int E, int M, int s,
+                                                float px, float py, float cs, float sn,
+                                                uint64_t key, int e0, int mi, bool have_aux,
+                                                float scale, const EpiOut& O) {
+  const int lane = threadIdx.x & 63;
+  const float nan = __builtin_nanf("");
+  float dv, g[3] = {0.f, 0.f, 0.f};
+  int ev = -1, ov = -1;
+  const int i = (int)(key & 0xffffffffu);
+  bool valid = key != kEmptyKey && (key >> 32) != 0 && (uint64_t)i < (uint64_t)M;
+  if (valid && !have_aux) {
+    e0 = off[i];
+    mi = off[i + 1] - e0;
+  }
+  valid = valid && mi >= 1 && mi <= kMaxObst && e0 >= 0 && e0 <= E - mi;
+  if (key == kEmptyKey) {
+    dv = __builtin_huge_valf();
+  } else if (!valid) {
+    // NaN result, or a key that names no obstacle of this edge set
+    dv = nan;
+    g[0] = g[1] = g[2] = nan;
+  } else {
+    int jstar = 0;
+    winner_adjoint(F, FL, WL, ax, ay, bx, by, e0, mi, cs, sn, px, py, O.mode != 0, jstar, g);
+    dv = from_orderable((uint32_t)(key >> 32));
+    ov = i;
+    ev = e0 + jstar;
+  }
+  if (lane != 0) return;
+  if (O.mode == 2) {
+    O.grad[3 * s + 0] = g[0] * scale;
+    O.grad[3 * s + 1] = g[1] * scale;
+    O.grad[3 * s + 2] = g[2] * scale;
+    return;
+  }
+  if (O.d) {
+    O.d[s] = dv;
+    O.edge[s] = ev;
+    O.obst[s] = ov;
+  }
+  if (O.mode == 1 && O.grad) {
+    O.grad[3 * s + 0] = g[0];
+    O.grad[3 * s + 1] = g[1];
+    O.grad[3 * s + 2] = g[2];
+  }
+  if (O.mode == 1 && O.hj) {
+    O.hj[4 * s + 0] = dv - O.dmin;
+    O.hj[4 * s + 1] = -g[0];
+    O.hj[4 * s + 2] = -g[1];
+    O.hj[4 * s + 3] = -g[2];
+  }
+}
+
+// One wave per stage: reduce the stage's gx partial keys (a few columns per
+// lane), then finish the stage.
 __global__ __launch_bounds__(64 * kEpiWaves) void epilogue_kernel(
     FpConst F, const float* __restrict__ poses, int N, const float* __restrict__ ax,
     const float* __restrict__ ay, const float* __restrict__ bx, const float* __restrict__ by,
     const int* __restrict__ off, int E, int M, const uint64_t* __restrict__ partial, int gx,
-    uint64_t* __restrict__ keys, const float* __restrict__ gout, int mode, float dmin,
-    float* __restrict__ d, int* __restrict__ edge, int* __restrict__ obst,
-    float* __restrict__ grad, float* __restrict__ hj) {
+    EpiOut O) {
   __shared__ FpLds fl[kEpiWaves];
   __shared__ WinnerLds wl[kEpiWaves];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -44,15 +117,15 @@ __global__ __launch_bounds__(64 * kEpiWaves) void epilogue_kernel(
   // the winning column's aux word carries the obstacle's edge range
   const uint64_t* prow = partial + (size_t)s * gx;
   const uint64_t* arow = partial + (size_t)N * gx + (size_t)s * gx;
-  if (mode == 2) {
-    key = keys[s];
-    scale = gout[s];
+  if (O.mode == 2) {
+    key = O.keys[s];
+    scale = O.gout[s];
   } else if (lane < gx) {
     key = prow[lane];
     a = arow[lane];
   }
   stage_footprint(fl[w], F);
-  if (mode != 2) {
+  if (O.mode != 2) {
     // keys are unique (they carry the obstacle index), so the scan order is
     // free: four columns per lane in flight
     int j = lane + 64;
@@ -74,65 +147,73 @@ __global__ __launch_bounds__(64 * kEpiWaves) void epilogue_kernel(
 
   int e0 = 0, mi = 0;
   bool have_aux = false;
-  if (mode != 2) {
+  if (O.mode != 2) {
     const uint64_t kmin = wave_min_u64(key);
     const uint64_t hit = __ballot(key == kmin);
     const int first = __ffsll((unsigned long long)hit) - 1;
     a = __shfl((unsigned long long)a, first);
     key = kmin;
-    if (lane == 0) keys[s] = key;
+    if (lane == 0) O.keys[s] = key;
     e0 = (int)(uint32_t)(a >> 32);
     mi = (int)(uint32_t)(a & 0xffffffffu);
     have_aux = true;
   }
   wave_sync();
+  epilogue_finish(F, fl[w], wl[w], ax, ay, bx, by, off, E, M, s, px, py, cs, sn, key, e0, mi,
+                  have_aux, scale, O);
+}
 
-  const float nan = __builtin_nanf("");
-  float dv, g[3] = {0.f, 0.f, 0.f};
-  int ev = -1, ov = -1;
-  const int i = (int)(key & 0xffffffffu);
-  bool valid = key != kEmptyKey && (key >> 32) != 0 && (uint64_t)i < (uint64_t)M;
-  if (valid && !have_aux) {
-    e0 = off[i];
-    mi = off[i + 1] - e0;
+// Many columns (few stages, many obstacles): one work-group per stage
+// reduces the keys alone (eight columns per lane in flight), loads the
+// winning column's aux word, and its first wave finishes the stage.
+constexpr int kWideThreads = 256;
+constexpr int kWideColumns = 256;   // wider rows than this take this kernel
+
+__global__ __launch_bounds__(kWideThreads) void epilogue_wide_kernel(
+    FpConst F, const float* __restrict__ poses, int N, const float* __restrict__ ax,
+    const float* __restrict__ ay, const float* __restrict__ bx, const float* __restrict__ by,
+    const int* __restrict__ off, int E, int M, const uint64_t* __restrict__ partial, int gx,
+    EpiOut O) {
+  __shared__ FpLds fl;
+  __shared__ WinnerLds wl;
+  __shared__ uint64_t red[kWideThreads / 64];
+  __shared__ uint64_t s_aux;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int s = blockIdx.x;
+  const uint64_t* prow = partial + (size_t)s * gx;
+  const uint64_t* arow = partial + (size_t)N * gx + (size_t)s * gx;
+  uint64_t key = kEmptyKey;
+  int col = 0;
+  int j = tid;
+  for (; j + 7 * kWideThreads < gx; j += 8 * kWideThreads) {
+    uint64_t k[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) k[u] = prow[j + u * kWideThreads];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k[u] < key) { key = k[u]; col = j + u * kWideThreads; }
   }
-  valid = valid && mi >= 1 && mi <= kMaxObst && e0 >= 0 && e0 <= E - mi;
-  if (key == kEmptyKey) {
-    dv = __builtin_huge_valf();
-  } else if (!valid) {
-    // NaN result, or a key that names no obstacle of this edge set
-    dv = nan;
-    g[0] = g[1] = g[2] = nan;
-  } else {
-    int jstar = 0;
-    winner_adjoint(F, fl[w], wl[w], ax, ay, bx, by, e0, mi, cs, sn, px, py, mode != 0, jstar, g);
-    dv = from_orderable((uint32_t)(key >> 32));
-    ov = i;
-    ev = e0 + jstar;
-  }
-  if (lane != 0) return;
-  if (mode == 2) {
-    grad[3 * s + 0] = g[0] * scale;
-    grad[3 * s + 1] = g[1] * scale;
-    grad[3 * s + 2] = g[2] * scale;
-    return;
-  }
-  if (d) {
-    d[s] = dv;
-    edge[s] = ev;
-    obst[s] = ov;
-  }
-  if (mode == 1 && grad) {
-    grad[3 * s + 0] = g[0];
-    grad[3 * s + 1] = g[1];
-    grad[3 * s + 2] = g[2];
-  }
-  if (mode == 1 && hj) {
-    hj[4 * s + 0] = dv - dmin;
-    hj[4 * s + 1] = -g[0];
-    hj[4 * s + 2] = -g[1];
-    hj[4 * s + 3] = -g[2];
-  }
+  for (; j < gx; j += kWideThreads)
+    if (prow[j] < key) { key = prow[j]; col = j; }
+  const uint64_t wmin = wave_min_u64(key);
+  if (lane == 0) red[w] = wmin;
+  if (w == 0) stage_footprint(fl, F);
+  __syncthreads();
+  uint64_t kmin = red[0];
+#pragma unroll
+  for (int v = 1; v < kWideThreads / 64; ++v) kmin = red[v] < kmin ? red[v] : kmin;
+  // keys are unique, so exactly one thread holds kmin (none if all are empty)
+  if (kmin != kEmptyKey && key == kmin) s_aux = arow[col];
+  __syncthreads();
+  if (w != 0) return;
+  const float* p = poses + 3 * s;
+  const float px = p[0], py = p[1];
+  float sn, cs;
+  sincosf(p[2], &sn, &cs);
+  const uint64_t a = kmin != kEmptyKey ? s_aux : 0;
+  if (lane == 0) O.keys[s] = kmin;
+  epilogue_finish(F, fl, wl, ax, ay, bx, by, off, E, M, s, px, py, cs, sn, kmin,
+                  (int)(uint32_t)(a >> 32), (int)(uint32_t)(a & 0xffffffffu), true, 1.0f, O);
 }
 
 static int mf_slots(int m) { return m <= 8 ? m : 16; }
@@ -165,10 +246,15 @@ hipError_t launch_epilogue(const FpConst& F, const float* poses, int N, const ps
                            const uint64_t* partial, int gx, uint64_t* keys, const float* gout,
                            int mode, float dmin, float* d, int* edge, int* obst, float* grad,
                            float* hj, hipStream_t st) {
-  const int blocks = (N + kEpiWaves - 1) / kEpiWaves;
-  epilogue_kernel<<<blocks, 64 * kEpiWaves, 0, st>>>(F, poses, N, e.ax, e.ay, e.bx, e.by,
-                                                     e.obst_off, e.E, e.M, partial, gx, keys,
-                                                     gout, mode, dmin, d, edge, obst, grad, hj);
+  const EpiOut O{keys, gout, mode, dmin, d, edge, obst, grad, hj};
+  if (mode != 2 && gx > kWideColumns) {
+    epilogue_wide_kernel<<<N, kWideThreads, 0, st>>>(F, poses, N, e.ax, e.ay, e.bx, e.by,
+                                                     e.obst_off, e.E, e.M, partial, gx, O);
+  } else {
+    const int blocks = (N + kEpiWaves - 1) / kEpiWaves;
+    epilogue_kernel<<<blocks, 64 * kEpiWaves, 0, st>>>(F, poses, N, e.ax, e.ay, e.bx, e.by,
+                                                       e.obst_off, e.E, e.M, partial, gx, O);
+  }
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@ import pytest
 
 from paper_2607_04310_amd import inputs
 from parity import check_stages
+from oracle import psdf as oracle_psdf
 
 pytestmark = pytest.mark.gpu
 
@@ -272,3 +273,36 @@ def test_time_stage_min(api):
     poses = torch.tensor(inst.poses, device="cuda")
     ms = api.time_stage_min(inst.footprint, poses, edges, 20)
     assert 0.0 < ms < 5.0
+
+
+@pytest.mark.parametrize("rects", [1 << 16, 1 << 18])
+def test_single_pose_many_obstacles(api, rects):
+    """One pose against up to 262144 obstacles: the partial rows are wide
+    enough for the one-work-group-per-stage reduction; full oracle parity."""
+    inst = inputs.single_pose(rects)
+    st = check(inst, run(api, inst), 1000.0)
+    assert st["stages"] == 1
+
+
+def test_single_pose_max_size_pruned_oracle(api):
+    """The sweep's largest size (4.19 M rectangles, 16.7 M edges, one pose):
+    the GPU's winner checked against the oracle on every obstacle that could
+    beat it.  Bounding circles (numpy, FP64) prune the rest: an obstacle
+    whose circle lies farther than d + 1e-3 from every footprint point cannot
+    have sd <= d."""
+    inst = inputs.single_pose(1 << 22)
+    d, e, o, g = run(api, inst)
+    E = inst.edges.reshape(-1, 4, 4).astype(np.float64)            # (M, 4 edges, 4)
+    ctr = E[:, :, :2].mean(axis=1)
+    rad = np.sqrt(((E[:, :, :2] - ctr[:, None, :]) ** 2).sum(-1)).max(axis=1)
+    p = inst.poses[0].astype(np.float64)
+    rmax = np.sqrt((inst.footprint.astype(np.float64) ** 2).sum(-1)).max()
+    lb = np.sqrt(((ctr - p[:2]) ** 2).sum(-1)) - rad - rmax
+    cand = np.flatnonzero(lb <= float(d[0]) + 1e-3)
+    assert o[0] in cand and len(cand) < 200
+    sub_edges = inst.edges.reshape(-1, 4, 4)[cand].reshape(-1, 4)
+    ref = oracle_psdf(inst.footprint, inst.poses, sub_edges, inputs.csr_offsets([4] * len(cand)))
+    assert abs(float(d[0]) - ref["phi"][0]) <= 1e-5
+    assert cand[ref["obst"][0]] == o[0]
+    gref = ref["grad"][0]
+    assert np.abs(g[0] - gref).max() <= 1e-4 * max(1.0, np.abs(gref).max())

@@ -50,10 +50,10 @@
  *  - keys (device uint64[N]) receives the winner of each stage:
  *    (orderable(sd) << 32) | obstacle, where orderable maps floats to
  *    unsigned integers in the same order (NaN lowest).  psdf_bwd consumes it.
- *  - ws (device, caller-owned) is scratch of at least
+ *  - ws (device, caller-owned, 16-byte aligned) is scratch of at least
  *    psdf_workspace_bytes(N, M) bytes: the per-work-group partial minima
- *    and the winners' edge ranges.
- *    Its content on entry does not matter.
+ *    and the winners' edge ranges, as 16-byte pairs.  Its content on entry
+ *    does not matter.  A misaligned ws gives PSDF_EINVAL.
  */
 #ifndef PSDF_H
 #define PSDF_H

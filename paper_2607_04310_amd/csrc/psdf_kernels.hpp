@@ -6,10 +6,10 @@
 // and evaluates sd for every stage of the work-group's stage block.  Per
 // stage the wave takes the minimum of the orderable sd, the lowest lane
 // holding it names the obstacle (lowest index on ties), and the work-group
-// writes one partial key (orderable(sd) << 32 | obstacle) per stage to
-// partial[stage][blockIdx.x], and the winner's (first edge << 32 | edge
-// count) to aux[stage][blockIdx.x].  The epilogue reduces the partial keys of
-// a stage; no atomics and no initialisation pass are needed.
+// writes one 16-byte partial per stage to partial[stage][blockIdx.x]: the key
+// (orderable(sd) << 32 | obstacle) and the winner's (first edge << 32 | edge
+// count).  The epilogue reduces the partial keys of a stage; no atomics and
+// no initialisation pass are needed.
 #pragma once
 
 #include <hip/hip_ext.h>
@@ -29,8 +29,7 @@ __global__ __launch_bounds__(BLK) void main_kernel(FpConst F, const float* __res
                                                     const float* __restrict__ bx,
                                                     const float* __restrict__ by,
                                                     const int* __restrict__ off, int E, int M,
-                                                    uint64_t* __restrict__ partial,
-                                                    uint64_t* __restrict__ aux) {
+                                                    ulonglong2* __restrict__ partial) {
   constexpr int NW = BLK / 64;
   __shared__ float4 st[kMaxStageBlock];
   __shared__ float4 rft[kMaxStageBlock * MF];
@@ -55,8 +54,7 @@ __global__ __launch_bounds__(BLK) void main_kernel(FpConst F, const float* __res
     auto emit = [&](int t, uint64_t key, uint64_t a) {
       if (lane == 0) {
         if (NW == 1) {
-          partial[(size_t)(s0 + t) * gx + blockIdx.x] = key;
-          aux[(size_t)(s0 + t) * gx + blockIdx.x] = a;
+          partial[(size_t)(s0 + t) * gx + blockIdx.x] = make_ulonglong2(key, a);
         } else {
           wk[w][t] = key;
           wa[w][t] = a;
@@ -74,8 +72,7 @@ __global__ __launch_bounds__(BLK) void main_kernel(FpConst F, const float* __res
 #pragma unroll
       for (int v = 1; v < NW; ++v)
         if (wk[v][t] < k) { k = wk[v][t]; a = wa[v][t]; }
-      partial[(size_t)(s0 + t) * gx + blockIdx.x] = k;
-      aux[(size_t)(s0 + t) * gx + blockIdx.x] = a;
+      partial[(size_t)(s0 + t) * gx + blockIdx.x] = make_ulonglong2(k, a);
     }
   }
 }
@@ -87,14 +84,13 @@ hipError_t launch_main_t(const LaunchShape& ls, const FpConst& F, const float* p
                          const psdf_edges& e, uint64_t* partial, hipStream_t st, hipEvent_t ev0,
                          hipEvent_t ev1) {
   dim3 grid((e.M + ls.blk - 1) / ls.blk, (N + ls.sb - 1) / ls.sb);
-  uint64_t* aux = partial + (size_t)N * grid.x;
+  ulonglong2* pk = reinterpret_cast<ulonglong2*>(partial);
   if (ls.blk == 64)
     hipExtLaunchKernelGGL(main_kernel<MF, MI, 64>, grid, dim3(64), 0, st, ev0, ev1, 0, F, poses,
-                          N, ls.sb, e.ax, e.ay, e.bx, e.by, e.obst_off, e.E, e.M, partial, aux);
+                          N, ls.sb, e.ax, e.ay, e.bx, e.by, e.obst_off, e.E, e.M, pk);
   else
     hipExtLaunchKernelGGL(main_kernel<MF, MI, 256>, grid, dim3(256), 0, st, ev0, ev1, 0, F,
-                          poses, N, ls.sb, e.ax, e.ay, e.bx, e.by, e.obst_off, e.E, e.M, partial,
-                          aux);
+                          poses, N, ls.sb, e.ax, e.ay, e.bx, e.by, e.obst_off, e.E, e.M, pk);
   return hipGetLastError();
 }
 

@@ -114,15 +114,16 @@ __global__ __launch_bounds__(64 * kEpiWaves) void epilogue_kernel(
   const float px = p[0], py = p[1], th = p[2];
   uint64_t key = kEmptyKey, a = 0;
   float scale = 1.0f;
-  // the winning column's aux word carries the obstacle's edge range
-  const uint64_t* prow = partial + (size_t)s * gx;
-  const uint64_t* arow = partial + (size_t)N * gx + (size_t)s * gx;
+  // (key, aux) per column; the winning column's aux word carries the
+  // obstacle's edge range
+  const ulonglong2* prow = reinterpret_cast<const ulonglong2*>(partial) + (size_t)s * gx;
   if (O.mode == 2) {
     key = O.keys[s];
     scale = O.gout[s];
   } else if (lane < gx) {
-    key = prow[lane];
-    a = arow[lane];
+    const ulonglong2 v = prow[lane];
+    key = v.x;
+    a = v.y;
   }
   stage_footprint(fl[w], F);
   if (O.mode != 2) {
@@ -130,16 +131,16 @@ __global__ __launch_bounds__(64 * kEpiWaves) void epilogue_kernel(
     // free: four columns per lane in flight
     int j = lane + 64;
     for (; j + 192 < gx; j += 256) {
-      uint64_t k[4], x[4];
+      ulonglong2 v[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) { k[u] = prow[j + 64 * u]; x[u] = arow[j + 64 * u]; }
+      for (int u = 0; u < 4; ++u) v[u] = prow[j + 64 * u];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (k[u] < key) { key = k[u]; a = x[u]; }
+        if (v[u].x < key) { key = v[u].x; a = v[u].y; }
     }
     for (; j < gx; j += 64) {
-      const uint64_t k = prow[j], x = arow[j];
-      if (k < key) { key = k; a = x; }
+      const ulonglong2 v = prow[j];
+      if (v.x < key) { key = v.x; a = v.y; }
     }
   }
   float sn, cs;
@@ -180,21 +181,20 @@ __global__ __launch_bounds__(kWideThreads) void epilogue_wide_kernel(
   __shared__ uint64_t s_aux;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int s = blockIdx.x;
-  const uint64_t* prow = partial + (size_t)s * gx;
-  const uint64_t* arow = partial + (size_t)N * gx + (size_t)s * gx;
+  const ulonglong2* prow = reinterpret_cast<const ulonglong2*>(partial) + (size_t)s * gx;
   uint64_t key = kEmptyKey;
   int col = 0;
   int j = tid;
   for (; j + 7 * kWideThreads < gx; j += 8 * kWideThreads) {
     uint64_t k[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) k[u] = prow[j + u * kWideThreads];
+    for (int u = 0; u < 8; ++u) k[u] = prow[j + u * kWideThreads].x;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
       if (k[u] < key) { key = k[u]; col = j + u * kWideThreads; }
   }
   for (; j < gx; j += kWideThreads)
-    if (prow[j] < key) { key = prow[j]; col = j; }
+    if (prow[j].x < key) { key = prow[j].x; col = j; }
   const uint64_t wmin = wave_min_u64(key);
   if (lane == 0) red[w] = wmin;
   if (w == 0) stage_footprint(fl, F);
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kWideThreads) void epilogue_wide_kernel(
 #pragma unroll
   for (int v = 1; v < kWideThreads / 64; ++v) kmin = red[v] < kmin ? red[v] : kmin;
   // keys are unique, so exactly one thread holds kmin (none if all are empty)
-  if (kmin != kEmptyKey && key == kmin) s_aux = arow[col];
+  if (kmin != kEmptyKey && key == kmin) s_aux = prow[col].y;
   __syncthreads();
   if (w != 0) return;
   const float* p = poses + 3 * s;
@@ -335,7 +335,8 @@ static int plain_common(const float* footprint, int32_t m, const float* poses, i
 
 size_t psdf_workspace_bytes(int32_t N, int32_t M) {
   if (N <= 0 || M <= 0) return 0;
-  // partial keys and their aux words, one column per work-group of 64 lanes
+  // a 16-byte (key, aux) partial per stage and work-group, at most one
+  // work-group per 64 obstacles
   return 2 * (size_t)N * (size_t)((M + 63) / 64) * sizeof(uint64_t);
 }
 
@@ -354,6 +355,8 @@ static int plain_run(const float* footprint, int32_t m, const float* poses, int3
   const size_t need = psdf_workspace_bytes(N, e.M);
   if (need > 0 && (!ws || ws_bytes < need))
     return set_error(PSDF_EWS, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  if (need > 0 && (reinterpret_cast<uintptr_t>(ws) & 15u) != 0)
+    return set_error(PSDF_EINVAL, "workspace is not 16-byte aligned");
   const LaunchShape ls = tuned_shape(F.m, e.mbar, N, e.M);
   uint64_t* partial = static_cast<uint64_t*>(ws);
   hipError_t err = launch_plain(F, poses, N, e, partial, ls, stream);
@@ -377,6 +380,8 @@ int psdf_time_stage_min(const float* footprint, int32_t m, const float* poses, i
   const size_t need = psdf_workspace_bytes(N, e.M);
   if (!ws || ws_bytes < need)
     return set_error(PSDF_EWS, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  if ((reinterpret_cast<uintptr_t>(ws) & 15u) != 0)
+    return set_error(PSDF_EINVAL, "workspace is not 16-byte aligned");
   const LaunchShape ls = tuned_shape(F.m, e.mbar, N, e.M);
   uint64_t* partial = static_cast<uint64_t*>(ws);
   hipEvent_t a = nullptr, b = nullptr;
@@ -426,6 +431,8 @@ int psdf_constraints(const float* footprint, int32_t m, const float* poses, int3
   const size_t need = psdf_workspace_bytes(N, e.M);
   if (need > 0 && (!ws || ws_bytes < need))
     return set_error(PSDF_EWS, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  if (need > 0 && (reinterpret_cast<uintptr_t>(ws) & 15u) != 0)
+    return set_error(PSDF_EINVAL, "workspace is not 16-byte aligned");
   const LaunchShape ls = tuned_shape(F.m, e.mbar, N, e.M);
   uint64_t* partial = static_cast<uint64_t*>(ws);
   hipError_t err = launch_plain(F, poses, N, e, partial, ls, stream);

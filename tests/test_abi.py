@@ -140,3 +140,15 @@ def test_time_stage_min_validation():
     assert lib.psdf_time_stage_min(fp.ctypes.data_as(ctypes.c_void_p), 4, None, 0,
                                    ctypes.byref(e), ctypes.byref(p), None, 0, 5, None,
                                    ctypes.byref(ms)) == _lib.PSDF_OK and ms.value == 0.0
+
+
+def test_misaligned_workspace_is_rejected():
+    fp = np.ascontiguousarray(RECT)
+    e = _lib.PsdfEdges(1, 1, 1, 1, 1, 4, 1, 4)
+    p = _lib.PsdfParams(1e-12, 1e-6, 1000.0)
+    d = ctypes.c_void_p(16)
+    rc = _lib.lib().psdf_eval(fp.ctypes.data_as(ctypes.c_void_p), 4, ctypes.c_void_p(16), 1,
+                              ctypes.byref(e), ctypes.byref(p), d, d, d, d, ctypes.c_void_p(8),
+                              1 << 30, None)
+    assert rc == _lib.PSDF_EINVAL
+    assert "aligned" in _lib.lib().psdf_last_error().decode()

@@ -56,6 +56,106 @@ __global__ void circle_kernel(const BatchInst* __restrict__ insts, const float* 
   circ[in.circ_off + o] = c;
 }
 
+// Horizon list of each instance (one work-group per instance): every stage
+// position of the instance lies within R of the centre c_p of their bounding
+// box, so for every stage s and obstacle i
+//   |p_s - c_i| - r_i - rmax - gamma >= |c_p - c_i| - R - r_i - rmax - gamma =: hb_i,
+// a lower bound of the stage's circle bound and hence of sd_i.  The
+// kHorizonPool obstacles of lowest hb (about) are the list the instance's
+// stages screen; the smallest hb left out bounds every excluded obstacle at
+// every stage.  A non-finite stage position, or a list longer than
+// kHorizonCap (a tie block), disables the list (-1): the instance's stages
+// then take the full evaluation.
+constexpr int kHorizonPool = 1024;
+
+__global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
+    const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
+    const float* __restrict__ poses, const float4* __restrict__ circ, int* __restrict__ hlist,
+    int* __restrict__ hcount, uint32_t* __restrict__ hrest) {
+  __shared__ int scan[kScreenThreads];
+  __shared__ uint32_t red[kScreenThreads / 64];
+  const int inst = blockIdx.x, tid = threadIdx.x;
+  const BatchInst in = insts[inst];
+  const FpConst& F = fps[inst];
+  const int M = in.M;
+  // bounding box of the stage positions (orderable keys: min of x, y, -x, -y)
+  uint32_t bx0 = 0xffffffffu, by0 = 0xffffffffu, bx1 = 0xffffffffu, by1 = 0xffffffffu;
+  int bad = 0;
+  for (int t = tid; t < in.N; t += kScreenThreads) {
+    const float* p = poses + 3 * (in.pose_off + t);
+    const float x = p[0], y = p[1];
+    if (!(isfinite(x) && isfinite(y))) { bad = 1; continue; }
+    bx0 = min(bx0, orderable(x)); by0 = min(by0, orderable(y));
+    bx1 = min(bx1, orderable(-x)); by1 = min(by1, orderable(-y));
+  }
+  bad = block_sum_i32(bad, scan);
+  bx0 = block_min_u32(bx0, red); by0 = block_min_u32(by0, red);
+  bx1 = block_min_u32(bx1, red); by1 = block_min_u32(by1, red);
+  if (bad > 0 || in.N == 0 || M == 0) {
+    if (tid == 0) { hcount[inst] = -1; hrest[inst] = 0xffffffffu; }
+    return;
+  }
+  const float cx = 0.5f * (from_orderable(bx0) - from_orderable(bx1));
+  const float cy = 0.5f * (from_orderable(by0) - from_orderable(by1));
+  // R = max distance of a stage position from the centre (max via the
+  // orderable image of -d)
+  uint32_t nr = 0xffffffffu;
+  for (int t = tid; t < in.N; t += kScreenThreads) {
+    const float* p = poses + 3 * (in.pose_off + t);
+    const float dx = p[0] - cx, dy = p[1] - cy;
+    nr = min(nr, orderable(-sqrtf(fmaf(dx, dx, dy * dy))));
+  }
+  nr = block_min_u32(nr, red);
+  const float R = -from_orderable(nr) * (1.0f + 1e-6f) + 1e-6f;
+  const float off = R + F.rmax + kLbGamma;
+  uint32_t k[kScreenKeysPerThread];
+  uint32_t kmin = 0xffffffffu, kmax = 0u;
+  int used = 0;
+  const int nq = (M + kScreenThreads - 1) / kScreenThreads;   // live key slots
+#pragma unroll
+  for (int q = 0; q < kScreenKeysPerThread; ++q) {
+    const int o = tid + kScreenThreads * q;
+    uint32_t key = 0xffffffffu;
+    if (q < nq && o < M) {
+      const float4 c = circ[in.circ_off + o];
+      if (c.x == c.x) {
+        const float dx = cx - c.x, dy = cy - c.y;
+        key = orderable(sqrtf(fmaf(dx, dx, dy * dy)) - c.z - off);
+      }
+    }
+    k[q] = key;
+    if (key != 0xffffffffu) { kmin = min(kmin, key); kmax = max(kmax, key); ++used; }
+  }
+  kmin = block_min_u32(kmin, red);
+  kmax = ~block_min_u32(~kmax, red);
+  const int n_used = block_sum_i32(used, scan);
+  const uint32_t T = n_used > kHorizonPool
+                         ? block_threshold<kScreenKeysPerThread>(k, nq, kmin, kmax,
+                                                                 kHorizonPool / 2, kHorizonPool,
+                                                                 scan)
+                         : 0xfffffffeu;
+  int mine = 0;
+  uint32_t rest = 0xffffffffu;
+#pragma unroll
+  for (int q = 0; q < kScreenKeysPerThread; ++q) {
+    if (k[q] == 0xffffffffu) continue;
+    if (k[q] <= T) ++mine;
+    else rest = min(rest, k[q]);
+  }
+  rest = block_min_u32(rest, red);
+  int total = 0;
+  int at = block_scan(mine, scan, &total);
+  if (total <= kHorizonCap) {
+#pragma unroll
+    for (int q = 0; q < kScreenKeysPerThread; ++q)
+      if (k[q] != 0xffffffffu && k[q] <= T) hlist[in.circ_off + at++] = tid + kScreenThreads * q;
+  }
+  if (tid == 0) {
+    hcount[inst] = total <= kHorizonCap ? total : -1;
+    hrest[inst] = rest;
+  }
+}
+
 struct Shape {
   int sb;       // stages per work item
   int nw;       // waves per work-group (obstacles per tile = 64 nw)
@@ -97,6 +197,9 @@ struct psdf_batch_plan {
   int* d_failed = nullptr;
   unsigned* d_sctrl = nullptr;
   float4* d_circ = nullptr;   // bounding circles, sum M
+  int* d_hlist = nullptr;     // horizon lists, sum M
+  int* d_hcount = nullptr;    // per instance
+  uint32_t* d_hrest = nullptr;
   struct SGroup { int mf, start, count, max_tiles; };
   std::vector<SGroup> sgroups;
   int max_M = 0;
@@ -443,6 +546,7 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
   a.fps = p->d_fp; a.insts = p->d_inst; a.stage_inst = p->d_stage_inst;
   a.poses = poses; a.ax = ax; a.ay = ay; a.bx = bx; a.by = by; a.off = off;
   a.circ = p->d_circ;
+  a.hlist = p->d_hlist; a.hcount = p->d_hcount; a.hrest = p->d_hrest;
   a.theta = theta; a.pool = pool; a.topk = topk; a.keys = keys;
   a.stage_cand = stage_cand; a.stage_cert = stage_cert; a.cand_keys = cand_keys;
   timer_begin(stream);
@@ -451,6 +555,12 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
     dim3 grid((p->max_M + 255) / 256, p->n_inst);
     circle_kernel<<<grid, 256, 0, stream>>>(p->d_inst, ax, ay, bx, by, off, p->d_circ);
     err = hipGetLastError();
+    if (err == hipSuccess) {
+      horizon_kernel<<<p->n_inst, kScreenThreads, 0, stream>>>(p->d_fp, p->d_inst, poses,
+                                                               p->d_circ, p->d_hlist,
+                                                               p->d_hcount, p->d_hrest);
+      err = hipGetLastError();
+    }
   }
   for (const auto& g : p->sgroups) {
     if (err != hipSuccess) break;
@@ -507,6 +617,9 @@ void psdf_batch_plan_destroy(psdf_batch_plan* p) {
   (void)hipFree(p->d_failed);
   (void)hipFree(p->d_sctrl);
   (void)hipFree(p->d_circ);
+  (void)hipFree(p->d_hlist);
+  (void)hipFree(p->d_hcount);
+  (void)hipFree(p->d_hrest);
   (void)hipSetDevice(cur);
   delete p;
 }
@@ -590,6 +703,11 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
     size_t sumM = 0;
     for (int k = 0; k < n_inst; ++k) sumM += desc[k].M;
     err = hipMalloc(&p->d_circ, std::max<size_t>(1, sumM) * sizeof(float4));
+    if (err == hipSuccess) err = hipMalloc(&p->d_hlist, std::max<size_t>(1, sumM) * sizeof(int));
+    if (err == hipSuccess)
+      err = hipMalloc(&p->d_hcount, std::max<size_t>(1, (size_t)n_inst) * sizeof(int));
+    if (err == hipSuccess)
+      err = hipMalloc(&p->d_hrest, std::max<size_t>(1, (size_t)n_inst) * sizeof(uint32_t));
     if (err == hipSuccess) err = hipMalloc(&p->d_stage_inst, S * sizeof(int));
     if (err == hipSuccess) err = hipMalloc(&p->d_stage_list, S * sizeof(int));
     if (err == hipSuccess) err = hipMalloc(&p->d_failed, S * sizeof(int));

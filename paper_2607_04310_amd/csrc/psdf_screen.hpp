@@ -31,8 +31,10 @@
 namespace psdf {
 
 constexpr int kScreenThreads = 256;
-constexpr int kScreenKeysPerThread = 64;                       // obstacles per thread
+constexpr int kScreenKeysPerThread = 64;                       // obstacles per thread (horizon pass)
 constexpr int kScreenMaxM = kScreenThreads * kScreenKeysPerThread;   // 16384
+constexpr int kStageKeys = 8;                                  // horizon entries per thread (stage pass)
+constexpr int kHorizonCap = kScreenThreads * kStageKeys;       // 2048
 constexpr int kPoolCap = 512;                                  // pool capacity (ties included)
 constexpr float kLbGamma = 1e-3f;
 
@@ -50,6 +52,9 @@ struct ScreenArgs {
   const float* by;
   const int* off;
   const float4* circ;      // bounding circles (circle_kernel)
+  const int* hlist;        // per instance (at circ_off): the obstacles its stages screen
+  const int* hcount;       // per instance: length of hlist, or -1 for every obstacle
+  const uint32_t* hrest;   // per instance: lower-bound key of every obstacle not in hlist
   const float* theta;      // MLP parameters, or nullptr: rank by edge distance
   int pool;                // P
   int topk;                // K
@@ -101,15 +106,19 @@ __device__ __forceinline__ int block_sum_i32(int v, int* red) {
 
 // Threshold search by bisection on the key values (no atomics): returns X
 // with count(keys <= X) in [lo_n, hi_n] when one exists, else the largest
-// X with count <= hi_n found.  Keys equal to 0xffffffff are unused slots.
-// lo and hi are the smallest and largest used key.
+// X with count <= hi_n found.  Keys equal to 0xffffffff are unused slots,
+// and slots q >= nq (block-uniform) are not looked at.  lo and hi are the
+// smallest and largest used key.
 template <int KPT>
-__device__ uint32_t block_threshold(const uint32_t (&k)[KPT], uint32_t lo, uint32_t hi, int lo_n,
-                                    int hi_n, int* red) {
+__device__ uint32_t block_threshold(const uint32_t (&k)[KPT], int nq, uint32_t lo, uint32_t hi,
+                                    int lo_n, int hi_n, int* red) {
   auto count = [&](uint32_t x) {
     int c = 0;
 #pragma unroll
-    for (int q = 0; q < KPT; ++q) c += k[q] <= x && k[q] != 0xffffffffu;
+    for (int q = 0; q < KPT; ++q) {
+      if (q >= nq) break;
+      c += k[q] <= x && k[q] != 0xffffffffu;
+    }
     return block_sum_i32(c, red);
   };
   uint32_t a = lo, b = hi;
@@ -137,21 +146,28 @@ __device__ __forceinline__ uint32_t block_min_u32(uint32_t v, uint32_t* red) {
   return r;
 }
 
-// Exclusive block scan of one int per thread; returns the prefix, *total the sum.
+// Exclusive block scan of one int per thread (wave scans by shuffles, then
+// the wave totals); returns the prefix, *total the sum.
 __device__ __forceinline__ int block_scan(int v, int* scratch, int* total) {
-  const int tid = threadIdx.x;
-  scratch[tid] = v;
-  __syncthreads();
-  for (int o = 1; o < kScreenThreads; o <<= 1) {
-    const int a = tid >= o ? scratch[tid - o] : 0;
-    __syncthreads();
-    scratch[tid] += a;
-    __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
   }
-  const int incl = scratch[tid];
-  *total = scratch[kScreenThreads - 1];
+  if (lane == 63) scratch[w] = x;
   __syncthreads();
-  return incl - v;
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kScreenThreads / 64; ++i) {
+    const int t = scratch[i];
+    base += i < w ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
 }
 
 template <int MF, int MI>
@@ -180,16 +196,35 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
   const int M = in.M, Eend = in.edge_off + in.E;
   const int* off = A.off + in.obst_off;
 
-  // ---- bounding-circle lower bounds, thread t owns obstacles t + 256 q
-  uint32_t k[kScreenKeysPerThread];
+  // An instance without a usable horizon list (a non-finite stage position,
+  // or a tie block too large for the list) sends its stages to the full
+  // evaluation.
+  const int hc = A.hcount[inst];
+  if (hc < 0) {
+    if (tid == 0) {
+      A.keys[s] = kEmptyKey;
+      if (A.stage_cand) A.stage_cand[s] = 0;
+      if (A.stage_cert) A.stage_cert[s] = 0;
+      if (A.cand_keys) A.cand_keys[s] = kEmptyKey;
+      A.failed[atomicAdd(&A.ctrl[0], 1u)] = s;
+    }
+    return;
+  }
+
+  // ---- bounding-circle lower bounds over the instance's horizon list,
+  // thread t owns entries t + 256 q
+  uint32_t k[kStageKeys];
   const float4* circ = A.circ + in.circ_off;
+  const int n_h = hc;
+  const int* hl = A.hlist + in.circ_off;
   const float lb_off = F.rmax + kLbGamma;
+  const int nq = (n_h + kScreenThreads - 1) / kScreenThreads;   // live key slots
 #pragma unroll
-  for (int q = 0; q < kScreenKeysPerThread; ++q) {
-    const int o = tid + kScreenThreads * q;
+  for (int q = 0; q < kStageKeys; ++q) {
+    const int idx = tid + kScreenThreads * q;
     uint32_t key = 0xffffffffu;
-    if (o < M) {
-      const float4 c = circ[o];
+    if (q < nq && idx < n_h) {
+      const float4 c = circ[hl[idx]];
       if (c.x == c.x) {   // not an empty obstacle
         const float dx = px - c.x, dy = py - c.y;
         const float lbv = sqrtf(fmaf(dx, dx, dy * dy)) - c.z - lb_off;
@@ -204,34 +239,42 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   int used = 0;
 #pragma unroll
-  for (int q = 0; q < kScreenKeysPerThread; ++q)
+  for (int q = 0; q < kStageKeys; ++q) {
+    if (q >= nq) break;
     if (k[q] != 0xffffffffu) { kmin = min(kmin, k[q]); kmax = max(kmax, k[q]); ++used; }
+  }
   kmin = block_min_u32(kmin, red);
   kmax = ~block_min_u32(~kmax, red);
   const int n_used = block_sum_i32(used, scan);
-  const uint32_t T = n_used > P ? block_threshold<kScreenKeysPerThread>(k, kmin, kmax, (3 * P) / 4,
-                                                                         P, scan)
+  const uint32_t T = n_used > P ? block_threshold<kStageKeys>(k, nq, kmin, kmax,
+                                                                         (3 * P) / 4, P, scan)
                                 : 0xfffffffeu;
   int mine = 0;
 #pragma unroll
-  for (int q = 0; q < kScreenKeysPerThread; ++q) mine += k[q] <= T && k[q] != 0xffffffffu;
+  for (int q = 0; q < kStageKeys; ++q) {
+    if (q >= nq) break;
+    mine += k[q] <= T && k[q] != 0xffffffffu;
+  }
   int pool_n = 0;
   int at = block_scan(mine, scan, &pool_n);
   const bool overflow = pool_n > kPoolCap;
   if (!overflow) {
 #pragma unroll
-    for (int q = 0; q < kScreenKeysPerThread; ++q)
-      if (k[q] <= T && k[q] != 0xffffffffu) {
-        pool_o[at] = tid + kScreenThreads * q;
+    for (int q = 0; q < kStageKeys; ++q)
+      if (q < nq && k[q] <= T && k[q] != 0xffffffffu) {
+        pool_o[at] = hl[tid + kScreenThreads * q];
         pool_lb[at] = k[q];
         ++at;
       }
   }
-  // smallest circle bound outside the pool
-  uint32_t rest = 0xffffffffu;
+  // smallest bound outside the pool: the horizon list's circle bounds, and
+  // the instance's bound for every obstacle left out of the list
+  uint32_t rest = A.hrest[inst];
 #pragma unroll
-  for (int q = 0; q < kScreenKeysPerThread; ++q)
+  for (int q = 0; q < kStageKeys; ++q) {
+    if (q >= nq) break;
     if (k[q] > T) rest = min(rest, k[q]);
+  }
   rest = block_min_u32(rest, red);
   // pool members: the tighter point-to-polygon bound (the larger of two
   // valid lower bounds is a lower bound); -inf (pose inside, invalid) is
@@ -318,7 +361,7 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
     smax = ~block_min_u32(~smax, red);
     const int n_live = block_sum_i32(live, scan);
     const int K = max(1, A.topk);
-    const uint32_t S = n_live > K ? block_threshold<SPT>(sk, smin, smax, (7 * K) / 8, K, scan)
+    const uint32_t S = n_live > K ? block_threshold<SPT>(sk, SPT, smin, smax, (7 * K) / 8, K, scan)
                                   : 0xfffffffeu;
     for (int q = tid; q < pool_n; q += kScreenThreads) cand[q] = 0;
     __syncthreads();

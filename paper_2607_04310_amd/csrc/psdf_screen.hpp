@@ -14,10 +14,12 @@
 // origin; every footprint point is within rmax of p):
 //  * every obstacle: its bounding circle (c_i, r_i), computed once per call
 //    by circle_kernel, gives dist(P0(x), P^i) >= |p - c_i| - r_i - rmax;
-//  * pool members, tighter: for a closed convex polygon not containing p,
-//    dist(p, P^i) is the smallest point-segment distance from p to its
-//    edges (an open chain has no interior), so
-//    dist(P0(x), P^i) >= dist(p, P^i) - rmax.
+//  * an instance's stages share a horizon bound (horizon_kernel) for the
+//    obstacles left out of the instance's list;
+//  * excluded pool members, only when the circle bounds do not certify: for
+//    a closed convex polygon not containing p, dist(p, P^i) is the smallest
+//    point-segment distance from p to its edges (an open chain has no
+//    interior), so dist(P0(x), P^i) >= dist(p, P^i) - rmax.
 // Both subtract gamma to absorb FP32 rounding; an invalid obstacle gets -inf.
 // Two convex sets at distance r > tau_sep are separated by the axis test
 // (the largest axis gap is at least kappa r), so their sd is d_sep >= r >= LB.
@@ -276,20 +278,6 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
     if (k[q] > T) rest = min(rest, k[q]);
   }
   rest = block_min_u32(rest, red);
-  // pool members: the tighter point-to-polygon bound (the larger of two
-  // valid lower bounds is a lower bound); -inf (pose inside, invalid) is
-  // kept as is, which makes the obstacle a candidate
-  if (!overflow) {
-    for (int q = tid; q < pool_n; q += kScreenThreads) {
-      const int o = pool_o[q];
-      const int a = off[o], b = off[o + 1];
-      const float lbv = obstacle_lb(px, py, A.ax, A.ay, A.bx, A.by, in.edge_off + a, b - a,
-                                    in.edge_off, Eend, F.eps, F.rmax);
-      const uint32_t kk = orderable(pose_ok ? lbv : -__builtin_huge_valf());
-      const uint32_t ninf = orderable(-__builtin_huge_valf());
-      pool_lb[q] = kk <= ninf ? kk : max(pool_lb[q], kk);
-    }
-  }
   __syncthreads();
 
   uint64_t keyK = kEmptyKey;
@@ -412,13 +400,37 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
     keyK = wkey[0];
 #pragma unroll
     for (int i = 1; i < kScreenThreads / 64; ++i) keyK = wkey[i] < keyK ? wkey[i] : keyK;
-    // ---- certificate
+    // ---- certificate, first with the circle bounds
     const float phiK = keyK == kEmptyKey ? __builtin_huge_valf()
                                          : from_orderable((uint32_t)(keyK >> 32));
+    const float bar = fmaxf(phiK, F.tau_sep);
     const float lbx = excl == 0xffffffffu ? __builtin_huge_valf() : from_orderable(excl);
     cert = (keyK != kEmptyKey && (keyK >> 32) == 0)            // NaN wins anyway
            || excl == 0xffffffffu                               // nothing excluded
-           || lbx > fmaxf(phiK, F.tau_sep);
+           || lbx > bar;
+    if (!cert) {
+      // then with the point-to-polygon bound of every excluded pool member
+      // whose circle bound does not clear the bar (the larger of two valid
+      // lower bounds is a lower bound; -inf, pose inside or invalid, stays
+      // -inf and keeps the stage uncertified); bounds outside the pool stay
+      const uint32_t ninf = orderable(-__builtin_huge_valf());
+      uint32_t ex2 = rest;
+      for (int q = tid; q < pool_n; q += kScreenThreads) {
+        if (cand[q]) continue;
+        uint32_t kq = pool_lb[q];
+        if (!(from_orderable(kq) > bar)) {
+          const int o = pool_o[q];
+          const int a = off[o], b = off[o + 1];
+          const float lbv = obstacle_lb(px, py, A.ax, A.ay, A.bx, A.by, in.edge_off + a, b - a,
+                                        in.edge_off, Eend, F.eps, F.rmax);
+          const uint32_t kk = orderable(pose_ok ? lbv : -__builtin_huge_valf());
+          kq = kk <= ninf ? kk : max(kq, kk);
+        }
+        ex2 = min(ex2, kq);
+      }
+      ex2 = block_min_u32(ex2, red);
+      cert = ex2 == 0xffffffffu || from_orderable(ex2) > bar;
+    }
   } else {
     cert = !overflow && pool_n == 0;   // no obstacle at all
   }

@@ -223,7 +223,10 @@ int psdf_encode_padded(const float* A, const float* B, const uint8_t* S, int32_t
  * with each instance's offsets relative to its own first edge (they start at
  * 0).  Outputs (device, length sum N, rows in the packed pose order): d,
  * edge (index within the instance's edges), obst (index within the
- * instance's obstacles), grad [sum N][3], keys.
+ * instance's obstacles), grad [sum N][3], keys.  The stages of an instance
+ * without obstacles (M = 0) get the result of an empty edge set: d = +inf,
+ * edge = obst = -1, zero gradient, key 0xffffffffffffffff.  Edge columns
+ * may be NULL when no instance has an obstacle.
  * ------------------------------------------------------------------------ */
 typedef struct {
   int32_t fp_off;   /* first vertex of this instance's footprint in the host footprint array */

@@ -18,13 +18,24 @@
 
 namespace psdf {
 
-// Bounding circle of every obstacle of every instance: (cx, cy, r, 0), with
-// r inflated to cover rounding.  Empty obstacles get cx = NaN (never in a
-// pool); invalid ones (bad range, non-finite) r = +inf (always in the pool).
+// Per-call prologue of the screened path, grid (obstacle blocks, instances):
+// the bounding circle of every obstacle, (cx, cy, r, 0) with r inflated to
+// cover rounding (an empty obstacle gets cx = NaN and is never in a pool; an
+// invalid one, bad range or non-finite, r = +inf and is always in it); the
+// first block of each instance opens its horizon list (count 0, excluded
+// bound +inf) and block (0, 0) clears the screening counters of every group.
 __global__ void circle_kernel(const BatchInst* __restrict__ insts, const float* __restrict__ ax,
                               const float* __restrict__ ay, const float* __restrict__ bx,
                               const float* __restrict__ by, const int* __restrict__ off,
-                              float4* __restrict__ circ) {
+                              float4* __restrict__ circ, int* __restrict__ hcount,
+                              uint32_t* __restrict__ hrest, unsigned* __restrict__ ctrl,
+                              int n_ctrl) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    hcount[blockIdx.y] = 0;
+    hrest[blockIdx.y] = 0xffffffffu;
+    if (blockIdx.y == 0)
+      for (int i = 0; i < n_ctrl; ++i) ctrl[i] = 0u;
+  }
   const BatchInst in = insts[blockIdx.y];
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= in.M) return;
@@ -33,22 +44,31 @@ __global__ void circle_kernel(const BatchInst* __restrict__ insts, const float* 
   if (mi != 0) {
     c = make_float4(0.f, 0.f, __builtin_huge_valf(), 0.f);
     if (mi > 0 && mi <= kMaxObst && a >= 0 && b <= in.E) {
+      // the obstacle's endpoints in registers, one pass over memory
+      float px[2 * kMaxObst], py[2 * kMaxObst];
       float sx = 0.f, sy = 0.f;
       bool finite = true;
-      for (int j = 0; j < mi; ++j) {
-        const int e = in.edge_off + a + j;
-        sx += ax[e] + bx[e];
-        sy += ay[e] + by[e];
-        finite = finite && isfinite(ax[e]) && isfinite(ay[e]) && isfinite(bx[e]) && isfinite(by[e]);
+#pragma unroll
+      for (int j = 0; j < kMaxObst; ++j) {
+        if (j < mi) {
+          const int e = in.edge_off + a + j;
+          px[2 * j] = ax[e]; py[2 * j] = ay[e];
+          px[2 * j + 1] = bx[e]; py[2 * j + 1] = by[e];
+          sx += px[2 * j] + px[2 * j + 1];
+          sy += py[2 * j] + py[2 * j + 1];
+          finite = finite && isfinite(px[2 * j]) && isfinite(py[2 * j]) &&
+                   isfinite(px[2 * j + 1]) && isfinite(py[2 * j + 1]);
+        }
       }
       if (finite) {
         const float cx = sx / (2.f * mi), cy = sy / (2.f * mi);
         float r2 = 0.f;
-        for (int j = 0; j < mi; ++j) {
-          const int e = in.edge_off + a + j;
-          r2 = fmaxf(r2, fmaf(ax[e] - cx, ax[e] - cx, (ay[e] - cy) * (ay[e] - cy)));
-          r2 = fmaxf(r2, fmaf(bx[e] - cx, bx[e] - cx, (by[e] - cy) * (by[e] - cy)));
-        }
+#pragma unroll
+        for (int j = 0; j < 2 * kMaxObst; ++j)
+          if (j < 2 * mi) {
+            const float dx = px[j] - cx, dy = py[j] - cy;
+            r2 = fmaxf(r2, fmaf(dx, dx, dy * dy));
+          }
         c = make_float4(cx, cy, sqrtf(r2) * (1.0f + 1e-6f) + 1e-6f, 0.f);
       }
     }
@@ -56,17 +76,22 @@ __global__ void circle_kernel(const BatchInst* __restrict__ insts, const float* 
   circ[in.circ_off + o] = c;
 }
 
-// Horizon list of each instance (one work-group per instance): every stage
-// position of the instance lies within R of the centre c_p of their bounding
-// box, so for every stage s and obstacle i
+// Horizon list of each instance: every stage position of the instance lies
+// within R of the centre c_p of their bounding box, so for every stage s and
+// obstacle i
 //   |p_s - c_i| - r_i - rmax - gamma >= |c_p - c_i| - R - r_i - rmax - gamma =: hb_i,
-// a lower bound of the stage's circle bound and hence of sd_i.  The
-// kHorizonPool obstacles of lowest hb (about) are the list the instance's
-// stages screen; the smallest hb left out bounds every excluded obstacle at
-// every stage.  A non-finite stage position, or a list longer than
-// kHorizonCap (a tie block), disables the list (-1): the instance's stages
-// then take the full evaluation.
+// a lower bound of the stage's circle bound and hence of sd_i.  Grid
+// (kHorizonSplit, instances): work-group c takes the c-th block of the
+// instance's obstacles and appends its (about) kHorizonPool / kHorizonSplit
+// lowest-hb obstacles to the list; the list thus holds every obstacle among
+// the kHorizonPool / kHorizonSplit lowest of the whole instance.  The
+// smallest hb left out (atomic minimum over the blocks) bounds every excluded
+// obstacle at every stage.  A non-finite stage position disables the list
+// (-1); a list longer than kHorizonCap (tie blocks) is not used by the stage
+// pass either: the instance's stages then take the full evaluation.
 constexpr int kHorizonPool = 1024;
+constexpr int kHorizonSplit = 4;
+constexpr int kHorizonKeys = kScreenMaxM / kHorizonSplit / kScreenThreads;   // 16
 
 __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
@@ -74,10 +99,14 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     int* __restrict__ hcount, uint32_t* __restrict__ hrest) {
   __shared__ int scan[kScreenThreads];
   __shared__ uint32_t red[kScreenThreads / 64];
-  const int inst = blockIdx.x, tid = threadIdx.x;
+  __shared__ int s_base;
+  const int inst = blockIdx.y, part = blockIdx.x, tid = threadIdx.x;
   const BatchInst in = insts[inst];
   const FpConst& F = fps[inst];
   const int M = in.M;
+  const int chunk = (M + kHorizonSplit - 1) / kHorizonSplit;
+  const int o0 = part * chunk, o1 = min(M, o0 + chunk);
+  if (o0 >= o1) return;   // empty block: nothing to add
   // bounding box of the stage positions (orderable keys: min of x, y, -x, -y)
   uint32_t bx0 = 0xffffffffu, by0 = 0xffffffffu, bx1 = 0xffffffffu, by1 = 0xffffffffu;
   int bad = 0;
@@ -91,8 +120,8 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   bad = block_sum_i32(bad, scan);
   bx0 = block_min_u32(bx0, red); by0 = block_min_u32(by0, red);
   bx1 = block_min_u32(bx1, red); by1 = block_min_u32(by1, red);
-  if (bad > 0 || in.N == 0 || M == 0) {
-    if (tid == 0) { hcount[inst] = -1; hrest[inst] = 0xffffffffu; }
+  if (bad > 0 || in.N == 0) {
+    if (tid == 0 && part == 0) hcount[inst] = -1;
     return;
   }
   const float cx = 0.5f * (from_orderable(bx0) - from_orderable(bx1));
@@ -108,15 +137,14 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   nr = block_min_u32(nr, red);
   const float R = -from_orderable(nr) * (1.0f + 1e-6f) + 1e-6f;
   const float off = R + F.rmax + kLbGamma;
-  uint32_t k[kScreenKeysPerThread];
+  uint32_t k[kHorizonKeys];
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   int used = 0;
-  const int nq = (M + kScreenThreads - 1) / kScreenThreads;   // live key slots
 #pragma unroll
-  for (int q = 0; q < kScreenKeysPerThread; ++q) {
-    const int o = tid + kScreenThreads * q;
+  for (int q = 0; q < kHorizonKeys; ++q) {
+    const int o = o0 + tid + kScreenThreads * q;
     uint32_t key = 0xffffffffu;
-    if (q < nq && o < M) {
+    if (o < o1) {
       const float4 c = circ[in.circ_off + o];
       if (c.x == c.x) {
         const float dx = cx - c.x, dy = cy - c.y;
@@ -129,15 +157,14 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   kmin = block_min_u32(kmin, red);
   kmax = ~block_min_u32(~kmax, red);
   const int n_used = block_sum_i32(used, scan);
-  const uint32_t T = n_used > kHorizonPool
-                         ? block_threshold<kScreenKeysPerThread>(k, nq, kmin, kmax,
-                                                                 kHorizonPool / 2, kHorizonPool,
-                                                                 scan)
-                         : 0xfffffffeu;
+  constexpr int P = kHorizonPool / kHorizonSplit;
+  const uint32_t T = n_used > P ? block_threshold<kHorizonKeys>(k, kHorizonKeys, kmin, kmax,
+                                                                P / 2, P, scan)
+                                : 0xfffffffeu;
   int mine = 0;
   uint32_t rest = 0xffffffffu;
 #pragma unroll
-  for (int q = 0; q < kScreenKeysPerThread; ++q) {
+  for (int q = 0; q < kHorizonKeys; ++q) {
     if (k[q] == 0xffffffffu) continue;
     if (k[q] <= T) ++mine;
     else rest = min(rest, k[q]);
@@ -145,15 +172,17 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   rest = block_min_u32(rest, red);
   int total = 0;
   int at = block_scan(mine, scan, &total);
-  if (total <= kHorizonCap) {
-#pragma unroll
-    for (int q = 0; q < kScreenKeysPerThread; ++q)
-      if (k[q] != 0xffffffffu && k[q] <= T) hlist[in.circ_off + at++] = tid + kScreenThreads * q;
-  }
   if (tid == 0) {
-    hcount[inst] = total <= kHorizonCap ? total : -1;
-    hrest[inst] = rest;
+    s_base = total > 0 ? atomicAdd(&hcount[inst], total) : 0;
+    if (rest != 0xffffffffu) atomicMin(&hrest[inst], rest);
   }
+  __syncthreads();
+  at += s_base;
+  // the instance's list has M slots and holds each obstacle at most once
+#pragma unroll
+  for (int q = 0; q < kHorizonKeys; ++q)
+    if (k[q] != 0xffffffffu && k[q] <= T)
+      hlist[in.circ_off + at++] = o0 + tid + kScreenThreads * q;
 }
 
 struct Shape {
@@ -190,6 +219,8 @@ struct psdf_batch_plan {
   unsigned* d_blockcnt = nullptr;
   size_t blockcnt_cap = 0;
   unsigned* d_ctrl = nullptr;        // two counters per group
+  int* d_empty_rows = nullptr;       // stage rows of instances without obstacles
+  int n_empty_rows = 0;
   // screening: stage -> instance, stage rows grouped by footprint size,
   // failed lists and counters (three per group)
   int* d_stage_inst = nullptr;
@@ -386,16 +417,35 @@ BatchArgs make_args(psdf_batch_plan* p, const float* poses, const float* ax, con
   return a;
 }
 
+// Stages of instances without obstacles: the result of an empty edge set
+// (d = +inf, no winner, zero gradient, the empty key).
+__global__ void empty_rows_kernel(const int* __restrict__ rows, int n, float* __restrict__ d,
+                                  int* __restrict__ edge, int* __restrict__ obst,
+                                  float* __restrict__ grad, uint64_t* __restrict__ keys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int s = rows[i];
+  d[s] = __builtin_huge_valf();
+  edge[s] = -1;
+  obst[s] = -1;
+  grad[3 * s + 0] = 0.f;
+  grad[3 * s + 1] = 0.f;
+  grad[3 * s + 2] = 0.f;
+  keys[s] = kEmptyKey;
+}
+
 int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay,
         const float* bx, const float* by, const int32_t* off, float* d, int32_t* edge,
         int32_t* obst, float* grad, uint64_t* keys, hipStream_t stream, bool use_graph) {
-  if (p->total_stages == 0 || p->n_items == 0) {
-    if (p->total_stages == 0) return PSDF_OK;
-  }
+  if (p->total_stages == 0) return PSDF_OK;
   const BatchArgs a = make_args(p, poses, ax, ay, bx, by, off, d, edge, obst, grad, keys);
-  if (p->n_items == 0) return set_error(PSDF_EINVAL, "batch has stages but no obstacles; "
-                                                      "use psdf_grad for empty edge sets");
   auto enqueue = [&](hipStream_t st) -> hipError_t {
+    if (p->n_empty_rows > 0) {
+      empty_rows_kernel<<<(p->n_empty_rows + 255) / 256, 256, 0, st>>>(
+          p->d_empty_rows, p->n_empty_rows, d, edge, obst, grad, keys);
+      hipError_t err = hipGetLastError();
+      if (err != hipSuccess) return err;
+    }
     for (const auto& g : p->groups) {
       BatchArgs ga = a;
       ga.items = a.items + g.start;
@@ -551,14 +601,15 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
   a.stage_cand = stage_cand; a.stage_cert = stage_cert; a.cand_keys = cand_keys;
   timer_begin(stream);
   hipError_t err = hipSuccess;
-  if (p->max_M > 0 && p->n_inst > 0) {
-    dim3 grid((p->max_M + 255) / 256, p->n_inst);
-    circle_kernel<<<grid, 256, 0, stream>>>(p->d_inst, ax, ay, bx, by, off, p->d_circ);
+  if (p->n_inst > 0) {
+    dim3 grid((std::max(1, p->max_M) + 255) / 256, p->n_inst);
+    circle_kernel<<<grid, 256, 0, stream>>>(p->d_inst, ax, ay, bx, by, off, p->d_circ,
+                                            p->d_hcount, p->d_hrest, p->d_sctrl,
+                                            2 * kGroups);
     err = hipGetLastError();
     if (err == hipSuccess) {
-      horizon_kernel<<<p->n_inst, kScreenThreads, 0, stream>>>(p->d_fp, p->d_inst, poses,
-                                                               p->d_circ, p->d_hlist,
-                                                               p->d_hcount, p->d_hrest);
+      horizon_kernel<<<dim3(kHorizonSplit, p->n_inst), kScreenThreads, 0, stream>>>(
+          p->d_fp, p->d_inst, poses, p->d_circ, p->d_hlist, p->d_hcount, p->d_hrest);
       err = hipGetLastError();
     }
   }
@@ -568,7 +619,7 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
     ga.stages = p->d_stage_list + g.start;
     ga.n_stages = g.count;
     ga.failed = p->d_failed + g.start;
-    ga.ctrl = p->d_sctrl + 3 * group_of(g.mf);
+    ga.ctrl = p->d_sctrl + 2 * group_of(g.mf);
     err = launch_screen(g.mf, p->mi_class, g.count, ga, stream);
     if (err != hipSuccess) break;
     const int grid = std::max(1, std::min(g.count * g.max_tiles, 4 * p->cu));
@@ -613,6 +664,7 @@ void psdf_batch_plan_destroy(psdf_batch_plan* p) {
   (void)hipFree(p->d_blockcnt);
   (void)hipFree(p->d_ctrl);
   (void)hipFree(p->d_stage_inst);
+  (void)hipFree(p->d_empty_rows);
   (void)hipFree(p->d_stage_list);
   (void)hipFree(p->d_failed);
   (void)hipFree(p->d_sctrl);
@@ -711,12 +763,23 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
     if (err == hipSuccess) err = hipMalloc(&p->d_stage_inst, S * sizeof(int));
     if (err == hipSuccess) err = hipMalloc(&p->d_stage_list, S * sizeof(int));
     if (err == hipSuccess) err = hipMalloc(&p->d_failed, S * sizeof(int));
-    if (err == hipSuccess) err = hipMalloc(&p->d_sctrl, 3 * kGroups * sizeof(unsigned));
-    if (err == hipSuccess) err = hipMemset(p->d_sctrl, 0, 3 * kGroups * sizeof(unsigned));
+    if (err == hipSuccess) err = hipMalloc(&p->d_sctrl, 2 * kGroups * sizeof(unsigned));
+    if (err == hipSuccess) err = hipMemset(p->d_sctrl, 0, 2 * kGroups * sizeof(unsigned));
     if (err == hipSuccess)
       err = hipMemcpy(p->d_stage_inst, stage_inst.data(), S * sizeof(int), hipMemcpyHostToDevice);
     if (err == hipSuccess && !list.empty())
       err = hipMemcpy(p->d_stage_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice);
+    std::vector<int> empty_rows;
+    for (int k = 0; k < n_inst; ++k)
+      if (desc[k].M == 0)
+        for (int t = 0; t < desc[k].N; ++t) empty_rows.push_back(desc[k].pose_off + t);
+    p->n_empty_rows = (int)empty_rows.size();
+    if (err == hipSuccess && !empty_rows.empty()) {
+      err = hipMalloc(&p->d_empty_rows, empty_rows.size() * sizeof(int));
+      if (err == hipSuccess)
+        err = hipMemcpy(p->d_empty_rows, empty_rows.data(), empty_rows.size() * sizeof(int),
+                        hipMemcpyHostToDevice);
+    }
   }
   if (err != hipSuccess) {
     int rc = hip_status(err);

@@ -62,7 +62,7 @@ struct ScreenArgs {
   int topk;                // K
   uint64_t* keys;
   int* failed;             // this launch's failed-stage list
-  unsigned* ctrl;          // [0] failed count, [1] fallback item, [2] fallback done
+  unsigned* ctrl;          // [0] failed count, [1] fallback item; cleared by the call's prologue
   int* stage_cand;         // optional: candidates evaluated per stage
   int* stage_cert;         // optional: 1 if certified
   uint64_t* cand_keys;     // optional: the candidates' minimum key (before any fallback)
@@ -199,10 +199,10 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
   const int* off = A.off + in.obst_off;
 
   // An instance without a usable horizon list (a non-finite stage position,
-  // or a tie block too large for the list) sends its stages to the full
-  // evaluation.
+  // or tie blocks that make it longer than kHorizonCap) sends its stages to
+  // the full evaluation.
   const int hc = A.hcount[inst];
-  if (hc < 0) {
+  if (hc < 0 || hc > kHorizonCap) {
     if (tid == 0) {
       A.keys[s] = kEmptyKey;
       if (A.stage_cand) A.stage_cand[s] = 0;
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
       cert = ex2 == 0xffffffffu || from_orderable(ex2) > bar;
     }
   } else {
-    cert = !overflow && pool_n == 0;   // no obstacle at all
+    cert = !overflow && pool_n == 0 && rest == 0xffffffffu;   // no obstacle at all
   }
   if (tid == 0) {
     A.keys[s] = keyK;
@@ -445,8 +445,8 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
 
 // Full evaluation of the failed stages: items (failed stage, tile of 256
 // obstacles) pulled from a counter; each work-group folds its tile's minimum
-// into keys[s] with a 64-bit atomicMin.  The last work-group out clears the
-// failed count and the item counter.
+// into keys[s] with a 64-bit atomicMin.  The failed count and the item
+// counter start at zero: the call's prologue clears them.
 template <int MF, int MI>
 __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int max_tiles) {
   __shared__ int s_item;
@@ -454,6 +454,7 @@ __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int 
   __shared__ float4 rf[MF];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int n_failed = (int)__hip_atomic_load(&A.ctrl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (n_failed == 0) return;   // every stage certified: nothing to do
   for (;;) {
     if (tid == 0) s_item = (int)atomicAdd(&A.ctrl[1], 1u);
     __syncthreads();
@@ -495,15 +496,6 @@ __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int 
       }
     }
     __syncthreads();
-  }
-  if (tid == 0) {
-    const unsigned done =
-        __hip_atomic_fetch_add(&A.ctrl[2], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    if (done == gridDim.x) {
-      __hip_atomic_store(&A.ctrl[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&A.ctrl[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&A.ctrl[2], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
   }
 }
 

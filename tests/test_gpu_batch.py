@@ -127,6 +127,27 @@ def test_batch_mixed_shapes_and_nan(api):
     b.close()
 
 
+def test_batch_obstacle_free_instances(api):
+    """Instances without obstacles give the empty-set result (d = +inf, no
+    winner, zero gradient), the same as psdf_grad on an empty edge set, in a
+    mixed batch and in a batch with no edge at all; graph replays included."""
+    rng = np.random.default_rng(78)
+    insts = [inputs.random_small(rng, n_obst=0 if k in (0, 2, 5) else 25, n_poses=15 + k,
+                                 segments=0 if k in (0, 2, 5) else 3, lo=-3, hi=3) for k in range(7)]
+    for only_empty in (False, True):
+        sel = [insts[k] for k in (0, 2, 5)] if only_empty else insts
+        b = api.Batch(sel, graph=True)
+        for _ in range(2):
+            d, e, o, g = batch_out(b)
+            assert_equal_outputs([d, e, o, g], per_instance(api, b))
+        for k, inst in enumerate(sel):
+            if len(inst.obst_off) == 1:
+                sl = slice(b.desc[k][2], b.desc[k][2] + inst.N)
+                assert np.all(np.isposinf(d[sl])) and np.all(e[sl] == -1) and np.all(o[sl] == -1)
+                assert np.all(g[sl] == 0)
+        b.close()
+
+
 def test_single_instance_batch_equals_plain(api):
     inst = inputs.c2(0)
     b = api.Batch([inst], graph=True)

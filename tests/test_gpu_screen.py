@@ -173,3 +173,50 @@ def test_screened_uneven_batch(api):
     _assert_same([x.clone() for x in out2], ref2)
     b.close()
     b2.close()
+
+
+def _assert_empty_rows(out, rows):
+    d, edge, obst, grad, keys = (x.cpu() for x in out)
+    assert bool(torch.isinf(d[rows]).all()) and bool((d[rows] > 0).all())
+    assert bool((edge[rows] == -1).all()) and bool((obst[rows] == -1).all())
+    assert bool((grad[rows] == 0).all()) and bool((keys[rows] == -1).all())
+
+
+def test_screened_obstacle_free_instances(api):
+    """Instances without obstacles, alone in a batch (no edges at all) and
+    mixed with populated ones: their stages get the empty-set result (min
+    over no obstacle is +inf) on the plain and the screened path, and every
+    such stage certifies."""
+    rng = np.random.default_rng(21)
+    b = api.Batch([inputs.random_small(rng, n_obst=0, n_poses=10) for _ in range(3)], graph=False)
+    ref = _run_plain(b)
+    _assert_empty_rows(ref, slice(None))
+    out, (cand, cert, ck) = b.screened(None, pool=16, topk=8, stats=True)
+    torch.cuda.synchronize()
+    _assert_same([x.clone() for x in out], ref)
+    assert bool(cert.bool().all())
+    b.close()
+    mixed = [inputs.random_small(rng, n_obst=0 if k % 2 else 30, n_poses=20, segments=0 if k % 2 else 5)
+             for k in range(6)]
+    b2 = api.Batch(mixed, graph=False)
+    ref2 = _run_plain(b2)
+    rows = torch.tensor(np.concatenate([np.full(20, k % 2 == 1) for k in range(6)]))
+    _assert_empty_rows(ref2, rows)
+    out2, (cand, cert, ck) = b2.screened(None, pool=16, topk=8, stats=True)
+    torch.cuda.synchronize()
+    _assert_same([x.clone() for x in out2], ref2)
+    assert bool(cert.bool().cpu()[rows].all())
+    b2.close()
+
+
+def test_screened_repeated_calls(api):
+    """Back-to-back screened calls with and without fallback work: the
+    screening counters start from zero on every call."""
+    insts = inputs.c5(4)
+    b = api.Batch(insts, graph=False)
+    ref = _run_plain(b)
+    for pool, topk in ((1, 1), (128, 256), (1, 1), (1, 1), (128, 256)):
+        out = b.screened(None, pool=pool, topk=topk)
+        torch.cuda.synchronize()
+        _assert_same([x.clone() for x in out], ref)
+    b.close()

@@ -95,7 +95,7 @@ constexpr int kHorizonKeys = kScreenMaxM / kHorizonSplit / kScreenThreads;   // 
 
 __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
-    const float* __restrict__ poses, const float4* __restrict__ circ, int* __restrict__ hlist,
+    const float* __restrict__ poses, const float4* __restrict__ circ, float4* __restrict__ hlist,
     int* __restrict__ hcount, uint32_t* __restrict__ hrest) {
   __shared__ int scan[kScreenThreads];
   __shared__ uint32_t red[kScreenThreads / 64];
@@ -178,11 +178,16 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   }
   __syncthreads();
   at += s_base;
-  // the instance's list has M slots and holds each obstacle at most once
+  // the instance's list has M slots and holds each obstacle at most once,
+  // as its circle with the local index in .w
 #pragma unroll
   for (int q = 0; q < kHorizonKeys; ++q)
-    if (k[q] != 0xffffffffu && k[q] <= T)
-      hlist[in.circ_off + at++] = o0 + tid + kScreenThreads * q;
+    if (k[q] != 0xffffffffu && k[q] <= T) {
+      const int o = o0 + tid + kScreenThreads * q;
+      float4 c = circ[in.circ_off + o];
+      c.w = __int_as_float(o);
+      hlist[in.circ_off + at++] = c;
+    }
 }
 
 struct Shape {
@@ -228,7 +233,7 @@ struct psdf_batch_plan {
   int* d_failed = nullptr;
   unsigned* d_sctrl = nullptr;
   float4* d_circ = nullptr;   // bounding circles, sum M
-  int* d_hlist = nullptr;     // horizon lists, sum M
+  float4* d_hlist = nullptr;  // horizon lists (circle, index), sum M
   int* d_hcount = nullptr;    // per instance
   uint32_t* d_hrest = nullptr;
   struct SGroup { int mf, start, count, max_tiles; };
@@ -755,7 +760,7 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
     size_t sumM = 0;
     for (int k = 0; k < n_inst; ++k) sumM += desc[k].M;
     err = hipMalloc(&p->d_circ, std::max<size_t>(1, sumM) * sizeof(float4));
-    if (err == hipSuccess) err = hipMalloc(&p->d_hlist, std::max<size_t>(1, sumM) * sizeof(int));
+    if (err == hipSuccess) err = hipMalloc(&p->d_hlist, std::max<size_t>(1, sumM) * sizeof(float4));
     if (err == hipSuccess)
       err = hipMalloc(&p->d_hcount, std::max<size_t>(1, (size_t)n_inst) * sizeof(int));
     if (err == hipSuccess)

@@ -54,7 +54,8 @@ struct ScreenArgs {
   const float* by;
   const int* off;
   const float4* circ;      // bounding circles (circle_kernel)
-  const int* hlist;        // per instance (at circ_off): the obstacles its stages screen
+  const float4* hlist;     // per instance (at circ_off): the circles its stages screen, the
+                           // obstacle's local index in .w (int bits)
   const int* hcount;       // per instance: length of hlist, or -1 for every obstacle
   const uint32_t* hrest;   // per instance: lower-bound key of every obstacle not in hlist
   const float* theta;      // MLP parameters, or nullptr: rank by edge distance
@@ -94,75 +95,91 @@ __device__ __forceinline__ float obstacle_lb(float px, float py, const float* __
   return sqrtf(d2) - rmax - kLbGamma;
 }
 
+constexpr int kWaves = kScreenThreads / 64;
+
+// ---- work-group reductions (every thread of the work-group calls them)
 __device__ __forceinline__ int block_sum_i32(int v, int* red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  v = fw_sum_i32(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   int r = 0;
 #pragma unroll
-  for (int i = 0; i < kScreenThreads / 64; ++i) r += red[i];
+  for (int i = 0; i < kWaves; ++i) r += red[i];
   __syncthreads();
   return r;
 }
 
-// Threshold search by bisection on the key values (no atomics): returns X
-// with count(keys <= X) in [lo_n, hi_n] when one exists, else the largest
-// X with count <= hi_n found.  Keys equal to 0xffffffff are unused slots,
-// and slots q >= nq (block-uniform) are not looked at.  lo and hi are the
-// smallest and largest used key.
+// Threshold search on the key values (no atomics): returns X with
+// count(keys <= X) in [lo_n, hi_n] when one exists, else the largest X with
+// count <= hi_n found (lo when count(lo) > hi_n: a tie block wider than the
+// window at the minimum).  Keys are orderable images of floats; 0xffffffff
+// marks an unused slot, and slots q >= nq (block-uniform) are not looked at.
+// lo and hi are the smallest and largest used key.  The bracket is halved in
+// value (the midpoint of the two floats), which resolves a distance quantile
+// in a few steps, and in key order wherever the float midpoint does not fall
+// strictly inside (infinite ends, adjacent floats).  Each count is a sum of
+// ballots and one barrier (two alternating halves of red, which holds
+// 2 kWaves ints).
 template <int KPT>
 __device__ uint32_t block_threshold(const uint32_t (&k)[KPT], int nq, uint32_t lo, uint32_t hi,
                                     int lo_n, int hi_n, int* red) {
+  int half = 0;
   auto count = [&](uint32_t x) {
     int c = 0;
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
       if (q >= nq) break;
-      c += k[q] <= x && k[q] != 0xffffffffu;
+      c += __popcll(__ballot(k[q] <= x && k[q] != 0xffffffffu));
     }
-    return block_sum_i32(c, red);
+    int* r = red + half * kWaves;
+    if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = c;
+    __syncthreads();
+    int t = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) t += r[i];
+    half ^= 1;
+    return t;
   };
   uint32_t a = lo, b = hi;
-  int ca = count(a);
-  if (ca > hi_n) return a;   // a tie block larger than the window at the minimum
-  while (b - a > 1u) {
-    const uint32_t mid = a + (b - a) / 2u;
-    const int c = count(mid);
-    if (c > hi_n) b = mid;
-    else if (c < lo_n) { a = mid; ca = c; }
-    else return mid;
+  uint32_t res = a;
+  const int c0 = count(a);
+  if (c0 < lo_n) {
+    for (;;) {
+      if (b - a <= 1u) { res = a; break; }
+      uint32_t mid = orderable(0.5f * from_orderable(a) + 0.5f * from_orderable(b));
+      if (!(mid > a && mid < b)) mid = a + (b - a) / 2u;
+      const int c = count(mid);
+      if (c > hi_n) b = mid;
+      else if (c < lo_n) a = mid;
+      else { res = mid; break; }
+    }
   }
-  return a;
+  __syncthreads();   // red is free again for the caller
+  return res;
 }
 
 __device__ __forceinline__ uint32_t block_min_u32(uint32_t v, uint32_t* red) {
-  v = wave_min_u32(v);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[w] = v;
+  v = fw_min_u32(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   uint32_t r = red[0];
 #pragma unroll
-  for (int i = 1; i < kScreenThreads / 64; ++i) r = min(r, red[i]);
+  for (int i = 1; i < kWaves; ++i) r = min(r, red[i]);
   __syncthreads();
   return r;
 }
 
-// Exclusive block scan of one int per thread (wave scans by shuffles, then
-// the wave totals); returns the prefix, *total the sum.
+// Exclusive block scan of one int per thread; returns the prefix, *total
+// the sum.
 __device__ __forceinline__ int block_scan(int v, int* scratch, int* total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) scratch[w] = x;
+  const int w = threadIdx.x >> 6;
+  int wt = 0;
+  const int x = fw_scan_i32(v, &wt);
+  if ((threadIdx.x & 63) == 0) scratch[w] = wt;
   __syncthreads();
   int base = 0, tot = 0;
 #pragma unroll
-  for (int i = 0; i < kScreenThreads / 64; ++i) {
+  for (int i = 0; i < kWaves; ++i) {
     const int t = scratch[i];
     base += i < w ? t : 0;
     tot += t;
@@ -216,22 +233,22 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
   // ---- bounding-circle lower bounds over the instance's horizon list,
   // thread t owns entries t + 256 q
   uint32_t k[kStageKeys];
-  const float4* circ = A.circ + in.circ_off;
+  int hidx[kStageKeys];
   const int n_h = hc;
-  const int* hl = A.hlist + in.circ_off;
+  const float4* hl = A.hlist + in.circ_off;
   const float lb_off = F.rmax + kLbGamma;
   const int nq = (n_h + kScreenThreads - 1) / kScreenThreads;   // live key slots
 #pragma unroll
   for (int q = 0; q < kStageKeys; ++q) {
     const int idx = tid + kScreenThreads * q;
     uint32_t key = 0xffffffffu;
-    if (q < nq && idx < n_h) {
-      const float4 c = circ[hl[idx]];
-      if (c.x == c.x) {   // not an empty obstacle
-        const float dx = px - c.x, dy = py - c.y;
-        const float lbv = sqrtf(fmaf(dx, dx, dy * dy)) - c.z - lb_off;
-        key = orderable(pose_ok ? lbv : -__builtin_huge_valf());
-      }
+    hidx[q] = 0;
+    if (q < nq && idx < n_h) {   // the list holds no empty obstacle
+      const float4 c = hl[idx];
+      hidx[q] = __float_as_int(c.w);
+      const float dx = px - c.x, dy = py - c.y;
+      const float lbv = sqrtf(fmaf(dx, dx, dy * dy)) - c.z - lb_off;
+      key = orderable(pose_ok ? lbv : -__builtin_huge_valf());
     }
     k[q] = key;
   }
@@ -264,7 +281,7 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
 #pragma unroll
     for (int q = 0; q < kStageKeys; ++q)
       if (q < nq && k[q] <= T && k[q] != 0xffffffffu) {
-        pool_o[at] = hl[tid + kScreenThreads * q];
+        pool_o[at] = hidx[q];
         pool_lb[at] = k[q];
         ++at;
       }
@@ -392,7 +409,7 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
       uint32_t kk = 0xffffffffu;
       if (act && mi != 0) kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, rf, px, py)) : 0u;
       const uint64_t key = kk == 0xffffffffu ? kEmptyKey : (((uint64_t)kk << 32) | (uint32_t)o);
-      const uint64_t wmin = wave_min_u64(key);
+      const uint64_t wmin = fw_min_u64(key);
       best = wmin < best ? wmin : best;
     }
     if (lane == 0) wkey[w] = best;
@@ -486,7 +503,7 @@ __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int 
       uint32_t kk = 0xffffffffu;
       if (act && mi != 0) kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, rf, px, py)) : 0u;
       const uint64_t key = kk == 0xffffffffu ? kEmptyKey : (((uint64_t)kk << 32) | (uint32_t)o);
-      const uint64_t wmin = wave_min_u64(key);
+      const uint64_t wmin = fw_min_u64(key);
       if (lane == 0) wk[w] = wmin;
       __syncthreads();
       if (tid == 0) {

@@ -62,6 +62,73 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
   return x;
 }
 
+// ---- cross-lane steps for a fully active wave (every lane of the wave
+// takes part; results are wave-uniform).  DPP moves within rows of 16 lanes
+// (quad swaps, half-row and row mirrors) reduce each row; reads of lanes 0,
+// 16, 32 and 48 combine the rows.  Counts come from ballots.
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <- 7 - i within 8 lanes
+constexpr int kDppMirror = 0x140;      // lane i <- 15 - i within 16 lanes
+constexpr int kDppShr = 0x110;         // + n: lane i <- i - n within the row, 0 below
+
+template <int C>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, C, 0xf, 0xf, true);
+}
+__device__ __forceinline__ uint32_t lane_u32(uint32_t x, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
+}
+
+__device__ __forceinline__ uint32_t fw_min_u32(uint32_t x) {
+  x = min(x, dpp_u32<kDppXor1>(x));
+  x = min(x, dpp_u32<kDppXor2>(x));
+  x = min(x, dpp_u32<kDppHalfMirror>(x));
+  x = min(x, dpp_u32<kDppMirror>(x));
+  return min(min(lane_u32(x, 0), lane_u32(x, 16)), min(lane_u32(x, 32), lane_u32(x, 48)));
+}
+
+__device__ __forceinline__ int fw_sum_i32(int v) {
+  uint32_t x = (uint32_t)v;
+  x += dpp_u32<kDppXor1>(x);
+  x += dpp_u32<kDppXor2>(x);
+  x += dpp_u32<kDppHalfMirror>(x);
+  x += dpp_u32<kDppMirror>(x);
+  return (int)(lane_u32(x, 0) + lane_u32(x, 16) + lane_u32(x, 32) + lane_u32(x, 48));
+}
+
+template <int C>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
+  return ((uint64_t)dpp_u32<C>((uint32_t)(x >> 32)) << 32) | dpp_u32<C>((uint32_t)x);
+}
+__device__ __forceinline__ uint64_t lane_u64(uint64_t x, int l) {
+  return ((uint64_t)lane_u32((uint32_t)(x >> 32), l) << 32) | lane_u32((uint32_t)x, l);
+}
+__device__ __forceinline__ uint64_t min_u64(uint64_t a, uint64_t b) { return b < a ? b : a; }
+
+__device__ __forceinline__ uint64_t fw_min_u64(uint64_t x) {
+  x = min_u64(x, dpp_u64<kDppXor1>(x));
+  x = min_u64(x, dpp_u64<kDppXor2>(x));
+  x = min_u64(x, dpp_u64<kDppHalfMirror>(x));
+  x = min_u64(x, dpp_u64<kDppMirror>(x));
+  return min_u64(min_u64(lane_u64(x, 0), lane_u64(x, 16)), min_u64(lane_u64(x, 32), lane_u64(x, 48)));
+}
+
+// Inclusive prefix sum over the wave; *total gets the wave's sum.
+__device__ __forceinline__ int fw_scan_i32(int v, int* total) {
+  uint32_t x = (uint32_t)v;
+  x += dpp_u32<kDppShr + 1>(x);
+  x += dpp_u32<kDppShr + 2>(x);
+  x += dpp_u32<kDppShr + 4>(x);
+  x += dpp_u32<kDppShr + 8>(x);
+  const uint32_t t0 = lane_u32(x, 15), t1 = lane_u32(x, 31), t2 = lane_u32(x, 47),
+                 t3 = lane_u32(x, 63);
+  const int row = (threadIdx.x & 63) >> 4;
+  x += (row > 0 ? t0 : 0u) + (row > 1 ? t1 : 0u) + (row > 2 ? t2 : 0u);
+  *total = (int)(t0 + t1 + t2 + t3);
+  return (int)x;
+}
+
 __device__ __forceinline__ float wave_sum(float x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);

@@ -153,7 +153,7 @@ __global__ __launch_bounds__(64 * NW) void batch_kernel(BatchArgs A) {
         }
         const uint64_t kmin = wave_min_u64(key);
         const int first = __ffsll((unsigned long long)__ballot(key == kmin)) - 1;
-        a = __shfl((unsigned long long)a, first);
+        a = lane_u64(a, first);
         key = kmin;
         wave_sync();
         const int ge0 = (int)(uint32_t)(a >> 32), gmi = (int)(uint32_t)(a & 0xffffffffu);

@@ -219,9 +219,7 @@ __global__ __launch_bounds__(64 * kGeoWaves) void geom_bwd_kernel(
   } else {
     // soft-min weights of the axis overlaps (hard minimum: the first one)
     const float dp = lane < K ? fmaxf(dl, 0.0f) : __builtin_huge_valf();
-    float mu = dp;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) mu = fminf(mu, __shfl_xor(mu, o));
+    const float mu = wave_min_f32(dp);
     float wq;
     if (F.hard) {
       const uint64_t k = lane < K ? (((uint64_t)__float_as_uint(dp) << 32) | (uint32_t)lane) : ~0ull;

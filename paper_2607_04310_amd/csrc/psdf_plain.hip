@@ -152,7 +152,7 @@ __global__ __launch_bounds__(64 * kEpiWaves) void epilogue_kernel(
     const uint64_t kmin = wave_min_u64(key);
     const uint64_t hit = __ballot(key == kmin);
     const int first = __ffsll((unsigned long long)hit) - 1;
-    a = __shfl((unsigned long long)a, first);
+    a = lane_u64(a, first);
     key = kmin;
     if (lane == 0) O.keys[s] = key;
     e0 = (int)(uint32_t)(a >> 32);

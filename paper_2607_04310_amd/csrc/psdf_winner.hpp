@@ -46,22 +46,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Wave-wide minimum of a 32-bit unsigned value.
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, o));
-  return x;
-}
-
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint64_t y = __shfl_xor((unsigned long long)x, o);
-    x = y < x ? y : x;
-  }
-  return x;
-}
-
 // ---- cross-lane steps for a fully active wave (every lane of the wave
 // takes part; results are wave-uniform).  DPP moves within rows of 16 lanes
 // (quad swaps, half-row and row mirrors) reduce each row; reads of lanes 0,
@@ -129,11 +113,33 @@ __device__ __forceinline__ int fw_scan_i32(int v, int* total) {
   return (int)x;
 }
 
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return x;
+__device__ __forceinline__ float fw_sum_f32(float x) {
+  x += __uint_as_float(dpp_u32<kDppXor1>(__float_as_uint(x)));
+  x += __uint_as_float(dpp_u32<kDppXor2>(__float_as_uint(x)));
+  x += __uint_as_float(dpp_u32<kDppHalfMirror>(__float_as_uint(x)));
+  x += __uint_as_float(dpp_u32<kDppMirror>(__float_as_uint(x)));
+  const uint32_t u = __float_as_uint(x);
+  return (__uint_as_float(lane_u32(u, 0)) + __uint_as_float(lane_u32(u, 16))) +
+         (__uint_as_float(lane_u32(u, 32)) + __uint_as_float(lane_u32(u, 48)));
 }
+
+__device__ __forceinline__ float fw_min_f32(float x) {
+  x = fminf(x, __uint_as_float(dpp_u32<kDppXor1>(__float_as_uint(x))));
+  x = fminf(x, __uint_as_float(dpp_u32<kDppXor2>(__float_as_uint(x))));
+  x = fminf(x, __uint_as_float(dpp_u32<kDppHalfMirror>(__float_as_uint(x))));
+  x = fminf(x, __uint_as_float(dpp_u32<kDppMirror>(__float_as_uint(x))));
+  const uint32_t u = __float_as_uint(x);
+  return fminf(fminf(__uint_as_float(lane_u32(u, 0)), __uint_as_float(lane_u32(u, 16))),
+               fminf(__uint_as_float(lane_u32(u, 32)), __uint_as_float(lane_u32(u, 48))));
+}
+
+// Wave-wide reductions used by the kernels; every lane of the wave takes
+// part (the callers reach them in wave-uniform control flow).
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) { return fw_min_u32(x); }
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) { return fw_min_u64(x); }
+__device__ __forceinline__ float wave_min_f32(float x) { return fw_min_f32(x); }
+__device__ __forceinline__ float wave_sum(float x) { return fw_sum_f32(x); }
+
 
 // Copy the footprint constants into LDS, lane l <-> slot l: one vector load
 // per array.  F must be addressable memory (global memory or the kernel
@@ -197,7 +203,7 @@ __device__ __forceinline__ void wave_stages_t(const FpConst& F, const float* __r
       const uint64_t hit = __ballot(k == kmin);
       const int first = __ffsll((unsigned long long)hit) - 1;
       key = ((uint64_t)kmin << 32) | (uint32_t)(obase + first);
-      a = ((uint64_t)(uint32_t)__shfl(e0, first) << 32) | (uint32_t)__shfl(mi, first);
+      a = ((uint64_t)lane_u32((uint32_t)e0, first) << 32) | lane_u32((uint32_t)mi, first);
     }
     emit(t, key, a);
   }
@@ -358,9 +364,7 @@ __device__ __forceinline__ void winner_adjoint(const FpConst& F, const FpLds& FL
     // weight of axis q is its softmax weight (hard minimum: 1 at the first
     // minimum); d delta+ / d delta = 1 for delta > 0, else 0.
     const float dp = lane < K ? fmaxf(dl, 0.0f) : __builtin_huge_valf();
-    float mu = dp;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) mu = fminf(mu, __shfl_xor(mu, o));
+    const float mu = wave_min_f32(dp);
     float w;
     if (F.hard) {
       const uint64_t k = lane < K ? (((uint64_t)__float_as_uint(dp) << 32) | (uint32_t)lane) : ~0ull;

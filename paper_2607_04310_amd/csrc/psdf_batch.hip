@@ -221,11 +221,7 @@ struct psdf_batch_plan {
   size_t items_cap = 0;
   uint64_t* d_partial = nullptr;   // partial keys, then aux words
   size_t partial_cap = 0;          // entries of each
-  unsigned* d_blockcnt = nullptr;
-  size_t blockcnt_cap = 0;
-  unsigned* d_ctrl = nullptr;        // two counters per group
-  int* d_empty_rows = nullptr;       // stage rows of instances without obstacles
-  int n_empty_rows = 0;
+  unsigned* d_ctrl = nullptr;        // item counter per group
   // screening: stage -> instance, stage rows grouped by footprint size,
   // failed lists and counters (three per group)
   int* d_stage_inst = nullptr;
@@ -346,7 +342,7 @@ int build_items(psdf_batch_plan* p, Shape sh) {
   std::vector<BatchInst> inst(p->n_inst);
   std::vector<BatchItem> items;
   std::vector<double> cost;
-  size_t part = 0, blocks = 0, circ = 0;
+  size_t part = 0, circ = 0;
   for (int k = 0; k < p->n_inst; ++k) {
     const psdf_batch_desc& d = p->desc[k];
     BatchInst& b = inst[k];
@@ -354,12 +350,10 @@ int build_items(psdf_batch_plan* p, Shape sh) {
     b.obst_off = d.obst_off; b.M = d.M; b.m = p->fp[k].m;
     b.nt = (d.M + tile - 1) / tile;
     b.part_off = (int)part;
-    b.blk_off = (int)blocks;
     b.circ_off = (int)circ;
     circ += d.M;
     const int nb = (d.N + sh.sb - 1) / sh.sb;
     part += (size_t)d.N * b.nt;
-    blocks += nb;
     if (d.M == 0) continue;
     const double per_edge = (double)d.E / std::max(1, d.M);
     for (int bi = 0; bi < nb; ++bi) {
@@ -382,7 +376,7 @@ int build_items(psdf_batch_plan* p, Shape sh) {
   std::vector<BatchItem> sorted(items.size());
   for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
 
-  if (part > p->partial_cap || sorted.size() > p->items_cap || blocks > p->blockcnt_cap)
+  if (part > p->partial_cap || sorted.size() > p->items_cap)
     return set_error(PSDF_EINVAL, "internal: plan capacity exceeded");
   hipError_t err = hipMemcpy(p->d_inst, inst.data(), inst.size() * sizeof(BatchInst),
                              hipMemcpyHostToDevice);
@@ -417,26 +411,90 @@ BatchArgs make_args(psdf_batch_plan* p, const float* poses, const float* ax, con
   a.direct = p->shape.direct;
   a.poses = poses; a.ax = ax; a.ay = ay; a.bx = bx; a.by = by; a.off = off;
   a.partial = p->d_partial; a.aux = p->d_partial + p->partial_cap;
-  a.blockcnt = p->d_blockcnt; a.ctrl = p->d_ctrl;   // per-group slices set by enqueue
+  a.ctrl = p->d_ctrl;   // per-group slices set by enqueue
   a.d = d; a.edge = edge; a.obst = obst; a.grad = grad; a.keys = keys;
   return a;
 }
 
-// Stages of instances without obstacles: the result of an empty edge set
-// (d = +inf, no winner, zero gradient, the empty key).
-__global__ void empty_rows_kernel(const int* __restrict__ rows, int n, float* __restrict__ d,
-                                  int* __restrict__ edge, int* __restrict__ obst,
-                                  float* __restrict__ grad, uint64_t* __restrict__ keys) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int s = rows[i];
-  d[s] = __builtin_huge_valf();
-  edge[s] = -1;
-  obst[s] = -1;
-  grad[3 * s + 0] = 0.f;
-  grad[3 * s + 1] = 0.f;
-  grad[3 * s + 2] = 0.f;
-  keys[s] = kEmptyKey;
+// One wave per stage (global row g): the stage's winning key, from the
+// minimum of its partial row (partial non-null: the winning column's aux
+// word carries the winner's global edge range) or from keys[g] (the screened
+// path: the range from the offsets); then the winner adjoint and the
+// outputs.  A stage without a partial column (no obstacle) gets the empty
+// key and the empty-set result.  Block 0 also clears ctrl[0..n_ctrl), the
+// item counters of the batch launches before it on the stream.
+__global__ __launch_bounds__(256) void batch_finish_kernel(
+    const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
+    const int* __restrict__ stage_inst, int S, const float* __restrict__ poses,
+    const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ bx,
+    const float* __restrict__ by, const int* __restrict__ off,
+    const uint64_t* __restrict__ partial, const uint64_t* __restrict__ aux,
+    uint64_t* __restrict__ keys, float* __restrict__ d, int* __restrict__ edge,
+    int* __restrict__ obst, float* __restrict__ grad, unsigned* __restrict__ ctrl, int n_ctrl) {
+  __shared__ FpLds fl[4];
+  __shared__ WinnerLds wl[4];
+  if (blockIdx.x == 0 && (int)threadIdx.x < n_ctrl) ctrl[threadIdx.x] = 0u;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = blockIdx.x * 4 + w;
+  if (g >= S) return;
+  const int inst = __builtin_amdgcn_readfirstlane(stage_inst[g]);
+  const BatchInst in = insts[inst];
+  const FpConst& F = fps[inst];
+  stage_footprint(fl[w], F);
+  const float* p = poses + 3 * g;
+  const float px = p[0], py = p[1];
+  float sn, cs;
+  sincosf(p[2], &sn, &cs);
+  uint64_t key = kEmptyKey;
+  int e0 = 0, mi = 0;
+  bool valid;
+  if (partial) {
+    uint64_t a = 0;
+    const size_t row = (size_t)in.part_off + (size_t)(g - in.pose_off) * in.nt;
+    for (int j = lane; j < in.nt; j += 64) {
+      const uint64_t k = partial[row + j];
+      if (k < key) { key = k; a = aux[row + j]; }
+    }
+    const uint64_t kmin = wave_min_u64(key);
+    const int first = __ffsll((unsigned long long)__ballot(key == kmin)) - 1;
+    a = lane_u64(a, first);
+    key = kmin;
+    e0 = (int)(uint32_t)(a >> 32);
+    mi = (int)(uint32_t)(a & 0xffffffffu);
+    valid = key != kEmptyKey && (key >> 32) != 0 && mi >= 1 && mi <= kMaxObst;
+  } else {
+    key = keys[g];
+    const int i = (int)(key & 0xffffffffu);
+    valid = key != kEmptyKey && (key >> 32) != 0 && (uint64_t)i < (uint64_t)in.M;
+    if (valid) {
+      e0 = off[in.obst_off + i];
+      mi = off[in.obst_off + i + 1] - e0;
+      e0 += in.edge_off;
+      valid = mi >= 1 && mi <= kMaxObst && e0 >= in.edge_off && e0 <= in.edge_off + in.E - mi;
+    }
+  }
+  wave_sync();
+  float dv = __builtin_huge_valf(), gv[3] = {0.f, 0.f, 0.f};
+  int ev = -1, ov = -1;
+  if (key != kEmptyKey && !valid) {
+    dv = __builtin_nanf("");
+    gv[0] = gv[1] = gv[2] = dv;
+  } else if (valid) {
+    int jstar = 0;
+    winner_adjoint(F, fl[w], wl[w], ax, ay, bx, by, e0, mi, cs, sn, px, py, true, jstar, gv);
+    dv = from_orderable((uint32_t)(key >> 32));
+    ov = (int)(key & 0xffffffffu);
+    ev = e0 - in.edge_off + jstar;
+  }
+  if (lane == 0) {
+    keys[g] = key;
+    d[g] = dv;
+    edge[g] = ev;
+    obst[g] = ov;
+    grad[3 * g + 0] = gv[0];
+    grad[3 * g + 1] = gv[1];
+    grad[3 * g + 2] = gv[2];
+  }
 }
 
 int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay,
@@ -445,21 +503,18 @@ int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay
   if (p->total_stages == 0) return PSDF_OK;
   const BatchArgs a = make_args(p, poses, ax, ay, bx, by, off, d, edge, obst, grad, keys);
   auto enqueue = [&](hipStream_t st) -> hipError_t {
-    if (p->n_empty_rows > 0) {
-      empty_rows_kernel<<<(p->n_empty_rows + 255) / 256, 256, 0, st>>>(
-          p->d_empty_rows, p->n_empty_rows, d, edge, obst, grad, keys);
-      hipError_t err = hipGetLastError();
-      if (err != hipSuccess) return err;
-    }
     for (const auto& g : p->groups) {
       BatchArgs ga = a;
       ga.items = a.items + g.start;
       ga.n_items = g.count;
-      ga.ctrl = a.ctrl + 2 * group_of(g.mf);
+      ga.ctrl = a.ctrl + group_of(g.mf);
       hipError_t err = launch_batch(g.mf, p->mi_class, p->shape.nw, g.grid, ga, st);
       if (err != hipSuccess) return err;
     }
-    return hipSuccess;
+    batch_finish_kernel<<<(p->total_stages + 3) / 4, 256, 0, st>>>(
+        p->d_fp, p->d_inst, p->d_stage_inst, p->total_stages, poses, ax, ay, bx, by, off,
+        a.partial, a.aux, keys, d, edge, obst, grad, p->d_ctrl, kGroups);
+    return hipGetLastError();
   };
   if (!use_graph) {
     timer_begin(stream);
@@ -486,61 +541,6 @@ int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay
   hipError_t err = hipGraphLaunch(p->exec, stream);
   timer_end(stream);
   return hip_status(err);
-}
-
-// One wave per stage: the winner adjoint of keys[s] (local obstacle index)
-// and the outputs, for batches whose keys come from the screened path.
-__global__ __launch_bounds__(256) void batch_epilogue_kernel(
-    const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
-    const int* __restrict__ stage_inst, int S, const float* __restrict__ poses,
-    const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ bx,
-    const float* __restrict__ by, const int* __restrict__ off, const uint64_t* __restrict__ keys,
-    float* __restrict__ d, int* __restrict__ edge, int* __restrict__ obst,
-    float* __restrict__ grad) {
-  __shared__ FpLds fl[4];
-  __shared__ WinnerLds wl[4];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int s = blockIdx.x * 4 + w;
-  if (s >= S) return;
-  const int inst = __builtin_amdgcn_readfirstlane(stage_inst[s]);
-  const BatchInst in = insts[inst];
-  const FpConst& F = fps[inst];
-  stage_footprint(fl[w], F);
-  const uint64_t key = keys[s];
-  const float* p = poses + 3 * s;
-  const float px = p[0], py = p[1];
-  float sn, cs;
-  sincosf(p[2], &sn, &cs);
-  const int i = (int)(key & 0xffffffffu);
-  bool valid = key != kEmptyKey && (key >> 32) != 0 && (uint64_t)i < (uint64_t)in.M;
-  int e0 = 0, mi = 0;
-  if (valid) {
-    e0 = off[in.obst_off + i];
-    mi = off[in.obst_off + i + 1] - e0;
-    e0 += in.edge_off;
-    valid = mi >= 1 && mi <= kMaxObst && e0 >= in.edge_off && e0 <= in.edge_off + in.E - mi;
-  }
-  wave_sync();
-  float dv = __builtin_huge_valf(), g[3] = {0.f, 0.f, 0.f};
-  int ev = -1, ov = -1;
-  if (key != kEmptyKey && !valid) {
-    dv = __builtin_nanf("");
-    g[0] = g[1] = g[2] = dv;
-  } else if (valid) {
-    int jstar = 0;
-    winner_adjoint(F, fl[w], wl[w], ax, ay, bx, by, e0, mi, cs, sn, px, py, true, jstar, g);
-    dv = from_orderable((uint32_t)(key >> 32));
-    ov = i;
-    ev = e0 - in.edge_off + jstar;
-  }
-  if (lane == 0) {
-    d[s] = dv;
-    edge[s] = ev;
-    obst[s] = ov;
-    grad[3 * s + 0] = g[0];
-    grad[3 * s + 1] = g[1];
-    grad[3 * s + 2] = g[2];
-  }
 }
 
 hipError_t launch_screen(int mf, int mi_class, int grid, const ScreenArgs& a, hipStream_t st) {
@@ -633,9 +633,9 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
   }
   timer_end(stream);
   if (err == hipSuccess) {
-    batch_epilogue_kernel<<<(p->total_stages + 3) / 4, 256, 0, stream>>>(
-        p->d_fp, p->d_inst, p->d_stage_inst, p->total_stages, poses, ax, ay, bx, by, off, keys, d,
-        edge, obst, grad);
+    batch_finish_kernel<<<(p->total_stages + 3) / 4, 256, 0, stream>>>(
+        p->d_fp, p->d_inst, p->d_stage_inst, p->total_stages, poses, ax, ay, bx, by, off, nullptr,
+        nullptr, keys, d, edge, obst, grad, nullptr, 0);
     err = hipGetLastError();
   }
   return hip_status(err);
@@ -666,10 +666,8 @@ void psdf_batch_plan_destroy(psdf_batch_plan* p) {
   (void)hipFree(p->d_inst);
   (void)hipFree(p->d_items);
   (void)hipFree(p->d_partial);
-  (void)hipFree(p->d_blockcnt);
   (void)hipFree(p->d_ctrl);
   (void)hipFree(p->d_stage_inst);
-  (void)hipFree(p->d_empty_rows);
   (void)hipFree(p->d_stage_list);
   (void)hipFree(p->d_failed);
   (void)hipFree(p->d_sctrl);
@@ -696,7 +694,7 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
   p->flags = flags;
   p->desc.assign(desc, desc + n_inst);
   p->fp.resize(n_inst);
-  size_t part_max = 0, blocks_max = 0, items_max = 0;
+  size_t part_max = 0, items_max = 0;
   long stages = 0;
   for (int k = 0; k < n_inst; ++k) {
     const psdf_batch_desc& d = desc[k];
@@ -714,7 +712,6 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
     stages += d.N;
     const size_t nt64 = (size_t)(d.M + 63) / 64;
     part_max += (size_t)d.N * nt64;
-    blocks_max += (size_t)d.N;
     items_max += (size_t)d.N * nt64;
   }
   if (stages > 0x7fffffffL) { delete p; return set_error(PSDF_ETOOBIG, "too many stages"); }
@@ -725,15 +722,12 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
   p->cu = cu > 0 ? cu : 256;
   p->partial_cap = std::max<size_t>(1, part_max);
   p->items_cap = std::max<size_t>(1, items_max);
-  p->blockcnt_cap = std::max<size_t>(1, blocks_max);
   if (err == hipSuccess) err = hipMalloc(&p->d_fp, std::max(1, n_inst) * sizeof(FpConst));
   if (err == hipSuccess) err = hipMalloc(&p->d_inst, std::max(1, n_inst) * sizeof(BatchInst));
   if (err == hipSuccess) err = hipMalloc(&p->d_items, p->items_cap * sizeof(BatchItem));
   if (err == hipSuccess) err = hipMalloc(&p->d_partial, 2 * p->partial_cap * sizeof(uint64_t));
-  if (err == hipSuccess) err = hipMalloc(&p->d_blockcnt, p->blockcnt_cap * sizeof(unsigned));
-  if (err == hipSuccess) err = hipMalloc(&p->d_ctrl, 2 * kGroups * sizeof(unsigned));
-  if (err == hipSuccess) err = hipMemset(p->d_blockcnt, 0, p->blockcnt_cap * sizeof(unsigned));
-  if (err == hipSuccess) err = hipMemset(p->d_ctrl, 0, 2 * kGroups * sizeof(unsigned));
+  if (err == hipSuccess) err = hipMalloc(&p->d_ctrl, kGroups * sizeof(unsigned));
+  if (err == hipSuccess) err = hipMemset(p->d_ctrl, 0, kGroups * sizeof(unsigned));
   if (err == hipSuccess && n_inst > 0)
     err = hipMemcpy(p->d_fp, p->fp.data(), n_inst * sizeof(FpConst), hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
@@ -774,17 +768,6 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
       err = hipMemcpy(p->d_stage_inst, stage_inst.data(), S * sizeof(int), hipMemcpyHostToDevice);
     if (err == hipSuccess && !list.empty())
       err = hipMemcpy(p->d_stage_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice);
-    std::vector<int> empty_rows;
-    for (int k = 0; k < n_inst; ++k)
-      if (desc[k].M == 0)
-        for (int t = 0; t < desc[k].N; ++t) empty_rows.push_back(desc[k].pose_off + t);
-    p->n_empty_rows = (int)empty_rows.size();
-    if (err == hipSuccess && !empty_rows.empty()) {
-      err = hipMalloc(&p->d_empty_rows, empty_rows.size() * sizeof(int));
-      if (err == hipSuccess)
-        err = hipMemcpy(p->d_empty_rows, empty_rows.data(), empty_rows.size() * sizeof(int),
-                        hipMemcpyHostToDevice);
-    }
   }
   if (err != hipSuccess) {
     int rc = hip_status(err);

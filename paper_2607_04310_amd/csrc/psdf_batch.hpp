@@ -5,12 +5,12 @@
 // counter, largest first.  For an item, lane <-> obstacle of the tile (edges
 // in registers), the work-group loops over the stage block exactly as the
 // plain per-stage minimum kernel does and writes one partial key and aux word
-// per stage.  The work-group that completes the last tile of a stage block
-// (an agent-scope acq_rel counter per block) then runs the winner adjoint of
-// those stages (one wave per stage) and writes the outputs.  The last
-// work-group to leave resets the item counter, and every block counter is
-// reset by the work-group that consumed it, so consecutive launches (and
-// graph replays) start from zero.  No work-group ever waits for another.
+// per stage.  A second kernel (batch_finish_kernel, one wave per stage)
+// reduces each stage's partial row, runs the winner adjoint and writes the
+// outputs, and clears the item counters for the next launch: the kernel
+// boundary orders the partials before their readers, which costs less on
+// this chip than a device-scope release per item (each one writes back the
+// L2 of the issuing XCD).  No work-group ever waits for another.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,7 +25,6 @@ struct BatchInst {
   int pose_off, N, edge_off, E, obst_off, M;
   int part_off;   // first partial slot: partial[part_off + s * nt + tile]
   int nt;         // obstacle tiles
-  int blk_off;    // first stage-block counter
   int m;          // footprint vertices
   int circ_off;   // first bounding circle of this instance's obstacles (screening)
 };
@@ -49,8 +48,7 @@ struct BatchArgs {
   const int* off;
   uint64_t* partial;
   uint64_t* aux;
-  unsigned* blockcnt;
-  unsigned* ctrl;   // this launch's [0] next item, [1] work-groups done
+  unsigned* ctrl;   // this launch's [0] next item
   float* d;
   int* edge;
   int* obst;
@@ -64,13 +62,11 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // class, NW waves per work-group (64 NW obstacles per tile).
 template <int MF, int MI, int NW>
 __global__ __launch_bounds__(64 * NW) void batch_kernel(BatchArgs A) {
-  __shared__ int s_item, s_last;
+  __shared__ int s_item;
   __shared__ float4 st[kMaxStageBlock];
   __shared__ float4 rft[kMaxStageBlock * MF];
   __shared__ uint64_t wk[NW][kMaxStageBlock];
   __shared__ uint64_t wa[NW][kMaxStageBlock];
-  __shared__ FpLds fl[NW];
-  __shared__ WinnerLds wl[NW];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
   for (int round = 0;; ++round) {
@@ -123,75 +119,6 @@ __global__ __launch_bounds__(64 * NW) void batch_kernel(BatchArgs A) {
       A.aux[slot] = a;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned* cnt = &A.blockcnt[in.blk_off + s0 / A.sb];
-      const unsigned done =
-          __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-      s_last = done == (unsigned)in.nt;
-      if (s_last) __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    if (s_last) {
-      // every tile of this stage block has written its partials: run the
-      // winner adjoint of its stages, one wave per stage
-      stage_footprint(fl[w], F);
-      for (int t = w; t < ns; t += NW) {
-        const int s = s0 + t, g = in.pose_off + s;
-        const float* p = A.poses + 3 * g;
-        const float px = p[0], py = p[1];
-        float sn, cs;
-        sincosf(p[2], &sn, &cs);
-        uint64_t key = kEmptyKey, a = 0;
-        const size_t row = (size_t)in.part_off + (size_t)s * in.nt;
-        for (int j = lane; j < in.nt; j += 64) {
-          const uint64_t k = __hip_atomic_load(&A.partial[row + j], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-          if (k < key) {
-            key = k;
-            a = __hip_atomic_load(&A.aux[row + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
-        }
-        const uint64_t kmin = wave_min_u64(key);
-        const int first = __ffsll((unsigned long long)__ballot(key == kmin)) - 1;
-        a = lane_u64(a, first);
-        key = kmin;
-        wave_sync();
-        const int ge0 = (int)(uint32_t)(a >> 32), gmi = (int)(uint32_t)(a & 0xffffffffu);
-        const bool valid = key != kEmptyKey && (key >> 32) != 0 && gmi >= 1 && gmi <= kMaxObst;
-        float dv = __builtin_huge_valf(), gv[3] = {0.f, 0.f, 0.f};
-        int ev = -1, ov = -1;
-        if (key != kEmptyKey && !valid) {
-          dv = __builtin_nanf("");
-          gv[0] = gv[1] = gv[2] = dv;
-        } else if (valid) {
-          int jstar = 0;
-          winner_adjoint(F, fl[w], wl[w], A.ax, A.ay, A.bx, A.by, ge0, gmi, cs, sn, px, py, true,
-                         jstar, gv);
-          dv = from_orderable((uint32_t)(key >> 32));
-          ov = (int)(key & 0xffffffffu);
-          ev = ge0 - in.edge_off + jstar;
-        }
-        if (lane == 0) {
-          A.keys[g] = key;
-          A.d[g] = dv;
-          A.edge[g] = ev;
-          A.obst[g] = ov;
-          A.grad[3 * g + 0] = gv[0];
-          A.grad[3 * g + 1] = gv[1];
-          A.grad[3 * g + 2] = gv[2];
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // the last work-group out resets the item counter for the next launch
-  if (!A.direct && threadIdx.x == 0) {
-    const unsigned done =
-        __hip_atomic_fetch_add(&A.ctrl[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    if (done == gridDim.x) {
-      __hip_atomic_store(&A.ctrl[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&A.ctrl[1], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
   }
 }
 

@@ -230,6 +230,7 @@ struct psdf_batch_plan {
   unsigned* d_sctrl = nullptr;
   float4* d_circ = nullptr;   // bounding circles, sum M
   float4* d_hlist = nullptr;  // horizon lists (circle, index), sum M
+  uint4* d_frag = nullptr;    // the screener's lane fragments, kFragWords x 64
   int* d_hcount = nullptr;    // per instance
   uint32_t* d_hrest = nullptr;
   struct SGroup { int mf, start, count, max_tiles; };
@@ -414,6 +415,16 @@ BatchArgs make_args(psdf_batch_plan* p, const float* poses, const float* ax, con
   a.ctrl = p->d_ctrl;   // per-group slices set by enqueue
   a.d = d; a.edge = edge; a.obst = obst; a.grad = grad; a.keys = keys;
   return a;
+}
+
+// The screener network's per-lane weight fragments, once per screened call
+// (one wave), so that every stage's work-group reads them with coalesced
+// vector loads instead of gathering the parameters.
+__global__ __launch_bounds__(64) void mlp_frag_kernel(const float* __restrict__ theta,
+                                                      uint4* __restrict__ table) {
+  MlpFrag f;
+  mlp_load(theta, f);
+  mlp_frag_store(f, table);
 }
 
 // One wave per stage (global row g): the stage's winning key, from the
@@ -602,7 +613,7 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
   a.poses = poses; a.ax = ax; a.ay = ay; a.bx = bx; a.by = by; a.off = off;
   a.circ = p->d_circ;
   a.hlist = p->d_hlist; a.hcount = p->d_hcount; a.hrest = p->d_hrest;
-  a.theta = theta; a.pool = pool; a.topk = topk; a.keys = keys;
+  a.theta = theta; a.frag = p->d_frag; a.pool = pool; a.topk = topk; a.keys = keys;
   a.stage_cand = stage_cand; a.stage_cert = stage_cert; a.cand_keys = cand_keys;
   timer_begin(stream);
   hipError_t err = hipSuccess;
@@ -617,6 +628,10 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
           p->d_fp, p->d_inst, poses, p->d_circ, p->d_hlist, p->d_hcount, p->d_hrest);
       err = hipGetLastError();
     }
+  }
+  if (err == hipSuccess && theta) {
+    mlp_frag_kernel<<<1, 64, 0, stream>>>(theta, p->d_frag);
+    err = hipGetLastError();
   }
   for (const auto& g : p->sgroups) {
     if (err != hipSuccess) break;
@@ -673,6 +688,7 @@ void psdf_batch_plan_destroy(psdf_batch_plan* p) {
   (void)hipFree(p->d_sctrl);
   (void)hipFree(p->d_circ);
   (void)hipFree(p->d_hlist);
+  (void)hipFree(p->d_frag);
   (void)hipFree(p->d_hcount);
   (void)hipFree(p->d_hrest);
   (void)hipSetDevice(cur);
@@ -755,6 +771,7 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
     for (int k = 0; k < n_inst; ++k) sumM += desc[k].M;
     err = hipMalloc(&p->d_circ, std::max<size_t>(1, sumM) * sizeof(float4));
     if (err == hipSuccess) err = hipMalloc(&p->d_hlist, std::max<size_t>(1, sumM) * sizeof(float4));
+    if (err == hipSuccess) err = hipMalloc(&p->d_frag, (size_t)kFragWords * 64 * sizeof(uint4));
     if (err == hipSuccess)
       err = hipMalloc(&p->d_hcount, std::max<size_t>(1, (size_t)n_inst) * sizeof(int));
     if (err == hipSuccess)

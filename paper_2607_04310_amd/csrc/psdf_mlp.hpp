@@ -33,11 +33,9 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef short bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// Round to BF16, nearest-even (finite inputs).
-__device__ __forceinline__ short to_bf16(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
+// Round to BF16, nearest-even (finite inputs): the hardware conversion
+// (v_cvt_pk_bf16_f32, two values per instruction).
+__device__ __forceinline__ short to_bf16(float f) { return __builtin_bit_cast(short, (__bf16)f); }
 
 __device__ __forceinline__ int perm_unit(int kb, int g, int r) {
   return 32 * kb + (r < 4 ? 4 * g + r : 16 + 4 * g + (r - 4));
@@ -74,6 +72,27 @@ __device__ __forceinline__ void mlp_load(const float* __restrict__ th, MlpFrag& 
   f.b3 = th[kOffB3];
 }
 
+// The fragments of all 64 lanes as a table of kFragWords 16-byte words per
+// lane, word k of lane l at [k * 64 + l] (coalesced across the wave): built
+// once per call by mlp_frag_kernel, read with kFragWords vector loads.
+constexpr int kFragWords = (sizeof(MlpFrag) + 15) / 16;
+
+__device__ __forceinline__ void mlp_frag_store(const MlpFrag& f, uint4* __restrict__ table) {
+  const int l = threadIdx.x & 63;
+  uint4 w[kFragWords] = {};
+  __builtin_memcpy(w, &f, sizeof(MlpFrag));
+#pragma unroll
+  for (int k = 0; k < kFragWords; ++k) table[k * 64 + l] = w[k];
+}
+
+__device__ __forceinline__ void mlp_frag_fetch(const uint4* __restrict__ table, MlpFrag& f) {
+  const int l = threadIdx.x & 63;
+  uint4 w[kFragWords];
+#pragma unroll
+  for (int k = 0; k < kFragWords; ++k) w[k] = table[k * 64 + l];
+  __builtin_memcpy(&f, w, sizeof(MlpFrag));
+}
+
 // Forward intermediates of one 16-pair group (lane l: pair n = l % 16).
 struct MlpAct {
   f32x4 h1pre[4];   // H1^T pre-activation, units 16 mb + 4g + r
@@ -82,15 +101,8 @@ struct MlpAct {
   float y;          // output of pair n (all four lane groups agree)
 };
 
-// x0..x3: the features of pair n (read by lanes g == 0 only).
-__device__ __forceinline__ void mlp_forward16(const MlpFrag& f, float x0, float x1, float x2,
-                                              float x3, MlpAct& a) {
-  const int l = threadIdx.x & 63, g = l >> 4;
-  bf16x4 bx;
-  bx[0] = g == 0 ? to_bf16(x0) : (short)0;
-  bx[1] = g == 0 ? to_bf16(x1) : (short)0;
-  bx[2] = g == 0 ? to_bf16(x2) : (short)0;
-  bx[3] = g == 0 ? to_bf16(x3) : (short)0;
+// bx: the BF16 features of pair n in lanes g == 0, zero in the other lanes.
+__device__ __forceinline__ void mlp_forward16_bf(const MlpFrag& f, bf16x4 bx, MlpAct& a) {
   short h1b[4][4];
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) {
@@ -123,6 +135,24 @@ __device__ __forceinline__ void mlp_forward16(const MlpFrag& f, float x0, float 
   part += __shfl_xor(part, 16);
   part += __shfl_xor(part, 32);
   a.y = part + f.b3;
+}
+
+// BF16 image of pair features x0..x3, as the network reads them.
+__device__ __forceinline__ bf16x4 mlp_features(float x0, float x1, float x2, float x3) {
+  bf16x4 bx;
+  bx[0] = to_bf16(x0);
+  bx[1] = to_bf16(x1);
+  bx[2] = to_bf16(x2);
+  bx[3] = to_bf16(x3);
+  return bx;
+}
+
+// x0..x3: the features of pair n (read by lanes g == 0 only).
+__device__ __forceinline__ void mlp_forward16(const MlpFrag& f, float x0, float x1, float x2,
+                                              float x3, MlpAct& a) {
+  const int g = (threadIdx.x & 63) >> 4;
+  const bf16x4 zero = {0, 0, 0, 0};
+  mlp_forward16_bf(f, g == 0 ? mlp_features(x0, x1, x2, x3) : zero, a);
 }
 
 }  // namespace psdf

@@ -38,6 +38,7 @@ constexpr int kScreenMaxM = kScreenThreads * kScreenKeysPerThread;   // 16384
 constexpr int kStageKeys = 8;                                  // horizon entries per thread (stage pass)
 constexpr int kHorizonCap = kScreenThreads * kStageKeys;       // 2048
 constexpr int kPoolCap = 512;                                  // pool capacity (ties included)
+constexpr int kFeatSlots = 1024;                               // slots per feature chunk (MLP ranking)
 constexpr float kLbGamma = 1e-3f;
 
 
@@ -59,6 +60,7 @@ struct ScreenArgs {
   const int* hcount;       // per instance: length of hlist, or -1 for every obstacle
   const uint32_t* hrest;   // per instance: lower-bound key of every obstacle not in hlist
   const float* theta;      // MLP parameters, or nullptr: rank by edge distance
+  const uint4* frag;       // the network's lane fragments (mlp_frag_kernel), used with theta
   int pool;                // P
   int topk;                // K
   uint64_t* keys;
@@ -196,6 +198,7 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
   __shared__ int pool_o[kPoolCap];        // pool obstacles (local index)
   __shared__ uint32_t pool_lb[kPoolCap];  // their orderable LB
   __shared__ float score[kPoolCap * MI];  // per pool edge slot (+inf for unused slots)
+  __shared__ bf16x4 feat[kFeatSlots];     // network features of a chunk of slots
   __shared__ uint8_t cand[kPoolCap];
   __shared__ int cand_o[kPoolCap];
   __shared__ uint64_t wkey[kScreenThreads / 64];
@@ -307,14 +310,16 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
     __syncthreads();
     if (A.theta) {
       MlpFrag fr;
-      mlp_load(A.theta, fr);
+      mlp_frag_fetch(A.frag, fr);
       const int n = lane & 15, g = lane >> 4;
-      for (int base = w * 16; base < slots; base += 16 * (kScreenThreads / 64)) {
-        const int e = base + n;
-        const int q = e / MI, j = e - q * MI;
-        float x0 = 0.f, x1 = 0.f, x2 = 0.f, x3 = 0.f;
-        bool valid = false;
-        if (e < slots) {
+      // chunks of kFeatSlots slots: the work-group stages every slot's BF16
+      // features in LDS in one pass (all loads in flight; a valid slot's
+      // score is set to 0 until the network overwrites it), then each wave
+      // runs the network on 16 slots at a time from LDS
+      for (int c0 = 0; c0 < slots; c0 += kFeatSlots) {
+        const int cn = min(kFeatSlots, slots - c0);
+        for (int e = tid; e < cn; e += kScreenThreads) {
+          const int q = (c0 + e) / MI, j = (c0 + e) - q * MI;
           const int o = pool_o[q];
           const int a = off[o], mi = off[o + 1] - a;
           if (j < mi) {
@@ -323,13 +328,20 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
             local_point(A.ax[ge], A.ay[ge], cs, sn, px, py, lax, lay);
             local_point(A.bx[ge], A.by[ge], cs, sn, px, py, lbx, lby);
             const float sc = 1.0f / kFeatureScale;
-            x0 = lax * sc; x1 = lay * sc; x2 = lbx * sc; x3 = lby * sc;
-            valid = true;
+            feat[e] = mlp_features(lax * sc, lay * sc, lbx * sc, lby * sc);
+            score[c0 + e] = 0.f;
           }
         }
-        MlpAct act;
-        mlp_forward16(fr, x0, x1, x2, x3, act);
-        if (g == 0 && valid) score[e] = act.y;
+        __syncthreads();
+        for (int base = w * 16; base < cn; base += 16 * (kScreenThreads / 64)) {
+          const int e = base + n;
+          const bool live = e < cn && score[c0 + e] != __builtin_huge_valf();
+          const bf16x4 zero = {0, 0, 0, 0};
+          MlpAct act;
+          mlp_forward16_bf(fr, g == 0 && live ? feat[e] : zero, act);
+          if (g == 0 && live) score[c0 + e] = act.y;
+        }
+        __syncthreads();
       }
     } else {
       for (int e = tid; e < slots; e += kScreenThreads) {

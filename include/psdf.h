@@ -38,10 +38,13 @@
  *    boundary order with B_j == A_{j+1} (bitwise); an obstacle of one edge is
  *    a free segment.  mbar is a host-side bound on the edges per obstacle (the
  *    paper's padded width m-bar, Sec. IV-A), 1 <= mbar <= PSDF_MAX_OBST_EDGES.
- *    Offsets are not scanned on the host: an obstacle whose edge count is
- *    negative or above mbar, or whose range leaves [0, E], makes every stage's
- *    result NaN (edge = obst = -1).  Obstacles with zero edges are ignored
- *    (the paper's S = 0 padding).
+ *    Offsets are not scanned on the host.  An obstacle whose edge count is
+ *    negative or above the edge class of mbar (mbar rounded up to 4, 8 or
+ *    16), whose range leaves [0, E], or with a non-finite coordinate makes
+ *    every stage's result NaN (edge = obst = -1); a count above mbar itself
+ *    is outside the contract.  psdf_validate_edges scans a device edge set
+ *    for all of these.  Obstacles with zero edges are ignored (the paper's
+ *    S = 0 padding).
  *  - Outputs per stage s: d[s] = phi, obst[s] = winning obstacle (lowest index
  *    on ties), edge[s] = global index of the winner's edge with the smallest
  *    point-segment pool distance (lowest index on ties), grad[3s..3s+2] =
@@ -197,6 +200,15 @@ int psdf_bwd_geometry(const float* footprint, int32_t m, const float* poses, int
 int psdf_sd_matrix(const float* footprint, int32_t m, const float* poses, int32_t N,
                    const psdf_edges* edges, const psdf_params* params, float* sd,
                    hipStream_t stream);
+
+/* psdf_validate_edges - debug scan of a device edge set (the staging step of
+ * Sec. IV-A / Alg. 1 EncodeEdges, checked): counts the obstacles outside the
+ * edge-set contract above (edge count negative or above mbar, range outside
+ * [0, E], a non-finite coordinate) and finds the lowest such index.
+ * result: device int32[2], overwritten with (count, lowest index), the index
+ * being M when every obstacle is valid.  Enqueued on `stream` (two kernels);
+ * reads each obstacle's offsets, and its edges only when its range is valid. */
+int psdf_validate_edges(const psdf_edges* edges, int32_t* result, hipStream_t stream);
 
 /* psdf_encode_padded - EncodeEdges of Alg. 1 for the paper's padded tensors
  * (Sec. IV-A): A, B device float32[Mbar][mbar][2] and the validity mask S

@@ -95,6 +95,7 @@ _SIGS = {
     "psdf_encode_ws_bytes": (ctypes.c_size_t, [_I32]),
     "psdf_timer_enable": (ctypes.c_int, [_I32]),
     "psdf_timer_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "psdf_validate_edges": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "psdf_encode_padded": (ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP,
                                           _VP, ctypes.c_size_t, _VP]),
 }

@@ -218,6 +218,18 @@ def psdf_sd_matrix(footprint, poses, edges: EdgeSet, params: Params | None = Non
     return sd
 
 
+def validate_edges(edges: EdgeSet):
+    """(count, lowest index) of the obstacles outside the edge-set contract:
+    edge count negative or above mbar, range outside [0, E], or a non-finite
+    coordinate (psdf_validate_edges).  The index is M when all are valid."""
+    out = torch.empty(2, dtype=torch.int32, device=edges.obst_off.device)
+    ec = edges.c()
+    _lib.check(_lib.lib().psdf_validate_edges(ctypes.byref(ec), out.data_ptr(),
+                                              _lib.stream_handle()))
+    count, first = out.tolist()
+    return count, first
+
+
 def psdf_encode_padded(A, B, S):
     """EncodeEdges (Alg. 1): padded (A, B, S) device tensors -> device EdgeSet."""
     Mbar, mbar = int(S.shape[0]), int(S.shape[1])

@@ -258,6 +258,30 @@ hipError_t launch_epilogue(const FpConst& F, const float* poses, int N, const ps
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ validation
+
+__global__ void validate_init_kernel(int* __restrict__ result, int M) {
+  result[0] = 0;
+  result[1] = M;
+}
+
+// One thread per obstacle: its offsets, then (valid range only) its edges.
+__global__ void validate_kernel(const float* __restrict__ ax, const float* __restrict__ ay,
+                                const float* __restrict__ bx, const float* __restrict__ by,
+                                const int* __restrict__ off, int E, int M, int mbar,
+                                int* __restrict__ result) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const int a = off[i], b = off[i + 1];
+  bool bad = b < a || b - a > mbar || a < 0 || b > E;
+  for (int j = a; !bad && j < b; ++j)
+    bad = !(isfinite(ax[j]) && isfinite(ay[j]) && isfinite(bx[j]) && isfinite(by[j]));
+  if (bad) {
+    atomicAdd(&result[0], 1);
+    atomicMin(&result[1], i);
+  }
+}
+
 // ------------------------------------------------------------------ EncodeEdges
 
 __global__ void encode_count_kernel(const uint8_t* __restrict__ S, int Mbar, int mbar,
@@ -474,6 +498,22 @@ int psdf_sd_matrix(const float* footprint, int32_t m, const float* poses, int32_
 }
 
 size_t psdf_encode_ws_bytes(int32_t Mbar) { return Mbar > 0 ? (size_t)Mbar * sizeof(int) : 0; }
+
+int psdf_validate_edges(const psdf_edges* edges, int32_t* result, hipStream_t stream) {
+  clear_error();
+  psdf_edges e;
+  const int rc = check_edges(edges, &e);
+  if (rc) return rc;
+  if (!result) return set_error(PSDF_EINVAL, "result is NULL");
+  validate_init_kernel<<<1, 1, 0, stream>>>(result, e.M);
+  hipError_t err = hipGetLastError();
+  if (err == hipSuccess && e.M > 0) {
+    validate_kernel<<<(e.M + 255) / 256, 256, 0, stream>>>(e.ax, e.ay, e.bx, e.by, e.obst_off, e.E,
+                                                           e.M, e.mbar, result);
+    err = hipGetLastError();
+  }
+  return hip_status(err);
+}
 
 int psdf_encode_padded(const float* A, const float* B, const uint8_t* S, int32_t Mbar,
                        int32_t mbar, float* ax, float* ay, float* bx, float* by,

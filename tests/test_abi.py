@@ -152,3 +152,12 @@ def test_misaligned_workspace_is_rejected():
                               1 << 30, None)
     assert rc == _lib.PSDF_EINVAL
     assert "aligned" in _lib.lib().psdf_last_error().decode()
+
+
+def test_validate_edges_argument_checks():
+    lib = _lib.lib()
+    assert lib.psdf_validate_edges(None, ctypes.c_void_p(16), None) == _lib.PSDF_EINVAL
+    e = _lib.PsdfEdges(1, 1, 1, 1, 1, 4, 1, 4)
+    assert lib.psdf_validate_edges(ctypes.byref(e), None, None) == _lib.PSDF_EINVAL
+    bad_mbar = _lib.PsdfEdges(1, 1, 1, 1, 1, 4, 1, 17)
+    assert lib.psdf_validate_edges(ctypes.byref(bad_mbar), ctypes.c_void_p(16), None) == _lib.PSDF_ETOOBIG

@@ -227,6 +227,50 @@ def test_encode_padded(api):
         assert torch.equal(x, y)
 
 
+def _validate_reference(ed, off, mbar):
+    """The edge-set contract checked on the host, obstacle by obstacle."""
+    E, bad = len(ed), []
+    for i in range(len(off) - 1):
+        a, b = int(off[i]), int(off[i + 1])
+        ok = a <= b and b - a <= mbar and a >= 0 and b <= E
+        ok = ok and bool(np.isfinite(ed[a:b]).all())
+        if not ok:
+            bad.append(i)
+    return len(bad), (bad[0] if bad else len(off) - 1)
+
+
+def test_validate_edges(api):
+    """psdf_validate_edges against the contract checked on the host: a valid
+    set, then planted violations (non-finite coordinate, decreasing offsets,
+    a count above mbar, a range past E), each found with the lowest index."""
+    rng = np.random.default_rng(11)
+    inst = inputs.random_small(rng, n_obst=300, n_poses=1, segments=40)
+    ed = inst.edges.astype(np.float32).copy()
+    off = inst.obst_off.astype(np.int32).copy()
+    M, E = len(off) - 1, len(ed)
+
+    def run(ed, off, mbar=4):
+        es = api.EdgeSet(ed, off, mbar)
+        got = api.validate_edges(es)
+        assert got == _validate_reference(ed, off, mbar), (got, _validate_reference(ed, off, mbar))
+        return got
+
+    assert run(ed, off) == (0, M)
+    e1 = ed.copy()
+    e1[off[250] + 1, 2] = np.nan          # obstacle 250: a NaN endpoint
+    e1[off[97], 0] = np.inf               # obstacle 97: an infinite one
+    assert run(e1, off) == (2, 97)
+    o2 = off.copy()
+    o2[120] = o2[121] + 1                 # obstacle 119 ends after obstacle 120 starts
+    assert run(ed, o2)[0] >= 1
+    assert run(ed, off, mbar=3)[0] == 300  # every rectangle exceeds mbar = 3
+    o3 = off.copy()
+    o3[-1] = E + 5                        # the last obstacle runs past E
+    assert run(ed, o3) == (1, M - 1)
+    empty = api.EdgeSet(np.zeros((0, 4), np.float32), np.zeros(1, np.int32), 1)
+    assert api.validate_edges(empty) == (0, 0)
+
+
 @pytest.mark.parametrize("blk,sb", [(64, 1), (64, 7), (256, 1), (256, 4), (256, 64)])
 def test_launch_shape_independent(api, blk, sb):
     """The per-stage minimum and its tie rule are exact: every launch shape

@@ -175,6 +175,39 @@ def extras(torch, api, flops, inputs):
         del es, poses, ws, o
     out["single_pose_sweep"] = sweep
 
+    # the query shapes of the paper's Table I: latency of one value call
+    # (psdf_eval) and one value + gradient call (psdf_grad) for B poses
+    # against M obstacles, eager from Python as a per-query caller issues
+    # them, and the value + gradient call replayed from a HIP graph
+    table = []
+    for M in (1, 10, 100):
+        for B in (1, 10, 100):
+            inst = inputs.table_i(M, B)
+            es = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar, device="cuda")
+            poses = torch.tensor(inst.poses, device="cuda")
+            ws = api.workspace(B, M, "cuda")
+            o = api.psdf_grad(inst.footprint, poses, es, ws=ws)
+            t_fwd = _timeit(torch, lambda: api.psdf_eval(inst.footprint, poses, es, ws=ws), 200, 20)
+            t_grad = _timeit(torch, lambda: api.psdf_grad(inst.footprint, poses, es, out=o, ws=ws),
+                             200, 20)
+            cap = torch.cuda.Stream()
+            cap.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(cap):
+                api.psdf_grad(inst.footprint, poses, es, out=o, ws=ws)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cap):
+                for _ in range(100):
+                    api.psdf_grad(inst.footprint, poses, es, out=o, ws=ws)
+            t_graph = _timeit(torch, g.replay, 5, 1) / 100
+            del g
+            table.append(dict(M=M, B=B, fwd_us=t_fwd * 1e3, grad_us=t_grad * 1e3,
+                              grad_graph_us=t_graph * 1e3))
+            del es, poses, ws, o
+    log("table I shapes: " + ", ".join(f"M={r['M']} B={r['B']}: {r['grad_us']:.1f} us"
+                                       for r in table))
+    out["table_i_latency"] = table
+
     # screener trained on held-out instances (different seeds from the test batch)
     log("c5: training set")
     X, T = screener.training_set(inputs.c5(10, cfg=6), near=1024, far=1024, seed=1)

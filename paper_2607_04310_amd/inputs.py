@@ -160,6 +160,16 @@ def c1(seed_instance: int = 0) -> Instance:
     return Instance(fp, poses, edges, csr_offsets([4] * 64), 4, dict(workload="c1"))
 
 
+def table_i(M: int, B: int, seed_instance: int = 0) -> Instance:
+    """The query shapes of the paper's Table I: B random poses against M random
+    obstacles (c1's footprint, rectangles and square)."""
+    rng = rng_for(7, 1000 * M + B + 100000 * seed_instance)
+    fp = rect_footprint()
+    poses = uniform_poses(rng, B)
+    edges = random_rects(rng, M, 0.2, 1.0, -5.0, 5.0)
+    return Instance(fp, poses, edges, csr_offsets([4] * M), 4, dict(workload=f"table_i M={M} B={B}"))
+
+
 def c2(seed_instance: int = 0) -> Instance:
     rng = rng_for(2, seed_instance)
     fp = hexagon_footprint(rng)

@@ -50,6 +50,14 @@ def test_c1(api, seed, eta):
     assert st["stages"] >= 18
 
 
+@pytest.mark.parametrize("M,B", [(1, 1), (1, 100), (10, 10), (100, 1), (100, 100)])
+def test_table_i_shapes(api, M, B):
+    """The query shapes of the paper's Table I (B poses, M obstacles)."""
+    inst = inputs.table_i(M, B)
+    st = check(inst, run(api, inst), 1000.0)
+    assert st["stages"] == B
+
+
 def test_c1_eval_matches_grad(api):
     inst = inputs.c1(0)
     a = run(api, inst, grad=False)

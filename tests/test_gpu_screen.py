@@ -92,6 +92,25 @@ def test_training_reduces_loss(api):
     assert _close(y.cpu().numpy(), ref)
 
 
+def test_training_checkpoint_resume(api, tmp_path):
+    """Training saved after 4 epochs and resumed from the checkpoint continues
+    the Adam step count and keeps reducing the loss."""
+    from paper_2607_04310_amd import screener
+    insts = inputs.c5(1, cfg=6)
+    X, T = screener.training_set(insts, near=256, far=256, seed=2)
+    st = {}
+    theta, hist = screener.train(X, T, epochs=4, batch=1024, lr=3e-3, seed=0, state=st)
+    path = tmp_path / "screener.safetensors"
+    screener.save_checkpoint(path, theta, st["m"], st["v"], step=st["step"], seed=0, hist=hist)
+    ck = screener.load_checkpoint(path, device="cuda")
+    assert torch.equal(ck["theta"], theta)
+    st2 = {}
+    theta2, hist2 = screener.train(X, T, epochs=4, batch=1024, lr=1e-3, seed=1, resume=ck, state=st2)
+    assert st2["step"] == st["step"] + 4 * (X.shape[0] // 1024)
+    assert hist2[-1] < hist[0] and np.isfinite(hist2).all()
+    assert not torch.equal(theta2, theta)
+
+
 def test_labels_vs_oracle(api):
     inst = inputs.c5_instance(0)
     b = api.Batch([inst], graph=False)

@@ -119,8 +119,10 @@ def _timeit(torch, fn, reps, warm):
 
 def extras(torch, api, flops, inputs):
     """Secondary lines: the uneven batch (c4: persistent graph vs the
-    per-instance loop) and certified screening (c5: plain batch vs screened
-    with the trained MLP and with distance ranking)."""
+    per-instance loop), c2 at throughput size (256 draws in one batch), one
+    pose against growing edge sets, the latency of the paper's Table I query
+    shapes, and certified screening (c5: plain batch vs screened with the
+    trained MLP and with distance ranking)."""
     from paper_2607_04310_amd import screener
     out = {}
     log("c4: building 512 instances")

@@ -77,8 +77,9 @@ struct Obst {
   float bx[MI], by[MI];   // B_j, world (extra V_obs points of an open obstacle)
   float ux[MI], uy[MI];   // (B_j - A_j) / (|B_j - A_j| + eps); n'_j = (-uy, ux)
   float len[MI];          // |B_j - A_j|
-  float olo[MI], ohi[MI]; // interval of (W - A_j) . n'_j over W in V_obs
+  float olo[MI], ohi[MI]; // interval of (W - A_j) . n'_j over W in V_obs (when own)
   int mi;
+  bool own;               // olo / ohi computed (on first need, own_intervals)
   bool closed;            // B_j == A_{j+1} for all j (bitwise): V_obs = {A_j}
   bool bad;               // edge count or range invalid, or a non-finite
                           // coordinate: the result is NaN
@@ -163,7 +164,13 @@ __device__ __forceinline__ void load_obstacle(Obst<MI>& o, const float* __restri
                          (__float_as_uint(o.by[j]) == __float_as_uint(ny));
   }
   o.closed = closed;
-  // own-axis intervals (Sec. IV-C), relative to A_j: pose independent
+  o.own = false;
+}
+
+// Own-axis intervals (Sec. IV-C), relative to A_j: pose independent, needed
+// only at stages that no robot axis separates, so taken on first need.
+template <int MI>
+__device__ __forceinline__ void own_intervals(Obst<MI>& o) {
 #pragma unroll
   for (int j = 0; j < MI; ++j) {
     float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
@@ -173,7 +180,7 @@ __device__ __forceinline__ void load_obstacle(Obst<MI>& o, const float* __restri
       lo = fminf(lo, q);
       hi = fmaxf(hi, q);
     }
-    if (!closed) {
+    if (!o.closed) {
 #pragma unroll
       for (int k = 0; k < MI; ++k) {
         const float q = fmaf(o.by[k] - o.ay[j], o.ux[j], -((o.bx[k] - o.ax[j]) * o.uy[j]));
@@ -184,6 +191,7 @@ __device__ __forceinline__ void load_obstacle(Obst<MI>& o, const float* __restri
     o.olo[j] = lo;
     o.ohi[j] = hi;
   }
+  o.own = true;
 }
 
 // The footprint rotated by a stage heading (c, s) = (cos, sin): slot l of rf
@@ -221,7 +229,7 @@ __device__ __forceinline__ float frame_d2(float a, float b, float L) {
 // the footprint rotated by the stage heading (rotated_slot, MF slots) and
 // (px, py) is the stage position.
 template <int MF, int MI>
-__device__ __forceinline__ float obstacle_sd(const FpConst& F, const Obst<MI>& o,
+__device__ __forceinline__ float obstacle_sd(const FpConst& F, Obst<MI>& o,
                                              const float4* rf, float px, float py) {
   // the obstacle translated to the pose origin, and its edge frames' offsets
   // ca = (A_j - p) . u_j, cb = (A_j - p) . n'_j
@@ -276,7 +284,9 @@ __device__ __forceinline__ float obstacle_sd(const FpConst& F, const Obst<MI>& o
     for (int k = 0; k < MI; ++k) visit(o.bx[k] - px, o.by[k] - py);
   }
 
-  // Overlaps and the separating-axis test.
+  // Overlaps and the separating-axis test: the robot axes, then, where none
+  // of them separates, the obstacle's axes (sep is their disjunction either
+  // way, and the overlaps are only used when no axis separates).
   float dl[MF + MI];
   bool sep = false;
 #pragma unroll
@@ -284,10 +294,13 @@ __device__ __forceinline__ float obstacle_sd(const FpConst& F, const Obst<MI>& o
     dl[l] = fminf(ra_hi[l] - F.oa[l], F.ob[l] - ra_lo[l]);
     sep = sep || (dl[l] < -F.eps_sat);
   }
+  if (!sep) {
+    if (!o.own) own_intervals<MI>(o);
 #pragma unroll
-  for (int j = 0; j < MI; ++j) {
-    dl[MF + j] = fminf(o.ohi[j] - rlo[j], rhi[j] - o.olo[j]);
-    sep = sep || (dl[MF + j] < -F.eps_sat);
+    for (int j = 0; j < MI; ++j) {
+      dl[MF + j] = fminf(o.ohi[j] - rlo[j], rhi[j] - o.olo[j]);
+      sep = sep || (dl[MF + j] < -F.eps_sat);
+    }
   }
 
   float sd = sqrtf(fminf(dv2, de2));

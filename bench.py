@@ -239,8 +239,10 @@ def extras(torch, api, flops, inputs):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the PSDF hot path has no multi-GPU "
-              "path in this build (see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the PSDF hot path has no multi-GPU path "
+              "(independent instances would shard across GPUs with no exchange; one huge "
+              "instance would shard its obstacles and all-reduce the per-stage minimum keys)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

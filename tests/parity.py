@@ -1,6 +1,6 @@
 """Tie-aware comparison of the HIP path against the FP64 oracle.
 
-Bars (from the build's target): |d - phi| <= 1e-5 m; gradient
+Bars (the stated tolerance of the FP32 path): |d - phi| <= 1e-5 m; gradient
 ||dg||_inf <= 1e-4 * max(1, ||g_ref||_inf); winning obstacle and edge
 bit-exact when the oracle's minimum is unique within TAU, otherwise inside
 the oracle's tie set (every candidate within TAU of the minimum).  Where the

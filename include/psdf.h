@@ -365,10 +365,9 @@ int psdf_screen_labels(const psdf_batch_plan* plan, const float* poses, const fl
 
 /* Launch shape of the per-stage minimum kernel: blk obstacles per work-group
  * (64 or 256) and sb stages per work-group (1..64).  A non-zero blk overrides
- * every later call in the process (for sweeps and the autotuner); blk = 0
- * restores the automatic choice (the autotuner's cached shape for the
- * problem size if it has one, else a heuristic).  Results do not depend on
- * the shape (the minimum and its tie rule are exact). */
+ * every later call in the process (for sweeps); blk = 0 restores the
+ * automatic choice (a heuristic on N and M).  Results do not depend on the
+ * shape (the minimum and its tie rule are exact). */
 int psdf_set_launch_shape(int32_t blk, int32_t sb);
 
 /* Kernel timer, an instrumentation aid for benchmarks.  With capacity > 0,

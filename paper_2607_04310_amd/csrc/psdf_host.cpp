@@ -171,23 +171,16 @@ LaunchShape choose_shape(int N, int M) {
 }
 
 namespace {
-std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, LaunchShape> g_tuned;   // (mf, mi class, N, M)
+std::mutex g_shape_mu;
 LaunchShape g_override{0, 0};
-int slot_class(int m) { return m <= 8 ? m : 16; }
 }  // namespace
 
 LaunchShape tuned_shape(int m, int mbar, int N, int M) {
-  std::lock_guard<std::mutex> lk(g_tune_mu);
+  (void)m;
+  (void)mbar;
+  std::lock_guard<std::mutex> lk(g_shape_mu);
   if (g_override.blk) return g_override;
-  auto it = g_tuned.find(std::make_tuple(slot_class(m), obst_class(mbar), N, M));
-  if (it != g_tuned.end()) return it->second;
   return choose_shape(N, M);
-}
-
-void remember_shape(int m, int mbar, int N, int M, const LaunchShape& ls) {
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tuned[std::make_tuple(slot_class(m), obst_class(mbar), N, M)] = ls;
 }
 
 namespace {
@@ -232,14 +225,14 @@ using namespace psdf;
 extern "C" int psdf_set_launch_shape(int32_t blk, int32_t sb) {
   clear_error();
   if (blk == 0) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::lock_guard<std::mutex> lk(g_shape_mu);
     g_override = LaunchShape{0, 0};
     return PSDF_OK;
   }
   if ((blk != 64 && blk != 256) || sb < 1 || sb > kMaxStageBlock)
     return set_error(PSDF_EINVAL, "launch shape blk=%d sb=%d (blk 64 or 256, sb 1..%d)", blk, sb,
                      kMaxStageBlock);
-  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::lock_guard<std::mutex> lk(g_shape_mu);
   g_override = LaunchShape{blk, sb};
   return PSDF_OK;
 }

@@ -42,9 +42,8 @@ bool timer_kernel_events(hipEvent_t* start, hipEvent_t* stop);
 LaunchShape choose_shape(int N, int M);
 
 // Launch shape for a problem: an explicit override (psdf_set_launch_shape),
-// else the autotuner's cached choice, else choose_shape.
+// else choose_shape.
 LaunchShape tuned_shape(int m, int mbar, int N, int M);
-void remember_shape(int m, int mbar, int N, int M, const LaunchShape& ls);
 
 hipError_t launch_plain(const FpConst& F, const float* poses, int N, const psdf_edges& e,
                         uint64_t* partial, const LaunchShape& ls, hipStream_t st);

@@ -32,6 +32,8 @@ PEAK_FP32_TFLOPS = 157.3
 # for a copy kernel of known size), valid only while the kernel's sources
 # hash to the value recorded beside it.
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "main_kernel_c2_hbm_counters.md")
+VALU_SUMMARY = os.path.join(ROOT, "profiles", "main_kernel_c2_valu_counters.md")
+SIMDS, CLOCK_GHZ = 1024, 2.4
 # The per-stage-minimum kernel's own sources: its code and instantiation, the
 # launch-shape choice, the build flags.
 KERNEL_SOURCES = [os.path.join("paper_2607_04310_amd", "csrc", f) for f in (
@@ -46,6 +48,21 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def counted_valu_insts():
+    """VALU wave-instructions per launch from the VALU counter summary, or
+    None when it is missing or the kernel has changed since."""
+    import re
+    try:
+        text = open(VALU_SUMMARY).read()
+    except OSError:
+        return None
+    mh = re.search(r"source_sha256:\s*([0-9a-f]+)", text)
+    mv = re.search(r"valu_insts_per_launch:\s*([0-9.eE+]+)", text)
+    if not mh or not mv or mh.group(1) != kernel_source_hash():
+        return None
+    return float(mv.group(1))
 
 
 def counted_traffic():
@@ -334,6 +351,8 @@ def main():
     flop = flops.flops_instance(len(inst.footprint), N, inst.edges, inst.obst_off)
     achieved = flop / (kernel_ms * 1e-3) / 1e12
     traffic, traffic_note = counted_traffic()
+    valu = counted_valu_insts()
+    valu_busy = None if valu is None else valu * 4 / (SIMDS * kernel_ms * 1e-3 * CLOCK_GHZ * 1e9)
     value = N * E / (ms_step * 1e-3)
     res = dict(
         metric=METRIC, value=value, unit="stage×edge evals/s", n_gpus=1, steps=args.steps,
@@ -348,6 +367,7 @@ def main():
                       frac=achieved / PEAK_FP32_TFLOPS, traffic=traffic,
                       traffic_note=traffic_note,
                       algorithmic_bytes=flops.bytes_instance(N, E, M),
+                      valu_busy=valu_busy, valu_insts_per_launch=valu,
                       kernel="main_kernel (per-stage minimum)", kernel_us=kernel_ms * 1e3,
                       kernel_us_event_bracketed=kernel_ms_bracketed * 1e3,
                       flop_per_launch=flop, source_sha256=kernel_source_hash()),

@@ -18,33 +18,19 @@
 
 namespace psdf {
 
-// Per-call prologue of the screened path, grid (obstacle blocks, instances):
-// the bounding circle of every obstacle, (cx, cy, r, 0) with r inflated to
-// cover rounding (an empty obstacle gets cx = NaN and is never in a pool; an
-// invalid one, bad range or non-finite, r = +inf and is always in it); the
-// first block of each instance opens its horizon list (count 0, excluded
-// bound +inf) and block (0, 0) clears the screening counters of every group.
-__global__ void circle_kernel(const BatchInst* __restrict__ insts, const float* __restrict__ ax,
-                              const float* __restrict__ ay, const float* __restrict__ bx,
-                              const float* __restrict__ by, const int* __restrict__ off,
-                              float4* __restrict__ circ, int* __restrict__ hcount,
-                              uint32_t* __restrict__ hrest, unsigned* __restrict__ ctrl,
-                              int n_ctrl) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    hcount[blockIdx.y] = 0;
-    hrest[blockIdx.y] = 0xffffffffu;
-    if (blockIdx.y == 0)
-      for (int i = 0; i < n_ctrl; ++i) ctrl[i] = 0u;
-  }
-  const BatchInst in = insts[blockIdx.y];
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= in.M) return;
+// Bounding circle (cx, cy, r, 0) of obstacle o of an instance, from its
+// edges in one pass, r inflated to cover rounding.  An empty obstacle gets
+// cx = NaN (never screened); an invalid one (bad range or a non-finite
+// coordinate) r = +inf (always a candidate).
+__device__ float4 obstacle_circle(const BatchInst& in, const float* __restrict__ ax,
+                                  const float* __restrict__ ay, const float* __restrict__ bx,
+                                  const float* __restrict__ by, const int* __restrict__ off,
+                                  int o) {
   const int a = off[in.obst_off + o], b = off[in.obst_off + o + 1], mi = b - a;
   float4 c = make_float4(__builtin_nanf(""), 0.f, 0.f, 0.f);
   if (mi != 0) {
     c = make_float4(0.f, 0.f, __builtin_huge_valf(), 0.f);
     if (mi > 0 && mi <= kMaxObst && a >= 0 && b <= in.E) {
-      // the obstacle's endpoints in registers, one pass over memory
       float px[2 * kMaxObst], py[2 * kMaxObst];
       float sx = 0.f, sy = 0.f;
       bool finite = true;
@@ -73,7 +59,7 @@ __global__ void circle_kernel(const BatchInst* __restrict__ insts, const float* 
       }
     }
   }
-  circ[in.circ_off + o] = c;
+  return c;
 }
 
 // Horizon list of each instance: every stage position of the instance lies
@@ -82,21 +68,25 @@ __global__ void circle_kernel(const BatchInst* __restrict__ insts, const float* 
 //   |p_s - c_i| - r_i - rmax - gamma >= |c_p - c_i| - R - r_i - rmax - gamma =: hb_i,
 // a lower bound of the stage's circle bound and hence of sd_i.  Grid
 // (kHorizonSplit, instances): work-group c takes the c-th block of the
-// instance's obstacles and appends its (about) kHorizonPool / kHorizonSplit
-// lowest-hb obstacles to the list; the list thus holds every obstacle among
-// the kHorizonPool / kHorizonSplit lowest of the whole instance.  The
-// smallest hb left out (atomic minimum over the blocks) bounds every excluded
-// obstacle at every stage.  A non-finite stage position disables the list
-// (-1); a list longer than kHorizonCap (tie blocks) is not used by the stage
-// pass either: the instance's stages then take the full evaluation.
+// instance's obstacles, computes their bounding circles (obstacle_circle),
+// and appends its (about) kHorizonPool / kHorizonSplit lowest-hb obstacles to
+// the list as (circle, index); the list thus holds every obstacle among the
+// kHorizonPool / kHorizonSplit lowest of the whole instance.  The smallest hb
+// left out (atomic minimum over the blocks) bounds every excluded obstacle at
+// every stage.  A non-finite stage position disables the list (-1); a list
+// longer than kHorizonCap (tie blocks) is not used by the stage pass either:
+// the instance's stages then take the full evaluation.  On entry the
+// instance's count is 0 and its bound +inf (plan creation, then the finish
+// kernel of every screened call).
 constexpr int kHorizonPool = 1024;
-constexpr int kHorizonSplit = 4;
-constexpr int kHorizonKeys = kScreenMaxM / kHorizonSplit / kScreenThreads;   // 16
+constexpr int kHorizonSplit = 16;
+constexpr int kHorizonKeys = kScreenMaxM / kHorizonSplit / kScreenThreads;   // 4
 
 __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
-    const float* __restrict__ poses, const float4* __restrict__ circ, float4* __restrict__ hlist,
-    int* __restrict__ hcount, uint32_t* __restrict__ hrest) {
+    const float* __restrict__ poses, const float* __restrict__ ax, const float* __restrict__ ay,
+    const float* __restrict__ bx, const float* __restrict__ by, const int* __restrict__ off,
+    float4* __restrict__ hlist, int* __restrict__ hcount, uint32_t* __restrict__ hrest) {
   __shared__ int scan[kScreenThreads];
   __shared__ uint32_t red[kScreenThreads / 64];
   __shared__ int s_base;
@@ -136,19 +126,22 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   }
   nr = block_min_u32(nr, red);
   const float R = -from_orderable(nr) * (1.0f + 1e-6f) + 1e-6f;
-  const float off = R + F.rmax + kLbGamma;
+  const float hoff = R + F.rmax + kLbGamma;
   uint32_t k[kHorizonKeys];
+  float4 cq[kHorizonKeys];
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   int used = 0;
 #pragma unroll
   for (int q = 0; q < kHorizonKeys; ++q) {
     const int o = o0 + tid + kScreenThreads * q;
     uint32_t key = 0xffffffffu;
+    cq[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (o < o1) {
-      const float4 c = circ[in.circ_off + o];
+      const float4 c = obstacle_circle(in, ax, ay, bx, by, off, o);
+      cq[q] = c;
       if (c.x == c.x) {
         const float dx = cx - c.x, dy = cy - c.y;
-        key = orderable(sqrtf(fmaf(dx, dx, dy * dy)) - c.z - off);
+        key = orderable(sqrtf(fmaf(dx, dx, dy * dy)) - c.z - hoff);
       }
     }
     k[q] = key;
@@ -184,7 +177,7 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   for (int q = 0; q < kHorizonKeys; ++q)
     if (k[q] != 0xffffffffu && k[q] <= T) {
       const int o = o0 + tid + kScreenThreads * q;
-      float4 c = circ[in.circ_off + o];
+      float4 c = cq[q];
       c.w = __int_as_float(o);
       hlist[in.circ_off + at++] = c;
     }
@@ -228,7 +221,6 @@ struct psdf_batch_plan {
   int* d_stage_list = nullptr;
   int* d_failed = nullptr;
   unsigned* d_sctrl = nullptr;
-  float4* d_circ = nullptr;   // bounding circles, sum M
   float4* d_hlist = nullptr;  // horizon lists (circle, index), sum M
   uint4* d_frag = nullptr;    // the screener's lane fragments, kFragWords x 64
   int* d_hcount = nullptr;    // per instance
@@ -433,7 +425,9 @@ __global__ __launch_bounds__(64) void mlp_frag_kernel(const float* __restrict__ 
 // path: the range from the offsets); then the winner adjoint and the
 // outputs.  A stage without a partial column (no obstacle) gets the empty
 // key and the empty-set result.  Block 0 also clears ctrl[0..n_ctrl), the
-// item counters of the batch launches before it on the stream.
+// item (or screening) counters of the launches before it on the stream, and
+// opens the n_inst horizon lists for the next screened call (count 0, bound
+// +inf).
 __global__ __launch_bounds__(256) void batch_finish_kernel(
     const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
     const int* __restrict__ stage_inst, int S, const float* __restrict__ poses,
@@ -441,10 +435,17 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(
     const float* __restrict__ by, const int* __restrict__ off,
     const uint64_t* __restrict__ partial, const uint64_t* __restrict__ aux,
     uint64_t* __restrict__ keys, float* __restrict__ d, int* __restrict__ edge,
-    int* __restrict__ obst, float* __restrict__ grad, unsigned* __restrict__ ctrl, int n_ctrl) {
+    int* __restrict__ obst, float* __restrict__ grad, unsigned* __restrict__ ctrl, int n_ctrl,
+    int* __restrict__ hcount, uint32_t* __restrict__ hrest, int n_inst) {
   __shared__ FpLds fl[4];
   __shared__ WinnerLds wl[4];
-  if (blockIdx.x == 0 && (int)threadIdx.x < n_ctrl) ctrl[threadIdx.x] = 0u;
+  if (blockIdx.x == 0) {
+    if ((int)threadIdx.x < n_ctrl) ctrl[threadIdx.x] = 0u;
+    for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
+      hcount[i] = 0;
+      hrest[i] = 0xffffffffu;
+    }
+  }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = blockIdx.x * 4 + w;
   if (g >= S) return;
@@ -524,7 +525,7 @@ int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay
     }
     batch_finish_kernel<<<(p->total_stages + 3) / 4, 256, 0, st>>>(
         p->d_fp, p->d_inst, p->d_stage_inst, p->total_stages, poses, ax, ay, bx, by, off,
-        a.partial, a.aux, keys, d, edge, obst, grad, p->d_ctrl, kGroups);
+        a.partial, a.aux, keys, d, edge, obst, grad, p->d_ctrl, kGroups, nullptr, nullptr, 0);
     return hipGetLastError();
   };
   if (!use_graph) {
@@ -611,23 +612,15 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
   ScreenArgs a;
   a.fps = p->d_fp; a.insts = p->d_inst; a.stage_inst = p->d_stage_inst;
   a.poses = poses; a.ax = ax; a.ay = ay; a.bx = bx; a.by = by; a.off = off;
-  a.circ = p->d_circ;
   a.hlist = p->d_hlist; a.hcount = p->d_hcount; a.hrest = p->d_hrest;
   a.theta = theta; a.frag = p->d_frag; a.pool = pool; a.topk = topk; a.keys = keys;
   a.stage_cand = stage_cand; a.stage_cert = stage_cert; a.cand_keys = cand_keys;
   timer_begin(stream);
   hipError_t err = hipSuccess;
   if (p->n_inst > 0) {
-    dim3 grid((std::max(1, p->max_M) + 255) / 256, p->n_inst);
-    circle_kernel<<<grid, 256, 0, stream>>>(p->d_inst, ax, ay, bx, by, off, p->d_circ,
-                                            p->d_hcount, p->d_hrest, p->d_sctrl,
-                                            2 * kGroups);
+    horizon_kernel<<<dim3(kHorizonSplit, p->n_inst), kScreenThreads, 0, stream>>>(
+        p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest);
     err = hipGetLastError();
-    if (err == hipSuccess) {
-      horizon_kernel<<<dim3(kHorizonSplit, p->n_inst), kScreenThreads, 0, stream>>>(
-          p->d_fp, p->d_inst, poses, p->d_circ, p->d_hlist, p->d_hcount, p->d_hrest);
-      err = hipGetLastError();
-    }
   }
   if (err == hipSuccess && theta) {
     mlp_frag_kernel<<<1, 64, 0, stream>>>(theta, p->d_frag);
@@ -650,7 +643,8 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
   if (err == hipSuccess) {
     batch_finish_kernel<<<(p->total_stages + 3) / 4, 256, 0, stream>>>(
         p->d_fp, p->d_inst, p->d_stage_inst, p->total_stages, poses, ax, ay, bx, by, off, nullptr,
-        nullptr, keys, d, edge, obst, grad, nullptr, 0);
+        nullptr, keys, d, edge, obst, grad, p->d_sctrl, 2 * kGroups, p->d_hcount, p->d_hrest,
+        p->n_inst);
     err = hipGetLastError();
   }
   return hip_status(err);
@@ -686,7 +680,6 @@ void psdf_batch_plan_destroy(psdf_batch_plan* p) {
   (void)hipFree(p->d_stage_list);
   (void)hipFree(p->d_failed);
   (void)hipFree(p->d_sctrl);
-  (void)hipFree(p->d_circ);
   (void)hipFree(p->d_hlist);
   (void)hipFree(p->d_frag);
   (void)hipFree(p->d_hcount);
@@ -769,13 +762,18 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
     }
     size_t sumM = 0;
     for (int k = 0; k < n_inst; ++k) sumM += desc[k].M;
-    err = hipMalloc(&p->d_circ, std::max<size_t>(1, sumM) * sizeof(float4));
-    if (err == hipSuccess) err = hipMalloc(&p->d_hlist, std::max<size_t>(1, sumM) * sizeof(float4));
+    err = hipMalloc(&p->d_hlist, std::max<size_t>(1, sumM) * sizeof(float4));
     if (err == hipSuccess) err = hipMalloc(&p->d_frag, (size_t)kFragWords * 64 * sizeof(uint4));
     if (err == hipSuccess)
       err = hipMalloc(&p->d_hcount, std::max<size_t>(1, (size_t)n_inst) * sizeof(int));
     if (err == hipSuccess)
       err = hipMalloc(&p->d_hrest, std::max<size_t>(1, (size_t)n_inst) * sizeof(uint32_t));
+    // horizon lists open (count 0, excluded bound +inf); every screened call
+    // leaves them so
+    if (err == hipSuccess)
+      err = hipMemset(p->d_hcount, 0, std::max<size_t>(1, (size_t)n_inst) * sizeof(int));
+    if (err == hipSuccess)
+      err = hipMemset(p->d_hrest, 0xff, std::max<size_t>(1, (size_t)n_inst) * sizeof(uint32_t));
     if (err == hipSuccess) err = hipMalloc(&p->d_stage_inst, S * sizeof(int));
     if (err == hipSuccess) err = hipMalloc(&p->d_stage_list, S * sizeof(int));
     if (err == hipSuccess) err = hipMalloc(&p->d_failed, S * sizeof(int));

@@ -13,7 +13,8 @@
 // Lower bounds (world frame, pose origin p, footprint radius rmax about the
 // origin; every footprint point is within rmax of p):
 //  * every obstacle: its bounding circle (c_i, r_i), computed once per call
-//    by circle_kernel, gives dist(P0(x), P^i) >= |p - c_i| - r_i - rmax;
+//    (obstacle_circle, in the horizon pass), gives
+//    dist(P0(x), P^i) >= |p - c_i| - r_i - rmax;
 //  * an instance's stages share a horizon bound (horizon_kernel) for the
 //    obstacles left out of the instance's list;
 //  * excluded pool members, only when the circle bounds do not certify: for
@@ -54,7 +55,6 @@ struct ScreenArgs {
   const float* bx;
   const float* by;
   const int* off;
-  const float4* circ;      // bounding circles (circle_kernel)
   const float4* hlist;     // per instance (at circ_off): the circles its stages screen, the
                            // obstacle's local index in .w (int bits)
   const int* hcount;       // per instance: length of hlist, or -1 for every obstacle
@@ -65,7 +65,7 @@ struct ScreenArgs {
   int topk;                // K
   uint64_t* keys;
   int* failed;             // this launch's failed-stage list
-  unsigned* ctrl;          // [0] failed count, [1] fallback item; cleared by the call's prologue
+  unsigned* ctrl;          // [0] failed count, [1] fallback item; zero on entry
   int* stage_cand;         // optional: candidates evaluated per stage
   int* stage_cert;         // optional: 1 if certified
   uint64_t* cand_keys;     // optional: the candidates' minimum key (before any fallback)
@@ -475,7 +475,8 @@ __global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
 // Full evaluation of the failed stages: items (failed stage, tile of 256
 // obstacles) pulled from a counter; each work-group folds its tile's minimum
 // into keys[s] with a 64-bit atomicMin.  The failed count and the item
-// counter start at zero: the call's prologue clears them.
+// counter start at zero: plan creation clears them, and so does the finish
+// kernel at the end of every screened call.
 template <int MF, int MI>
 __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int max_tiles) {
   __shared__ int s_item;

@@ -191,8 +191,13 @@ __device__ __forceinline__ int block_scan(int v, int* scratch, int* total) {
   return base + x - v;
 }
 
+// One work-group per stage, latency-bound (barriers between the phases).  At
+// MI = 4 and MF <= 8 the register budget is capped at 128 VGPRs, so that four
+// work-groups share a CU instead of three (a few spills in the network's
+// scoring loop; c5 call 10 % faster).  Five per CU spill too much.
 template <int MF, int MI>
-__global__ __launch_bounds__(kScreenThreads) void screen_kernel(ScreenArgs A) {
+__global__ __launch_bounds__(kScreenThreads)
+__attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_kernel(ScreenArgs A) {
   __shared__ int scan[kScreenThreads];
   __shared__ uint32_t red[kScreenThreads / 64];
   __shared__ int pool_o[kPoolCap];        // pool obstacles (local index)

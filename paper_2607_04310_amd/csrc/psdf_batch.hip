@@ -18,28 +18,33 @@
 
 namespace psdf {
 
-// Bounding circle (cx, cy, r, 0) of obstacle o of an instance, from its
-// edges in one pass, r inflated to cover rounding.  An empty obstacle gets
-// cx = NaN (never screened); an invalid one (bad range or a non-finite
-// coordinate) r = +inf (always a candidate).
+// Bounding circle (cx, cy, r, 0) of an obstacle with edges [a, b) of an
+// instance, from its edges in one pass, r inflated to cover rounding.  An
+// empty obstacle gets cx = NaN (never screened); an invalid one (bad range,
+// more than MI edges or a non-finite coordinate) r = +inf (always a
+// candidate).  All MI edge loads are issued together (indices clamped into
+// the obstacle's range); edges past the obstacle's own count add nothing.
+template <int MI>
 __device__ float4 obstacle_circle(const BatchInst& in, const float* __restrict__ ax,
                                   const float* __restrict__ ay, const float* __restrict__ bx,
-                                  const float* __restrict__ by, const int* __restrict__ off,
-                                  int o) {
-  const int a = off[in.obst_off + o], b = off[in.obst_off + o + 1], mi = b - a;
+                                  const float* __restrict__ by, int a, int b) {
+  const int mi = b - a;
   float4 c = make_float4(__builtin_nanf(""), 0.f, 0.f, 0.f);
   if (mi != 0) {
     c = make_float4(0.f, 0.f, __builtin_huge_valf(), 0.f);
-    if (mi > 0 && mi <= kMaxObst && a >= 0 && b <= in.E) {
-      float px[2 * kMaxObst], py[2 * kMaxObst];
+    if (mi > 0 && mi <= MI && a >= 0 && b <= in.E) {
+      float px[2 * MI], py[2 * MI];
+#pragma unroll
+      for (int j = 0; j < MI; ++j) {
+        const int e = in.edge_off + a + min(j, mi - 1);
+        px[2 * j] = ax[e]; py[2 * j] = ay[e];
+        px[2 * j + 1] = bx[e]; py[2 * j + 1] = by[e];
+      }
       float sx = 0.f, sy = 0.f;
       bool finite = true;
 #pragma unroll
-      for (int j = 0; j < kMaxObst; ++j) {
+      for (int j = 0; j < MI; ++j) {
         if (j < mi) {
-          const int e = in.edge_off + a + j;
-          px[2 * j] = ax[e]; py[2 * j] = ay[e];
-          px[2 * j + 1] = bx[e]; py[2 * j + 1] = by[e];
           sx += px[2 * j] + px[2 * j + 1];
           sy += py[2 * j] + py[2 * j + 1];
           finite = finite && isfinite(px[2 * j]) && isfinite(py[2 * j]) &&
@@ -50,7 +55,7 @@ __device__ float4 obstacle_circle(const BatchInst& in, const float* __restrict__
         const float cx = sx / (2.f * mi), cy = sy / (2.f * mi);
         float r2 = 0.f;
 #pragma unroll
-        for (int j = 0; j < 2 * kMaxObst; ++j)
+        for (int j = 0; j < 2 * MI; ++j)
           if (j < 2 * mi) {
             const float dx = px[j] - cx, dy = py[j] - cy;
             r2 = fmaxf(r2, fmaf(dx, dx, dy * dy));
@@ -82,6 +87,7 @@ constexpr int kHorizonPool = 1024;
 constexpr int kHorizonSplit = 16;
 constexpr int kHorizonKeys = kScreenMaxM / kHorizonSplit / kScreenThreads;   // 4
 
+template <int MI>
 __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
     const float* __restrict__ poses, const float* __restrict__ ax, const float* __restrict__ ay,
@@ -131,13 +137,22 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   float4 cq[kHorizonKeys];
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   int used = 0;
+  // the edge ranges of the thread's obstacles, loaded together (an index
+  // past the block is clamped to its last obstacle, o1 - 1 < M)
+  int ea[kHorizonKeys], eb[kHorizonKeys];
+#pragma unroll
+  for (int q = 0; q < kHorizonKeys; ++q) {
+    const int o = min(o0 + tid + kScreenThreads * q, o1 - 1);
+    ea[q] = off[in.obst_off + o];
+    eb[q] = off[in.obst_off + o + 1];
+  }
 #pragma unroll
   for (int q = 0; q < kHorizonKeys; ++q) {
     const int o = o0 + tid + kScreenThreads * q;
     uint32_t key = 0xffffffffu;
     cq[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (o < o1) {
-      const float4 c = obstacle_circle(in, ax, ay, bx, by, off, o);
+      const float4 c = obstacle_circle<MI>(in, ax, ay, bx, by, ea[q], eb[q]);
       cq[q] = c;
       if (c.x == c.x) {
         const float dx = cx - c.x, dy = cy - c.y;
@@ -618,8 +633,16 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
   timer_begin(stream);
   hipError_t err = hipSuccess;
   if (p->n_inst > 0) {
-    horizon_kernel<<<dim3(kHorizonSplit, p->n_inst), kScreenThreads, 0, stream>>>(
-        p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest);
+    const dim3 grid(kHorizonSplit, p->n_inst);
+    if (p->mi_class == 4)
+      horizon_kernel<4><<<grid, kScreenThreads, 0, stream>>>(
+          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest);
+    else if (p->mi_class == 8)
+      horizon_kernel<8><<<grid, kScreenThreads, 0, stream>>>(
+          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest);
+    else
+      horizon_kernel<16><<<grid, kScreenThreads, 0, stream>>>(
+          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest);
     err = hipGetLastError();
   }
   if (err == hipSuccess && theta) {

@@ -65,7 +65,7 @@ struct ScreenArgs {
   int topk;                // K
   uint64_t* keys;
   int* failed;             // this launch's failed-stage list
-  unsigned* ctrl;          // [0] failed count, [1] fallback item; zero on entry
+  unsigned* ctrl;          // [0] failed count (zero on entry), [1] unused
   int* stage_cand;         // optional: candidates evaluated per stage
   int* stage_cert;         // optional: 1 if certified
   uint64_t* cand_keys;     // optional: the candidates' minimum key (before any fallback)
@@ -478,24 +478,22 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
 }
 
 // Full evaluation of the failed stages: items (failed stage, tile of 256
-// obstacles) pulled from a counter; each work-group folds its tile's minimum
-// into keys[s] with a 64-bit atomicMin.  The failed count and the item
-// counter start at zero: plan creation clears them, and so does the finish
-// kernel at the end of every screened call.
+// obstacles), every item the same work, taken by the work-groups in turn
+// (item b, b + grid, ...); each work-group folds its tile's minimum into
+// keys[s] with a 64-bit atomicMin.  The failed count starts at zero: plan
+// creation clears it, and so does the finish kernel at the end of every
+// screened call.
 template <int MF, int MI>
 __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int max_tiles) {
-  __shared__ int s_item;
   __shared__ uint64_t wk[4];
   __shared__ float4 rf[MF];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int n_failed = (int)__hip_atomic_load(&A.ctrl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (n_failed == 0) return;   // every stage certified: nothing to do
-  for (;;) {
-    if (tid == 0) s_item = (int)atomicAdd(&A.ctrl[1], 1u);
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(s_item);
-    if (it >= n_failed * max_tiles) break;
-    const int s = A.failed[it / max_tiles], tile = it % max_tiles;
+  const long n_items = (long)n_failed * max_tiles;
+  for (long item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const int it = __builtin_amdgcn_readfirstlane((int)(item / max_tiles));
+    const int tile = __builtin_amdgcn_readfirstlane((int)(item % max_tiles));
+    const int s = A.failed[it];
     const int inst = __builtin_amdgcn_readfirstlane(A.stage_inst[s]);
     const BatchInst in = A.insts[inst];
     if (tile * 256 < in.M) {

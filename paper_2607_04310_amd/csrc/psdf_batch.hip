@@ -92,10 +92,22 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
     const float* __restrict__ poses, const float* __restrict__ ax, const float* __restrict__ ay,
     const float* __restrict__ bx, const float* __restrict__ by, const int* __restrict__ off,
-    float4* __restrict__ hlist, int* __restrict__ hcount, uint32_t* __restrict__ hrest) {
+    float4* __restrict__ hlist, int* __restrict__ hcount, uint32_t* __restrict__ hrest,
+    const float* __restrict__ theta, uint4* __restrict__ frag) {
   __shared__ int scan[kScreenThreads];
   __shared__ uint32_t red[kScreenThreads / 64];
   __shared__ int s_base;
+  if (blockIdx.x == kHorizonSplit) {
+    // the extra column: the screener network's per-lane weight fragments,
+    // once per call (one wave), so that every stage's work-group reads them
+    // with coalesced vector loads instead of gathering the parameters
+    if (blockIdx.y == 0 && theta && threadIdx.x < 64) {
+      MlpFrag f;
+      mlp_load(theta, f);
+      mlp_frag_store(f, frag);
+    }
+    return;
+  }
   const int inst = blockIdx.y, part = blockIdx.x, tid = threadIdx.x;
   const BatchInst in = insts[inst];
   const FpConst& F = fps[inst];
@@ -424,16 +436,6 @@ BatchArgs make_args(psdf_batch_plan* p, const float* poses, const float* ax, con
   return a;
 }
 
-// The screener network's per-lane weight fragments, once per screened call
-// (one wave), so that every stage's work-group reads them with coalesced
-// vector loads instead of gathering the parameters.
-__global__ __launch_bounds__(64) void mlp_frag_kernel(const float* __restrict__ theta,
-                                                      uint4* __restrict__ table) {
-  MlpFrag f;
-  mlp_load(theta, f);
-  mlp_frag_store(f, table);
-}
-
 // One wave per stage (global row g): the stage's winning key, from the
 // minimum of its partial row (partial non-null: the winning column's aux
 // word carries the winner's global edge range) or from keys[g] (the screened
@@ -633,20 +635,20 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
   timer_begin(stream);
   hipError_t err = hipSuccess;
   if (p->n_inst > 0) {
-    const dim3 grid(kHorizonSplit, p->n_inst);
+    // column kHorizonSplit of the grid builds the network's fragment table
+    const dim3 grid(kHorizonSplit + (theta ? 1 : 0), p->n_inst);
     if (p->mi_class == 4)
       horizon_kernel<4><<<grid, kScreenThreads, 0, stream>>>(
-          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest);
+          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest,
+          theta, p->d_frag);
     else if (p->mi_class == 8)
       horizon_kernel<8><<<grid, kScreenThreads, 0, stream>>>(
-          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest);
+          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest,
+          theta, p->d_frag);
     else
       horizon_kernel<16><<<grid, kScreenThreads, 0, stream>>>(
-          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest);
-    err = hipGetLastError();
-  }
-  if (err == hipSuccess && theta) {
-    mlp_frag_kernel<<<1, 64, 0, stream>>>(theta, p->d_frag);
+          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest,
+          theta, p->d_frag);
     err = hipGetLastError();
   }
   for (const auto& g : p->sgroups) {

@@ -74,7 +74,8 @@ __device__ __forceinline__ void mlp_load(const float* __restrict__ th, MlpFrag& 
 
 // The fragments of all 64 lanes as a table of kFragWords 16-byte words per
 // lane, word k of lane l at [k * 64 + l] (coalesced across the wave): built
-// once per call by mlp_frag_kernel, read with kFragWords vector loads.
+// once per call by the horizon pass (its extra grid column), read with
+// kFragWords vector loads.
 constexpr int kFragWords = (sizeof(MlpFrag) + 15) / 16;
 
 __device__ __forceinline__ void mlp_frag_store(const MlpFrag& f, uint4* __restrict__ table) {

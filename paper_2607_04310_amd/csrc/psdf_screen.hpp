@@ -60,7 +60,7 @@ struct ScreenArgs {
   const int* hcount;       // per instance: length of hlist, or -1 for every obstacle
   const uint32_t* hrest;   // per instance: lower-bound key of every obstacle not in hlist
   const float* theta;      // MLP parameters, or nullptr: rank by edge distance
-  const uint4* frag;       // the network's lane fragments (mlp_frag_kernel), used with theta
+  const uint4* frag;       // the network's lane fragments (built by horizon_kernel), used with theta
   int pool;                // P
   int topk;                // K
   uint64_t* keys;

@@ -257,6 +257,10 @@ struct psdf_batch_plan {
   int max_M = 0;
   // graph
   hipStream_t cap_stream = nullptr;
+  // footprint-size groups run concurrently: group k > 0 on side[k - 1],
+  // forked from and joined back to the caller's stream with events
+  hipStream_t side[6] = {};
+  hipEvent_t ev[7] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<const void*> bound;
@@ -319,6 +323,9 @@ bool cache_find(const std::string& key, Shape* s) {
 
 constexpr int kGroupMF[] = {3, 4, 5, 6, 7, 8, 16};
 constexpr int kGroups = 7;
+static_assert(sizeof(psdf_batch_plan::side) / sizeof(hipStream_t) == kGroups - 1 &&
+                  sizeof(psdf_batch_plan::ev) / sizeof(hipEvent_t) == kGroups,
+              "one side stream per group after the first, one event per group");
 int group_of(int m) { return m <= 8 ? m - 3 : 6; }
 
 hipError_t launch_batch(int mf, int mi_class, int nw, int grid, const BatchArgs& a, hipStream_t st) {
@@ -532,14 +539,27 @@ int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay
   if (p->total_stages == 0) return PSDF_OK;
   const BatchArgs a = make_args(p, poses, ax, ay, bx, by, off, d, edge, obst, grad, keys);
   auto enqueue = [&](hipStream_t st) -> hipError_t {
-    for (const auto& g : p->groups) {
+    // the groups write disjoint partial rows and count their items on
+    // counters of their own, so they run concurrently (their tails overlap)
+    const int ng = (int)p->groups.size();
+    hipError_t err = hipSuccess;
+    if (ng > 1) {
+      err = hipEventRecord(p->ev[0], st);
+      for (int k = 1; k < ng && err == hipSuccess; ++k)
+        err = hipStreamWaitEvent(p->side[k - 1], p->ev[0], 0);
+    }
+    for (int k = 0; k < ng && err == hipSuccess; ++k) {
+      const auto& g = p->groups[k];
       BatchArgs ga = a;
       ga.items = a.items + g.start;
       ga.n_items = g.count;
       ga.ctrl = a.ctrl + group_of(g.mf);
-      hipError_t err = launch_batch(g.mf, p->mi_class, p->shape.nw, g.grid, ga, st);
-      if (err != hipSuccess) return err;
+      hipStream_t gs = k == 0 ? st : p->side[k - 1];
+      err = launch_batch(g.mf, p->mi_class, p->shape.nw, g.grid, ga, gs);
+      if (err == hipSuccess && k > 0) err = hipEventRecord(p->ev[k], gs);
+      if (err == hipSuccess && k > 0) err = hipStreamWaitEvent(st, p->ev[k], 0);
     }
+    if (err != hipSuccess) return err;
     batch_finish_kernel<<<(p->total_stages + 3) / 4, 256, 0, st>>>(
         p->d_fp, p->d_inst, p->d_stage_inst, p->total_stages, poses, ax, ay, bx, by, off,
         a.partial, a.aux, keys, d, edge, obst, grad, p->d_ctrl, kGroups, nullptr, nullptr, 0);
@@ -696,6 +716,10 @@ void psdf_batch_plan_destroy(psdf_batch_plan* p) {
   (void)hipSetDevice(p->device);
   free_graph(p);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (hipStream_t s : p->side)
+    if (s) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : p->ev)
+    if (e) (void)hipEventDestroy(e);
   (void)hipFree(p->d_fp);
   (void)hipFree(p->d_inst);
   (void)hipFree(p->d_items);
@@ -765,6 +789,10 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
   if (err == hipSuccess && n_inst > 0)
     err = hipMemcpy(p->d_fp, p->fp.data(), n_inst * sizeof(FpConst), hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+  for (hipStream_t& s : p->side)
+    if (err == hipSuccess) err = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  for (hipEvent_t& e : p->ev)
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
   // screening tables
   if (err == hipSuccess) {
     const int S = std::max(1, p->total_stages);

@@ -271,6 +271,9 @@ int psdf_batch_plan_create(psdf_batch_plan** plan, const psdf_batch_desc* desc, 
 void psdf_batch_plan_destroy(psdf_batch_plan* plan);
 
 /* Evaluate every instance: d, edge, obst, grad and keys as described above.
+ * The launches of the different footprint sizes run concurrently: they fork
+ * from `stream` onto plan-owned side streams with events and join back
+ * before the final kernel, so the call still completes in `stream` order.
  * With PSDF_BATCH_GRAPH the first call (and any call whose pointers differ
  * from the captured ones) captures the launch into a hipGraph on a
  * plan-owned stream; later calls replay it on `stream`.  Input contents may

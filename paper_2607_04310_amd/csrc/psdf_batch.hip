@@ -82,7 +82,8 @@ __device__ float4 obstacle_circle(const BatchInst& in, const float* __restrict__
 // longer than kHorizonCap (tie blocks) is not used by the stage pass either:
 // the instance's stages then take the full evaluation.  On entry the
 // instance's count is 0 and its bound +inf (plan creation, then the finish
-// kernel of every screened call).
+// kernel of every screened call).  With a network the grid has one more
+// column, whose first work-group builds the network's fragment table.
 constexpr int kHorizonPool = 1024;
 constexpr int kHorizonSplit = 16;
 constexpr int kHorizonKeys = kScreenMaxM / kHorizonSplit / kScreenThreads;   // 4

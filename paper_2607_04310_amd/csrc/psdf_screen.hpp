@@ -34,8 +34,8 @@
 namespace psdf {
 
 constexpr int kScreenThreads = 256;
-constexpr int kScreenKeysPerThread = 64;                       // obstacles per thread (horizon pass)
-constexpr int kScreenMaxM = kScreenThreads * kScreenKeysPerThread;   // 16384
+constexpr int kScreenKeysPerThread = 64;                       // obstacles per thread and instance
+constexpr int kScreenMaxM = kScreenThreads * kScreenKeysPerThread;   // 16384, the most screened
 constexpr int kStageKeys = 8;                                  // horizon entries per thread (stage pass)
 constexpr int kHorizonCap = kScreenThreads * kStageKeys;       // 2048
 constexpr int kPoolCap = 512;                                  // pool capacity (ties included)

@@ -233,6 +233,67 @@ static int mf_slots(int m) { return m <= 8 ? m : 16; }
 
 int partial_columns(int M, const LaunchShape& ls) { return (M + ls.blk - 1) / ls.blk; }
 
+// Small edge sets (1 <= M <= 64 obstacles of at most four edges): one wave
+// per stage holds every obstacle (lane <-> obstacle), takes the stage's
+// minimum with the same wave_stages arithmetic as main_kernel, and finishes
+// the stage at once (epilogue_finish) in one launch instead of two.  The
+// result is the two-kernel result bit for bit: the single partial column's
+// (key, aux) is exactly what the epilogue would have reduced.
+constexpr int kSmallWaves = 4;   // stages per work-group
+constexpr int kSmallMaxM = 64;
+
+template <int MF>
+__global__ __launch_bounds__(64 * kSmallWaves) void small_kernel(
+    FpConst F, const float* __restrict__ poses, int N, const float* __restrict__ ax,
+    const float* __restrict__ ay, const float* __restrict__ bx, const float* __restrict__ by,
+    const int* __restrict__ off, int E, int M, EpiOut O) {
+  __shared__ float4 st[kSmallWaves];
+  __shared__ float4 rft[kSmallWaves * MF];
+  __shared__ FpLds fl[kSmallWaves];
+  __shared__ WinnerLds wl[kSmallWaves];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int s = blockIdx.x * kSmallWaves + w;
+  if (s >= N) return;   // whole waves only: no work-group barrier below
+  const bool active = lane < M;
+  int e0 = 0, mi = 0;
+  if (active) {
+    e0 = off[lane];
+    mi = off[lane + 1] - e0;
+  }
+  const float* p = poses + 3 * s;
+  const float px = p[0], py = p[1];
+  float sn, cs;
+  sincosf(p[2], &sn, &cs);
+  // the wave's one-stage table, as fill_stage_table builds it
+  if (lane < MF) rft[w * MF + lane] = rotated_slot(F, lane, cs, sn);
+  if (lane == 0) st[w] = make_float4(cs, sn, px, py);
+  stage_footprint(fl[w], F);
+  wave_sync();
+  uint64_t key = kEmptyKey, a = 0;   // uniform across the wave
+  auto emit = [&](int, uint64_t k, uint64_t x) {
+    key = k;
+    a = x;
+  };
+  wave_stages<MF, 4>(F, ax, ay, bx, by, e0, mi, E, active, false, 0, 1, st + w, rft + w * MF,
+                     emit);
+  if (lane == 0) O.keys[s] = key;
+  epilogue_finish(F, fl[w], wl[w], ax, ay, bx, by, off, E, M, s, px, py, cs, sn, key,
+                  (int)(uint32_t)(a >> 32), (int)(uint32_t)(a & 0xffffffffu), true, 1.0f, O);
+}
+
+template <int MF>
+hipError_t launch_small_mf(const FpConst& F, const float* poses, int N, const psdf_edges& e,
+                           const EpiOut& O, hipStream_t st) {
+  small_kernel<MF><<<(N + kSmallWaves - 1) / kSmallWaves, 64 * kSmallWaves, 0, st>>>(
+      F, poses, N, e.ax, e.ay, e.bx, e.by, e.obst_off, e.E, e.M, O);
+  return hipGetLastError();
+}
+
+bool small_path(const psdf_edges& e) {
+  return e.M >= 1 && e.M <= kSmallMaxM && obst_class(e.mbar) == 4;
+}
+
+
 hipError_t launch_plain(const FpConst& F, const float* poses, int N, const psdf_edges& e,
                         uint64_t* partial, const LaunchShape& ls, hipStream_t st) {
   if (e.M == 0) return hipSuccess;
@@ -381,6 +442,10 @@ static int plain_run(const float* footprint, int32_t m, const float* poses, int3
     return set_error(PSDF_EWS, "workspace of %zu bytes, %zu needed", ws_bytes, need);
   if (need > 0 && (reinterpret_cast<uintptr_t>(ws) & 15u) != 0)
     return set_error(PSDF_EINVAL, "workspace is not 16-byte aligned");
+  if (small_path(e)) {
+    const EpiOut O{keys, nullptr, mode, 0.0f, d, edge, obst, grad, nullptr};
+    return hip_status(PSDF_BY_MF(launch_small_mf, F, poses, N, e, O, stream));
+  }
   const LaunchShape ls = tuned_shape(F.m, e.mbar, N, e.M);
   uint64_t* partial = static_cast<uint64_t*>(ws);
   hipError_t err = launch_plain(F, poses, N, e, partial, ls, stream);
@@ -457,12 +522,18 @@ int psdf_constraints(const float* footprint, int32_t m, const float* poses, int3
     return set_error(PSDF_EWS, "workspace of %zu bytes, %zu needed", ws_bytes, need);
   if (need > 0 && (reinterpret_cast<uintptr_t>(ws) & 15u) != 0)
     return set_error(PSDF_EINVAL, "workspace is not 16-byte aligned");
-  const LaunchShape ls = tuned_shape(F.m, e.mbar, N, e.M);
-  uint64_t* partial = static_cast<uint64_t*>(ws);
-  hipError_t err = launch_plain(F, poses, N, e, partial, ls, stream);
-  if (err == hipSuccess)
-    err = launch_epilogue(F, poses, N, e, partial, e.M > 0 ? partial_columns(e.M, ls) : 0, keys,
-                          nullptr, 1, d_min, nullptr, nullptr, nullptr, nullptr, hj, stream);
+  hipError_t err = hipSuccess;
+  if (small_path(e)) {
+    const EpiOut O{keys, nullptr, 1, d_min, nullptr, nullptr, nullptr, nullptr, hj};
+    err = PSDF_BY_MF(launch_small_mf, F, poses, N, e, O, stream);
+  } else {
+    const LaunchShape ls = tuned_shape(F.m, e.mbar, N, e.M);
+    uint64_t* partial = static_cast<uint64_t*>(ws);
+    err = launch_plain(F, poses, N, e, partial, ls, stream);
+    if (err == hipSuccess)
+      err = launch_epilogue(F, poses, N, e, partial, e.M > 0 ? partial_columns(e.M, ls) : 0, keys,
+                            nullptr, 1, d_min, nullptr, nullptr, nullptr, nullptr, hj, stream);
+  }
   if (err == hipSuccess && hj_host)
     err = hipMemcpyAsync(hj_host, hj, (size_t)N * 4 * sizeof(float), hipMemcpyDeviceToHost, stream);
   return hip_status(err);

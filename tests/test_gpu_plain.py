@@ -294,6 +294,28 @@ def test_launch_shape_independent(api, blk, sb):
         assert np.array_equal(x, y)
 
 
+def test_small_path_matches_two_kernel_path(api):
+    """Edge sets of at most 64 obstacles (of at most four edges) take the
+    one-launch path; one empty obstacle appended (65 obstacles, no new edge)
+    sends the same problem through the two-kernel path, and the outputs must
+    agree bit for bit, a non-finite pose included."""
+    for seed in (0, 1, 2):
+        inst = inputs.c1(seed)
+        assert inst.M == 64
+        inst.poses = inst.poses.copy()
+        inst.poses[5, 1] = np.nan
+        big = inputs.Instance(inst.footprint, inst.poses, inst.edges,
+                              np.append(inst.obst_off, inst.obst_off[-1]).astype(np.int32),
+                              inst.mbar, dict(workload="c1 + empty obstacle"))
+        assert big.M == 65
+        for grad in (True, False):
+            a, b = run(api, inst, grad=grad), run(api, big, grad=grad)
+            for x, y in zip(a, b):
+                if x is None:
+                    continue
+                assert np.array_equal(x, y, equal_nan=True)
+
+
 def test_constraints_export(api):
     """psdf_constraints: (phi - d_min, -grad) per stage, equal to psdf_grad's
     outputs transformed in FP32, and the pinned host copy equal to the device

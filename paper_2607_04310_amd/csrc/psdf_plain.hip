@@ -233,59 +233,90 @@ static int mf_slots(int m) { return m <= 8 ? m : 16; }
 
 int partial_columns(int M, const LaunchShape& ls) { return (M + ls.blk - 1) / ls.blk; }
 
-// Small edge sets (1 <= M <= 64 obstacles of at most four edges): one wave
-// per stage holds every obstacle (lane <-> obstacle), takes the stage's
-// minimum with the same wave_stages arithmetic as main_kernel, and finishes
-// the stage at once (epilogue_finish) in one launch instead of two.  The
-// result is the two-kernel result bit for bit: the single partial column's
-// (key, aux) is exactly what the epilogue would have reduced.
-constexpr int kSmallWaves = 4;   // stages per work-group
-constexpr int kSmallMaxM = 64;
+// Small edge sets (1 <= M <= 256 obstacles of at most four edges): NW waves
+// hold every obstacle of a stage (lane <-> obstacle, wave w takes obstacles
+// 64 w ...), take the stage's minimum with the same wave_stages arithmetic as
+// main_kernel, and the first wave finishes the stage at once
+// (epilogue_finish): one launch instead of two.  The result is the
+// two-kernel result bit for bit: keys are unique, so the minimum over the
+// waves' (key, aux) pairs is what the epilogue would have reduced.  NW = 1:
+// four stages per work-group, one wave each; NW = 4: one stage per
+// work-group.
+constexpr int kSmallMaxM = 256;
 
-template <int MF>
-__global__ __launch_bounds__(64 * kSmallWaves) void small_kernel(
+template <int MF, int NW>
+__global__ __launch_bounds__(256) void small_kernel(
     FpConst F, const float* __restrict__ poses, int N, const float* __restrict__ ax,
     const float* __restrict__ ay, const float* __restrict__ bx, const float* __restrict__ by,
     const int* __restrict__ off, int E, int M, EpiOut O) {
-  __shared__ float4 st[kSmallWaves];
-  __shared__ float4 rft[kSmallWaves * MF];
-  __shared__ FpLds fl[kSmallWaves];
-  __shared__ WinnerLds wl[kSmallWaves];
+  constexpr int SPB = 4 / NW;   // stages per work-group
+  __shared__ float4 st[SPB];
+  __shared__ float4 rft[SPB * MF];
+  __shared__ FpLds fl[SPB];
+  __shared__ WinnerLds wl[SPB];
+  __shared__ uint64_t wk[4], wa[4];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int s = blockIdx.x * kSmallWaves + w;
-  if (s >= N) return;   // whole waves only: no work-group barrier below
-  const bool active = lane < M;
+  const int slot = NW == 1 ? w : 0;             // the work-group's stage slot of this wave
+  const int s = blockIdx.x * SPB + slot;
+  if (s >= N) return;   // with NW = 4 the whole work-group; else whole waves
+  const int obase = NW == 1 ? 0 : 64 * w;
+  const bool active = obase + lane < M;
   int e0 = 0, mi = 0;
   if (active) {
-    e0 = off[lane];
-    mi = off[lane + 1] - e0;
+    e0 = off[obase + lane];
+    mi = off[obase + lane + 1] - e0;
   }
   const float* p = poses + 3 * s;
   const float px = p[0], py = p[1];
   float sn, cs;
   sincosf(p[2], &sn, &cs);
-  // the wave's one-stage table, as fill_stage_table builds it
-  if (lane < MF) rft[w * MF + lane] = rotated_slot(F, lane, cs, sn);
-  if (lane == 0) st[w] = make_float4(cs, sn, px, py);
-  stage_footprint(fl[w], F);
-  wave_sync();
+  // the stage table, as fill_stage_table builds it (written by the stage's
+  // first wave)
+  const bool first = NW == 1 || w == 0;
+  if (first) {
+    if (lane < MF) rft[slot * MF + lane] = rotated_slot(F, lane, cs, sn);
+    if (lane == 0) st[slot] = make_float4(cs, sn, px, py);
+    stage_footprint(fl[slot], F);
+  }
+  if (NW == 1) wave_sync();
+  else __syncthreads();
   uint64_t key = kEmptyKey, a = 0;   // uniform across the wave
-  auto emit = [&](int, uint64_t k, uint64_t x) {
-    key = k;
-    a = x;
-  };
-  wave_stages<MF, 4>(F, ax, ay, bx, by, e0, mi, E, active, false, 0, 1, st + w, rft + w * MF,
-                     emit);
+  if (obase < M) {
+    auto emit = [&](int, uint64_t k, uint64_t x) {
+      key = k;
+      a = x;
+    };
+    wave_stages<MF, 4>(F, ax, ay, bx, by, e0, mi, E, active, false, obase, 1, st + slot,
+                       rft + slot * MF, emit);
+  }
+  if (NW > 1) {
+    if (lane == 0) {
+      wk[w] = key;
+      wa[w] = a;
+    }
+    __syncthreads();
+    if (w != 0) return;
+#pragma unroll
+    for (int v = 1; v < NW; ++v)
+      if (wk[v] < key) {
+        key = wk[v];
+        a = wa[v];
+      }
+  }
   if (lane == 0) O.keys[s] = key;
-  epilogue_finish(F, fl[w], wl[w], ax, ay, bx, by, off, E, M, s, px, py, cs, sn, key,
+  epilogue_finish(F, fl[slot], wl[slot], ax, ay, bx, by, off, E, M, s, px, py, cs, sn, key,
                   (int)(uint32_t)(a >> 32), (int)(uint32_t)(a & 0xffffffffu), true, 1.0f, O);
 }
 
 template <int MF>
 hipError_t launch_small_mf(const FpConst& F, const float* poses, int N, const psdf_edges& e,
                            const EpiOut& O, hipStream_t st) {
-  small_kernel<MF><<<(N + kSmallWaves - 1) / kSmallWaves, 64 * kSmallWaves, 0, st>>>(
-      F, poses, N, e.ax, e.ay, e.bx, e.by, e.obst_off, e.E, e.M, O);
+  if (e.M <= 64)
+    small_kernel<MF, 1><<<(N + 3) / 4, 256, 0, st>>>(F, poses, N, e.ax, e.ay, e.bx, e.by,
+                                                     e.obst_off, e.E, e.M, O);
+  else
+    small_kernel<MF, 4><<<N, 256, 0, st>>>(F, poses, N, e.ax, e.ay, e.bx, e.by, e.obst_off, e.E,
+                                           e.M, O);
   return hipGetLastError();
 }
 

@@ -295,25 +295,28 @@ def test_launch_shape_independent(api, blk, sb):
 
 
 def test_small_path_matches_two_kernel_path(api):
-    """Edge sets of at most 64 obstacles (of at most four edges) take the
-    one-launch path; one empty obstacle appended (65 obstacles, no new edge)
-    sends the same problem through the two-kernel path, and the outputs must
-    agree bit for bit, a non-finite pose included."""
+    """Edge sets of at most 256 obstacles (of at most four edges) take the
+    one-launch path (one wave per stage up to 64 obstacles, four above).
+    Empty obstacles appended (no new edge) move the same problem to the
+    four-wave form (65 obstacles) and to the two-kernel path (257), and the
+    outputs must agree bit for bit, a non-finite pose included."""
     for seed in (0, 1, 2):
         inst = inputs.c1(seed)
         assert inst.M == 64
         inst.poses = inst.poses.copy()
         inst.poses[5, 1] = np.nan
-        big = inputs.Instance(inst.footprint, inst.poses, inst.edges,
-                              np.append(inst.obst_off, inst.obst_off[-1]).astype(np.int32),
-                              inst.mbar, dict(workload="c1 + empty obstacle"))
-        assert big.M == 65
-        for grad in (True, False):
-            a, b = run(api, inst, grad=grad), run(api, big, grad=grad)
-            for x, y in zip(a, b):
-                if x is None:
-                    continue
-                assert np.array_equal(x, y, equal_nan=True)
+        outs = {}
+        for M in (64, 65, 257):
+            off = np.concatenate([inst.obst_off, np.full(M - 64, inst.obst_off[-1])]).astype(np.int32)
+            padded = inputs.Instance(inst.footprint, inst.poses, inst.edges, off, inst.mbar,
+                                     dict(workload=f"c1 + {M - 64} empty obstacles"))
+            assert padded.M == M
+            outs[M] = [run(api, padded, grad=g) for g in (True, False)]
+        for M in (65, 257):
+            for a, b in zip(outs[64], outs[M]):
+                for x, y in zip(a, b):
+                    if x is not None:
+                        assert np.array_equal(x, y, equal_nan=True)
 
 
 def test_constraints_export(api):

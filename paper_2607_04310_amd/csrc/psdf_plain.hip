@@ -6,6 +6,8 @@
 //   epilogue_kernel  one wave per stage: reduce the partial keys, recompute the
 //                    winning obstacle with the wave-parallel adjoint
 //                    (psdf_winner.hpp), write keys, d, edge, obst, gradient
+// or, for at most 256 obstacles of at most four edges, small_kernel alone
+// (both steps for a stage in one launch, bit for bit the same outputs).
 #include <hip/hip_runtime.h>
 
 #include <cmath>

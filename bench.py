@@ -240,9 +240,9 @@ def extras(torch, api, flops, inputs):
     c5 = inputs.c5(64)
     pairs5 = sum(i.N * i.E for i in c5)
     b = api.Batch(c5, graph=True)
-    # a kernel this long reaches its steady clock only after some tens of
-    # calls (first block of ten about 15 % slower), so these c5 lines warm up
-    # for 30 calls and report the median of five blocks
+    # the first blocks of ten calls of this workload run up to 15 % slower
+    # than the later ones (measured: 0.73, 0.68, 0.65, 0.62, 0.62 ms), so
+    # these c5 lines warm up for 30 calls and report the median of five blocks
     t_plain = _timeit(torch, b.run, 10, 30, blocks=5)
     res = dict(pairs=pairs5, train_pairs=int(X.shape[0]), train_loss=hist[-1], plain_ms=t_plain,
                plain_evals_per_s=pairs5 / (t_plain * 1e-3))

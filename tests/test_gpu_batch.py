@@ -88,6 +88,25 @@ def test_graph_replay_after_inputs_change(api, c4):
     b.close()
 
 
+def test_concurrent_groups_graph_replays(api, c4):
+    """Several footprint sizes run as concurrent launches (forked streams,
+    graph branches once captured): every replay, with eager work and host
+    synchronisations between replays, equals the per-instance loop."""
+    sub = c4[:60]
+    assert len({len(i.footprint) for i in sub}) > 1     # more than one group
+    ref = None
+    for graph in (True, False):
+        b = api.Batch(sub, graph=graph)
+        for rep in range(4):
+            out = batch_out(b)
+            if ref is None:
+                ref = per_instance(api, b)
+            assert_equal_outputs(out, ref)
+            x = torch.randn(1 << 20, device="cuda")       # eager work between replays
+            (x * 2.0).sum().item()
+        b.close()
+
+
 def test_autotune_keeps_results(api, c4):
     sub = c4[:96]
     b = api.Batch(sub, graph=True, autotune=True)

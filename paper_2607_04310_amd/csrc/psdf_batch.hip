@@ -544,6 +544,7 @@ int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay
     // counters of their own, so they run concurrently (their tails overlap)
     const int ng = (int)p->groups.size();
     hipError_t err = hipSuccess;
+    if (ng > 1 && !p->side[ng - 2]) return hipErrorInvalidValue;   // created with the plan
     if (ng > 1) {
       err = hipEventRecord(p->ev[0], st);
       for (int k = 1; k < ng && err == hipSuccess; ++k)
@@ -790,10 +791,18 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
   if (err == hipSuccess && n_inst > 0)
     err = hipMemcpy(p->d_fp, p->fp.data(), n_inst * sizeof(FpConst), hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
-  for (hipStream_t& s : p->side)
-    if (err == hipSuccess) err = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-  for (hipEvent_t& e : p->ev)
-    if (err == hipSuccess) err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+  // side streams and events for the concurrent footprint-size groups: one
+  // stream per group present after the first, one event per group
+  {
+    bool present[kGroups] = {};
+    for (int k = 0; k < n_inst; ++k) present[group_of(p->fp[k].m)] = true;
+    int ng = 0;
+    for (bool b : present) ng += b ? 1 : 0;
+    for (int k = 0; k + 1 < ng && err == hipSuccess; ++k)
+      err = hipStreamCreateWithFlags(&p->side[k], hipStreamNonBlocking);
+    for (int k = 0; k < ng && ng > 1 && err == hipSuccess; ++k)
+      err = hipEventCreateWithFlags(&p->ev[k], hipEventDisableTiming);
+  }
   // screening tables
   if (err == hipSuccess) {
     const int S = std::max(1, p->total_stages);

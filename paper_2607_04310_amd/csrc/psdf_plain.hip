@@ -18,7 +18,7 @@
 
 namespace psdf {
 
-constexpr int kEpiWaves = 4;   // stages per epilogue work-group
+constexpr int kEpiWaves = 1;   // stages per epilogue work-group
 
 // mode 0: value, winner and edge; 1: plus gradient; 2: bwd (gradient scaled
 // by gout[s], written to grad only; keys are read, not reduced).  In modes 0

@@ -456,7 +456,9 @@ BatchArgs make_args(psdf_batch_plan* p, const float* poses, const float* ax, con
 // item (or screening) counters of the launches before it on the stream, and
 // opens the n_inst horizon lists for the next screened call (count 0, bound
 // +inf).
-__global__ __launch_bounds__(256) void batch_finish_kernel(
+constexpr int kFinWaves = 1;   // stages per finish work-group (one wave each)
+
+__global__ __launch_bounds__(64 * kFinWaves) void batch_finish_kernel(
     const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
     const int* __restrict__ stage_inst, int S, const float* __restrict__ poses,
     const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ bx,
@@ -465,8 +467,8 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(
     uint64_t* __restrict__ keys, float* __restrict__ d, int* __restrict__ edge,
     int* __restrict__ obst, float* __restrict__ grad, unsigned* __restrict__ ctrl, int n_ctrl,
     int* __restrict__ hcount, uint32_t* __restrict__ hrest, int n_inst) {
-  __shared__ FpLds fl[4];
-  __shared__ WinnerLds wl[4];
+  __shared__ FpLds fl[kFinWaves];
+  __shared__ WinnerLds wl[kFinWaves];
   if (blockIdx.x == 0) {
     if ((int)threadIdx.x < n_ctrl) ctrl[threadIdx.x] = 0u;
     for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(
     }
   }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = blockIdx.x * 4 + w;
+  const int g = blockIdx.x * kFinWaves + w;
   if (g >= S) return;
   const int inst = __builtin_amdgcn_readfirstlane(stage_inst[g]);
   const BatchInst in = insts[inst];
@@ -565,7 +567,7 @@ int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay
       if (err == hipSuccess && k > 0) err = hipStreamWaitEvent(st, p->ev[k], 0);
     }
     if (err != hipSuccess) return err;
-    batch_finish_kernel<<<(p->total_stages + 3) / 4, 256, 0, st>>>(
+    batch_finish_kernel<<<(p->total_stages + kFinWaves - 1) / kFinWaves, 64 * kFinWaves, 0, st>>>(
         p->d_fp, p->d_inst, p->d_stage_inst, p->total_stages, poses, ax, ay, bx, by, off,
         a.partial, a.aux, keys, d, edge, obst, grad, p->d_ctrl, kGroups, nullptr, nullptr, 0);
     return hipGetLastError();
@@ -691,7 +693,8 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
   }
   timer_end(stream);
   if (err == hipSuccess) {
-    batch_finish_kernel<<<(p->total_stages + 3) / 4, 256, 0, stream>>>(
+    batch_finish_kernel<<<(p->total_stages + kFinWaves - 1) / kFinWaves, 64 * kFinWaves, 0,
+                          stream>>>(
         p->d_fp, p->d_inst, p->d_stage_inst, p->total_stages, poses, ax, ay, bx, by, off, nullptr,
         nullptr, keys, d, edge, obst, grad, p->d_sctrl, 2 * kGroups, p->d_hcount, p->d_hrest,
         p->n_inst);

@@ -241,27 +241,25 @@ int partial_columns(int M, const LaunchShape& ls) { return (M + ls.blk - 1) / ls
 // main_kernel, and the first wave finishes the stage at once
 // (epilogue_finish): one launch instead of two.  The result is the
 // two-kernel result bit for bit: keys are unique, so the minimum over the
-// waves' (key, aux) pairs is what the epilogue would have reduced.  NW = 1:
-// four stages per work-group, one wave each; NW = 4: one stage per
-// work-group.
+// waves' (key, aux) pairs is what the epilogue would have reduced.  One
+// stage per work-group of NW waves (one-wave work-groups spread the stages
+// over the CUs).
 constexpr int kSmallMaxM = 256;
 
 template <int MF, int NW>
-__global__ __launch_bounds__(256) void small_kernel(
+__global__ __launch_bounds__(64 * NW) void small_kernel(
     FpConst F, const float* __restrict__ poses, int N, const float* __restrict__ ax,
     const float* __restrict__ ay, const float* __restrict__ bx, const float* __restrict__ by,
     const int* __restrict__ off, int E, int M, EpiOut O) {
-  constexpr int SPB = 4 / NW;   // stages per work-group
-  __shared__ float4 st[SPB];
-  __shared__ float4 rft[SPB * MF];
-  __shared__ FpLds fl[SPB];
-  __shared__ WinnerLds wl[SPB];
-  __shared__ uint64_t wk[4], wa[4];
+  __shared__ float4 st[1];
+  __shared__ float4 rft[MF];
+  __shared__ FpLds fl[1];
+  __shared__ WinnerLds wl[1];
+  __shared__ uint64_t wk[NW], wa[NW];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int slot = NW == 1 ? w : 0;             // the work-group's stage slot of this wave
-  const int s = blockIdx.x * SPB + slot;
-  if (s >= N) return;   // with NW = 4 the whole work-group; else whole waves
-  const int obase = NW == 1 ? 0 : 64 * w;
+  const int s = blockIdx.x;
+  if (s >= N) return;   // the whole work-group
+  const int obase = 64 * w;
   const bool active = obase + lane < M;
   int e0 = 0, mi = 0;
   if (active) {
@@ -274,11 +272,10 @@ __global__ __launch_bounds__(256) void small_kernel(
   sincosf(p[2], &sn, &cs);
   // the stage table, as fill_stage_table builds it (written by the stage's
   // first wave)
-  const bool first = NW == 1 || w == 0;
-  if (first) {
-    if (lane < MF) rft[slot * MF + lane] = rotated_slot(F, lane, cs, sn);
-    if (lane == 0) st[slot] = make_float4(cs, sn, px, py);
-    stage_footprint(fl[slot], F);
+  if (w == 0) {
+    if (lane < MF) rft[lane] = rotated_slot(F, lane, cs, sn);
+    if (lane == 0) st[0] = make_float4(cs, sn, px, py);
+    stage_footprint(fl[0], F);
   }
   if (NW == 1) wave_sync();
   else __syncthreads();
@@ -288,8 +285,7 @@ __global__ __launch_bounds__(256) void small_kernel(
       key = k;
       a = x;
     };
-    wave_stages<MF, 4>(F, ax, ay, bx, by, e0, mi, E, active, false, obase, 1, st + slot,
-                       rft + slot * MF, emit);
+    wave_stages<MF, 4>(F, ax, ay, bx, by, e0, mi, E, active, false, obase, 1, st, rft, emit);
   }
   if (NW > 1) {
     if (lane == 0) {
@@ -306,7 +302,7 @@ __global__ __launch_bounds__(256) void small_kernel(
       }
   }
   if (lane == 0) O.keys[s] = key;
-  epilogue_finish(F, fl[slot], wl[slot], ax, ay, bx, by, off, E, M, s, px, py, cs, sn, key,
+  epilogue_finish(F, fl[0], wl[0], ax, ay, bx, by, off, E, M, s, px, py, cs, sn, key,
                   (int)(uint32_t)(a >> 32), (int)(uint32_t)(a & 0xffffffffu), true, 1.0f, O);
 }
 
@@ -314,8 +310,8 @@ template <int MF>
 hipError_t launch_small_mf(const FpConst& F, const float* poses, int N, const psdf_edges& e,
                            const EpiOut& O, hipStream_t st) {
   if (e.M <= 64)
-    small_kernel<MF, 1><<<(N + 3) / 4, 256, 0, st>>>(F, poses, N, e.ax, e.ay, e.bx, e.by,
-                                                     e.obst_off, e.E, e.M, O);
+    small_kernel<MF, 1><<<N, 64, 0, st>>>(F, poses, N, e.ax, e.ay, e.bx, e.by, e.obst_off, e.E,
+                                          e.M, O);
   else
     small_kernel<MF, 4><<<N, 256, 0, st>>>(F, poses, N, e.ax, e.ay, e.bx, e.by, e.obst_off, e.E,
                                            e.M, O);

@@ -1,23 +1,41 @@
 """Benchmark of the PSDF hot path on one MI355X.
 
-A step is one psdf_grad call (per-stage minimum over obstacles, winning
-obstacle and edge, and the pose gradient) on the 'c2' workload: hexagonal
-footprint (circumradius 0.5 m, radii jittered +-10 %), N = 50 stage poses
-along a random smooth path, 16384 edges from 4096 random rectangles in a
-40 x 40 m square.  Inputs are resident in HBM before the timed region.
+A step is one psdf_batch call (value, winning obstacle and edge, and the pose
+gradient of every stage) on the 'c5' workload: 64 independent instances,
+each a hexagonal footprint (circumradius 0.5 m, vertex radii jittered
++-10 %) at N = 50 stage poses along a random smooth path, against 65536 edges
+from 16384 rectangles (sides U[0.1, 0.8] m) whose centres follow a
+32-component Gaussian mixture (sigma = 2 m) in a 60 x 60 m square;
+2.10e8 stage x edge pairs per step.  Inputs are resident in HBM before the
+timed region.
 
-Prints one JSON line: value = stage x edge evaluations per second of whole
-psdf_grad calls, K calls captured into one HIP graph and replayed (the eager
-per-call rate, host launch cost included, is reported beside it); roofline of the dominant (per-stage minimum) kernel from HIP
-events on its launch stream (K back-to-back launches between one event pair;
-the per-launch event-bracketed figure, which adds the dispatch overhead, is
-reported beside it); cpu_baseline = the FP64 oracle on host cores.
+Prints one JSON line:
+  value        stage x edge evaluations per second of whole psdf_batch calls
+               (K calls, each a replay of the plan's HIP graph, between one
+               event pair);
+  screened     the same outputs (bit for bit) from the certified screened
+               forms on the same inputs: the bound-threshold form, and the
+               top-K forms ranked by the edge distance and by the screener
+               network trained on held-out instances; rate, certification,
+               exact evaluations per stage, winner recall;
+  roofline     the persistent batch kernel: algorithmic FLOP per launch over
+               its mean duration from HIP events that each dispatch records
+               on its launch stream; VALU issue and HBM bytes from the
+               rocprofv3 counter summaries in profiles/ while the kernel's
+               sources are unchanged;
+  cpu_baseline the FP64 oracle on the host's cores (all, and one), built for
+               the host (-O3 -march=native), on a bounded c5 sample;
+  extras       c2 latency (one psdf_grad call), c2 x 256, the uneven batch c4
+               against its per-instance loop, one pose against growing edge
+               sets, the paper's Table I query shapes.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,163 +48,232 @@ PEAK_FP32_TFLOPS = 157.3
 # instruction).  The kernels are built without packed FP32, so one FMA per
 # lane and cycle, 78.6 TFLOP/s, is the ceiling they can reach.
 REACHABLE_FP32_TFLOPS = 78.6
-
-# HBM bytes per launch of the dominant kernel, from the FETCH_SIZE / WRITE_SIZE
-# counter runs recorded in this file (each scaled by the same counter's reading
-# for a copy kernel of known size), valid only while the kernel's sources
-# hash to the value recorded beside it.
-COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "main_kernel_c2_hbm_counters.md")
-VALU_SUMMARY = os.path.join(ROOT, "profiles", "main_kernel_c2_valu_counters.md")
 SIMDS, CLOCK_GHZ = 1024, 2.4
-# The per-stage-minimum kernel's own sources: its code and instantiation, the
-# launch-shape choice, the build flags.
-KERNEL_SOURCES = [os.path.join("paper_2607_04310_amd", "csrc", f) for f in (
-    "psdf_device.hpp", "psdf_kernels.hpp", "psdf_winner.hpp", "psdf_inst_mf6.hip",
-    "psdf_host.cpp", "psdf_host.hpp")] + [os.path.join("paper_2607_04310_amd", "build.py")]
+
+CSRC = os.path.join("paper_2607_04310_amd", "csrc")
+# each kernel's own sources (code, instantiation, launch choice, build flags)
+KERNELS = {
+    "batch_kernel": dict(
+        sources=[os.path.join(CSRC, f) for f in (
+            "psdf_device.hpp", "psdf_winner.hpp", "psdf_batch.hpp", "psdf_batch_mf6.hip",
+            "psdf_batch.hip", "psdf_host.cpp", "psdf_host.hpp")]
+        + [os.path.join("paper_2607_04310_amd", "build.py")],
+        valu=os.path.join(ROOT, "profiles", "batch_kernel_c5_valu_counters.md"),
+        hbm=os.path.join(ROOT, "profiles", "batch_kernel_c5_hbm_counters.md")),
+    "main_kernel": dict(
+        sources=[os.path.join(CSRC, f) for f in (
+            "psdf_device.hpp", "psdf_kernels.hpp", "psdf_winner.hpp", "psdf_inst_mf6.hip",
+            "psdf_host.cpp", "psdf_host.hpp")]
+        + [os.path.join("paper_2607_04310_amd", "build.py")],
+        valu=os.path.join(ROOT, "profiles", "main_kernel_c2_valu_counters.md"),
+        hbm=os.path.join(ROOT, "profiles", "main_kernel_c2_hbm_counters.md")),
+}
 
 
-def kernel_source_hash():
-    import hashlib
+def source_hash(kernel):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNELS[kernel]["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def counted_valu_insts():
-    """VALU wave-instructions per launch from the VALU counter summary, or
-    None when it is missing or the kernel has changed since."""
-    import re
+def counted(kernel, what, field):
+    """A figure recorded in a counter summary, or (None, why not) when the
+    summary is missing or the kernel has changed since it was taken."""
     try:
-        text = open(VALU_SUMMARY).read()
-    except OSError:
-        return None
-    mh = re.search(r"source_sha256:\s*([0-9a-f]+)", text)
-    mv = re.search(r"valu_insts_per_launch:\s*([0-9.eE+]+)", text)
-    if not mh or not mv or mh.group(1) != kernel_source_hash():
-        return None
-    return float(mv.group(1))
-
-
-def counted_traffic():
-    """(bytes per launch, note) from the counter summary, or (None, why not)."""
-    import re
-    try:
-        text = open(COUNTER_SUMMARY).read()
+        text = open(KERNELS[kernel][what]).read()
     except OSError:
         return None, "no counter summary"
     mh = re.search(r"source_sha256:\s*([0-9a-f]+)", text)
-    mb = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not mh or not mb:
+    mv = re.search(field + r":\s*([0-9.eE+]+)", text)
+    if not mh or not mv:
         return None, "counter summary incomplete"
-    if mh.group(1) != kernel_source_hash():
+    if mh.group(1) != source_hash(kernel):
         return None, "kernel changed since the counters were taken"
-    return float(mb.group(1)), "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
-
-
-def parse():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="bound on the CPU-oracle sample (0 disables it)")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--counters", action="store_true",
-                    help="only launch the c2 psdf_grad call `steps` times and a 256 MiB "
-                         "device copy (the calibration of the HBM byte counters)")
-    ap.add_argument("--extras", type=int, default=1,
-                    help="also measure the uneven batch (c4) and the screened path (c5)")
-    return ap.parse_args()
-
-
-def cpu_baseline(inst, seconds):
-    """The FP64 oracle (value, winner, gradient) on all host cores, repeated on
-    the same workload until `seconds` of wall time have passed."""
-    import oracle
-    oracle.psdf(inst.footprint, inst.poses[:1], inst.edges, inst.obst_off)   # load / warm
-    done, reps, used = 0.0, 0, 0
-    t0 = time.perf_counter()
-    while True:
-        r = oracle.psdf(inst.footprint, inst.poses, inst.edges, inst.obst_off)
-        used = r["threads"]
-        reps += 1
-        done = time.perf_counter() - t0
-        if done >= seconds:
-            break
-    value = reps * inst.N * inst.E / done
-    return dict(value=value, unit="stage×edge evals/s", cores=int(used), kind="oracle",
-                sample=f"{reps} full c2 evaluations (N={inst.N}, E={inst.E}, value+winner+gradient, "
-                       f"FP64) in {done:.1f} s")
+    return float(mv.group(1)), "rocprofv3 counters"
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def _timeit(torch, fn, reps, warm, blocks=1):
-    """Mean ms per call over `reps` calls after `warm` untimed ones; with
-    blocks > 1, the median over that many such timed blocks."""
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=24.0,
+                    help="bound on the CPU-oracle sample (0 disables it)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--counters", choices=["", "c5", "c2"], default="",
+                    help="only launch the workload's dominant call `steps` times (eagerly) and a "
+                         "256 MiB device copy (the calibration of the HBM byte counters)")
+    ap.add_argument("--extras", type=int, default=1, help="also measure the secondary workloads")
+    ap.add_argument("--screened", type=int, default=1, help="also measure the screened forms")
+    return ap.parse_args()
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def timed_calls(torch, fn, reps, warm):
+    """Mean ms per call of `reps` calls between one event pair, after `warm`."""
     for _ in range(warm):
         fn()
     torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    times = []
-    for _ in range(blocks):
-        a.record()
+    a, b = _events(torch)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def graph_calls(torch, fn, reps, outs):
+    """Mean ms per call of `reps` calls captured into one HIP graph (outside
+    the timed region) and replayed once between an event pair, after an
+    untimed replay whose outputs must equal the eager call's bit for bit."""
+    fn()
+    torch.cuda.synchronize()
+    ref = [x.clone() for x in outs]
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cap):
         for _ in range(reps):
             fn()
-        b.record()
-        torch.cuda.synchronize()
-        times.append(a.elapsed_time(b) / reps)
-    return sorted(times)[len(times) // 2]
+    for x in outs:
+        x.zero_()
+    g.replay()
+    torch.cuda.synchronize()
+    for x, y in zip(outs, ref):
+        if not (torch.equal(x, y) or torch.equal(torch.nan_to_num(x, 7.0), torch.nan_to_num(y, 7.0))):
+            raise RuntimeError("graph replay differs from the eager call")
+    a, b = _events(torch)
+    a.record()
+    g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    del g
+    return a.elapsed_time(b) / reps
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(c5, seconds):
+    """The FP64 oracle (value, winner, gradient) timed on this host: all cores
+    on whole c5 instances, repeated until half the budget is spent, then one
+    core on the first 4 stages of instance 0, for the other half."""
+    import oracle
+    oracle.use_native_build()
+    inst = c5[0]
+    oracle.psdf(inst.footprint, inst.poses[:1], inst.edges, inst.obst_off)   # load / warm
+    t0 = time.perf_counter()
+    pairs, k, used = 0, 0, 0
+    while True:
+        i = c5[k % len(c5)]
+        r = oracle.psdf(i.footprint, i.poses, i.edges, i.obst_off)
+        used = r["threads"]
+        pairs += i.N * i.E
+        k += 1
+        done = time.perf_counter() - t0
+        if done >= seconds / 2:
+            break
+    t1 = time.perf_counter()
+    p1, k1 = 0, 0
+    while True:
+        r = oracle.psdf(inst.footprint, inst.poses[:4], inst.edges, inst.obst_off, nthreads=1)
+        p1 += 4 * inst.E
+        k1 += 1
+        done1 = time.perf_counter() - t1
+        if done1 >= seconds / 2:
+            break
+    return dict(value=pairs / done, unit="stage×edge evals/s", cores=int(used), kind="oracle",
+                sample=f"{k} whole c5 instances (N={inst.N}, E={inst.E}, value+winner+gradient, "
+                       f"FP64) in {done:.1f} s on {used} threads",
+                one_core_value=p1 / done1,
+                one_core_sample=f"{k1} x the first 4 stages of c5 instance 0 in {done1:.1f} s",
+                cpu_model=cpu_model(), nproc=os.cpu_count(),
+                build="g++ -O3 -march=native -ffp-contract=off -fopenmp")
 
 
 def extras(torch, api, flops, inputs):
-    """Secondary lines: the uneven batch (c4: persistent graph vs the
-    per-instance loop), c2 at throughput size (256 draws in one batch), one
-    pose against growing edge sets, the latency of the paper's Table I query
-    shapes, and certified screening (c5: plain batch vs screened with the
-    trained MLP and with distance ranking)."""
-    from paper_2607_04310_amd import screener
+    """c2 latency with its kernel's roofline, c2 x 256, the uneven batch c4
+    against its per-instance loop, one pose against growing edge sets, and
+    the Table I query shapes."""
+    from paper_2607_04310_amd import _lib
     out = {}
+    inst = inputs.c2(0)
+    es = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar, device="cuda")
+    poses = torch.tensor(inst.poses, device="cuda")
+    ws = api.workspace(inst.N, inst.M, "cuda")
+    o = api.psdf_grad(inst.footprint, poses, es, ws=ws)
+
+    def c2_step():
+        api.psdf_grad(inst.footprint, poses, es, out=o, ws=ws)
+    t_graph = graph_calls(torch, c2_step, 200, list(o))
+    t_eager = timed_calls(torch, c2_step, 200, 20)
+    kms = api.time_stage_min(inst.footprint, poses, es, 200, ws=ws)
+    fl = flops.flops_instance(len(inst.footprint), inst.N, inst.edges, inst.obst_off)
+    valu, _ = counted("main_kernel", "valu", "valu_insts_per_launch")
+    out["c2_latency"] = dict(
+        workload="c2: hexagon (m=6), N=50 path poses, E=16384 (4096 rectangles, 40x40 m), psdf_grad",
+        us_per_call=t_graph * 1e3, eager_us_per_call=t_eager * 1e3,
+        evals_per_s=inst.N * inst.E / (t_graph * 1e-3),
+        main_kernel_us=kms * 1e3, main_kernel_tflops=fl / (kms * 1e-3) / 1e12,
+        main_kernel_frac=fl / (kms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+        main_kernel_valu_busy=None if valu is None else valu * 4 / (SIMDS * kms * 1e-3 * CLOCK_GHZ * 1e9))
+    log(f"c2: {t_graph * 1e3:.2f} us per call (graph), {t_eager * 1e3:.2f} eager, main kernel "
+        f"{kms * 1e3:.2f} us")
+    del es, poses, ws, o
+
     log("c4: building 512 instances")
     c4 = inputs.c4(512)
     pairs4 = sum(i.N * i.E for i in c4)
     b = api.Batch(c4, graph=True, autotune=True)
     b.autotune()
-    log(f"c4: autotuned {b.info()}")
-    t_batch = _timeit(torch, b.run, 20, 3)
+    t_batch = timed_calls(torch, b.run, 20, 3)
     views = [b.instance_views(k) for k in range(b.n_inst)]
 
     def loop():
-        for fp, poses, es in views:
-            api.psdf_grad(fp, poses, es)
-    t_loop = _timeit(torch, loop, 3, 1)
+        for fp, ps, e in views:
+            api.psdf_grad(fp, ps, e)
+    t_loop = timed_calls(torch, loop, 3, 1)
     f4 = sum(flops.flops_instance(len(i.footprint), i.N, i.edges, i.obst_off) for i in c4)
     out["c4_batch"] = dict(pairs=pairs4, batch_ms=t_batch, loop_ms=t_loop,
                            batch_evals_per_s=pairs4 / (t_batch * 1e-3),
                            loop_evals_per_s=pairs4 / (t_loop * 1e-3),
                            batch_tflops=f4 / (t_batch * 1e-3) / 1e12, shape=b.info())
+    log(f"c4: batch {t_batch:.3f} ms, loop {t_loop:.3f} ms")
     b.close()
+    del c4, views
 
-    # c2 at throughput size: 256 independent c2 draws in one batch launch
-    log("c2x256: building")
     c2b = inputs.c2_batch(256)
     pairs2 = sum(i.N * i.E for i in c2b)
     b = api.Batch(c2b, graph=True, autotune=True)
     b.autotune()
-    t = _timeit(torch, b.run, 20, 3)
+    t = timed_calls(torch, b.run, 20, 3)
     f2 = sum(flops.flops_instance(len(i.footprint), i.N, i.edges, i.obst_off) for i in c2b)
     out["c2x256_batch"] = dict(pairs=pairs2, ms=t, evals_per_s=pairs2 / (t * 1e-3),
                                tflops=f2 / (t * 1e-3) / 1e12, shape=b.info())
-    log(f"c2x256: {t:.3f} ms, {pairs2 / (t * 1e-3):.3e} evals/s")
+    log(f"c2x256: {t:.3f} ms")
     b.close()
     del c2b
 
-    # one stage pose against growing edge sets: every edge is read once per
-    # call, the HBM end of the workload
     sweep = []
     for rects in (1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22):
         inst = inputs.single_pose(rects)
@@ -194,19 +281,14 @@ def extras(torch, api, flops, inputs):
         poses = torch.tensor(inst.poses, device="cuda")
         ws = api.workspace(1, inst.M, "cuda")
         o = api.psdf_grad(inst.footprint, poses, es, ws=ws)
-        t = _timeit(torch, lambda: api.psdf_grad(inst.footprint, poses, es, out=o, ws=ws), 20, 3)
+        t = timed_calls(torch, lambda: api.psdf_grad(inst.footprint, poses, es, out=o, ws=ws), 20, 3)
         nbytes = flops.bytes_instance(1, inst.E, inst.M)
-        fl = flops.flops_instance(len(inst.footprint), 1, inst.edges, inst.obst_off)
         sweep.append(dict(E=inst.E, ms=t, evals_per_s=inst.E / (t * 1e-3),
-                          gbytes_per_s=nbytes / (t * 1e-3) / 1e9, tflops=fl / (t * 1e-3) / 1e12))
-        log(f"single pose E={inst.E}: {t * 1e3:.1f} us, {nbytes / (t * 1e-3) / 1e9:.0f} GB/s")
+                          gbytes_per_s=nbytes / (t * 1e-3) / 1e9))
         del es, poses, ws, o
     out["single_pose_sweep"] = sweep
+    log("single pose: " + ", ".join(f"E={r['E']}: {r['gbytes_per_s']:.0f} GB/s" for r in sweep))
 
-    # the query shapes of the paper's Table I: latency of one value call
-    # (psdf_eval) and one value + gradient call (psdf_grad) for B poses
-    # against M obstacles, eager from Python as a per-query caller issues
-    # them, and the value + gradient call replayed from a HIP graph
     table = []
     for M in (1, 10, 100):
         for B in (1, 10, 100):
@@ -215,54 +297,50 @@ def extras(torch, api, flops, inputs):
             poses = torch.tensor(inst.poses, device="cuda")
             ws = api.workspace(B, M, "cuda")
             o = api.psdf_grad(inst.footprint, poses, es, ws=ws)
-            t_fwd = _timeit(torch, lambda: api.psdf_eval(inst.footprint, poses, es, ws=ws), 200, 20)
-            t_grad = _timeit(torch, lambda: api.psdf_grad(inst.footprint, poses, es, out=o, ws=ws),
-                             200, 20)
-            cap = torch.cuda.Stream()
-            cap.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(cap):
-                api.psdf_grad(inst.footprint, poses, es, out=o, ws=ws)
-            torch.cuda.synchronize()
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=cap):
-                for _ in range(100):
-                    api.psdf_grad(inst.footprint, poses, es, out=o, ws=ws)
-            t_graph = _timeit(torch, g.replay, 5, 1) / 100
-            del g
+            t_fwd = timed_calls(torch, lambda: api.psdf_eval(inst.footprint, poses, es, ws=ws), 200, 20)
+            step = lambda: api.psdf_grad(inst.footprint, poses, es, out=o, ws=ws)  # noqa: E731
+            t_grad = timed_calls(torch, step, 200, 20)
+            t_g = graph_calls(torch, step, 100, list(o))
             table.append(dict(M=M, B=B, fwd_us=t_fwd * 1e3, grad_us=t_grad * 1e3,
-                              grad_graph_us=t_graph * 1e3))
+                              grad_graph_us=t_g * 1e3))
             del es, poses, ws, o
-    log("table I shapes: " + ", ".join(f"M={r['M']} B={r['B']}: {r['grad_us']:.1f} us"
-                                       for r in table))
     out["table_i_latency"] = table
-
-    # screener trained on held-out instances (different seeds from the test batch)
-    log("c5: training set")
-    X, T = screener.training_set(inputs.c5(10, cfg=6), near=1024, far=1024, seed=1)
-    log(f"c5: training on {X.shape[0]} pairs")
-    theta, hist = screener.train(X, T, epochs=12, batch=4096, lr=2e-3, seed=0, log=log)
-    c5 = inputs.c5(64)
-    pairs5 = sum(i.N * i.E for i in c5)
-    b = api.Batch(c5, graph=True)
-    # the first blocks of ten calls of this workload run up to 15 % slower
-    # than the later ones (measured: 0.73, 0.68, 0.65, 0.62, 0.62 ms), so
-    # these c5 lines warm up for 30 calls and report the median of five blocks
-    t_plain = _timeit(torch, b.run, 10, 30, blocks=5)
-    res = dict(pairs=pairs5, train_pairs=int(X.shape[0]), train_loss=hist[-1], plain_ms=t_plain,
-               plain_evals_per_s=pairs5 / (t_plain * 1e-3))
-    ref = [x.clone() for x in (b.d, b.keys)]
-    for name, th in (("mlp", theta), ("distance", None)):
-        log(f"c5: screened, {name} ranking")
-        t = _timeit(torch, lambda: b.screened(th, pool=128, topk=256), 10, 30, blocks=5)
-        (d, _, _, _, keys), (cand, cert, ck) = b.screened(th, pool=128, topk=256, stats=True)
-        torch.cuda.synchronize()
-        exact = bool(torch.equal(keys, ref[1]))
-        res[name] = dict(ms=t, evals_per_s=pairs5 / (t * 1e-3), exact=exact,
-                         certified=float(cert.float().mean()), mean_candidates=float(cand.float().mean()),
-                         winner_recall=float((ck == keys).float().mean()))
-    out["c5_screen"] = res
-    b.close()
+    log("table I: " + ", ".join(f"{r['M']}x{r['B']}: {r['grad_graph_us']:.1f} us" for r in table))
     return out
+
+
+def screened_forms(torch, api, inputs, c5, b, ref, steps):
+    """The certified screened forms on the c5 batch: each timed as `steps`
+    calls in one HIP graph replay, its outputs equal to the plain batch's."""
+    from paper_2607_04310_amd import screener
+    log("c5: training the screener on held-out instances")
+    X, T = screener.training_set(inputs.c5(10, cfg=6), near=1024, far=1024, seed=1)
+    theta, hist = screener.train(X, T, epochs=12, batch=4096, lr=2e-3, seed=0, log=log)
+    pairs = sum(i.N * i.E for i in c5)
+    forms = {"bound": lambda: b.screened_bound(),
+             "distance": lambda: b.screened(None, pool=128, topk=256),
+             "trained_mlp": lambda: b.screened(theta, pool=128, topk=256)}
+    res = dict(train_pairs=int(X.shape[0]), train_loss=hist[-1])
+    outs = [b.d, b.edge, b.obst, b.grad, b.keys]
+    for name, fn in forms.items():
+        ms = graph_calls(torch, fn, steps, outs)
+        if name == "bound":
+            _, (cand, cert, ck) = b.screened_bound(stats=True)
+        else:
+            _, (cand, cert, ck) = b.screened(None if name == "distance" else theta, pool=128,
+                                             topk=256, stats=True)
+        torch.cuda.synchronize()
+        exact = all(torch.equal(x, y) or torch.equal(torch.nan_to_num(x, 7.0), torch.nan_to_num(y, 7.0))
+                    for x, y in zip(outs, ref))
+        if not exact:
+            raise RuntimeError(f"screened ({name}) outputs differ from the plain batch")
+        res[name] = dict(ms=ms, evals_per_s=pairs / (ms * 1e-3), exact=exact,
+                         certified=float(cert.float().mean()),
+                         exact_evals_per_stage=float(cand.float().mean()),
+                         winner_recall=float((ck == b.keys).float().mean()))
+        log(f"c5 screened {name}: {ms:.4f} ms, certified {res[name]['certified']:.4f}, "
+            f"{res[name]['exact_evals_per_stage']:.1f} exact per stage")
+    return res
 
 
 def main():
@@ -274,124 +352,108 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2607_04310_amd import _lib, api, flops, inputs
 
-    dev = torch.device("cuda:0")
-    inst = inputs.c2(0)
-    edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar, device=dev)
-    poses = torch.tensor(inst.poses, device=dev)
-    N, E, M = inst.N, inst.E, inst.M
-    out = (torch.empty(N, device=dev), torch.empty(N, dtype=torch.int32, device=dev),
-           torch.empty(N, dtype=torch.int32, device=dev), torch.empty((N, 3), device=dev),
-           torch.empty(N, dtype=torch.int64, device=dev))
-    params = api.Params()
-    ws = api.workspace(N, M, dev)
-
-    def step():
-        api.psdf_grad(inst.footprint, poses, edges, params, out=out, ws=ws)
-
-    if args.counters:
-        src = torch.ones(64 << 20, device=dev)
-        dst = torch.empty_like(src)
+    if args.counters == "c2":
+        inst = inputs.c2(0)
+        es = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar, device="cuda")
+        poses = torch.tensor(inst.poses, device="cuda")
+        ws = api.workspace(inst.N, inst.M, "cuda")
         for _ in range(args.steps):
-            step()
+            api.psdf_grad(inst.footprint, poses, es, ws=ws)
+    log("c5: building 64 instances")
+    c5 = inputs.c5(64)
+    pairs = sum(i.N * i.E for i in c5)
+    if args.counters:
+        if args.counters == "c5":
+            b = api.Batch(c5, graph=False)
+            for _ in range(args.steps):
+                b.run()
+            b.close()
+        src = torch.ones(64 << 20, device="cuda")
+        dst = torch.empty_like(src)
         for _ in range(4):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps(dict(counters_run=True, steps=args.steps, copy_bytes=src.numel() * 4)))
+        print(json.dumps(dict(counters_run=args.counters, steps=args.steps,
+                              copy_bytes=src.numel() * 4)))
         return
 
+    bg = api.Batch(c5, graph=True)       # replays the plan's own HIP graph
+    be = api.Batch(c5, graph=False)      # eager launches (kernel timing, screened forms)
+    if bg.info() != be.info():
+        raise RuntimeError("the two plans of the same batch chose different launch shapes")
+    be.run()
+    torch.cuda.synchronize()
+    ref = [x.clone() for x in (be.d, be.edge, be.obst, be.grad, be.keys)]
     for _ in range(args.warmup):
-        step()
+        bg.run()
     torch.cuda.synchronize()
-    ref = [x.clone() for x in out]
+    got = [bg.d, bg.edge, bg.obst, bg.grad, bg.keys]
+    if not all(torch.equal(x, y) or torch.equal(torch.nan_to_num(x, 7.0), torch.nan_to_num(y, 7.0))
+               for x, y in zip(got, ref)):
+        raise RuntimeError("graph replay of psdf_batch differs from the eager call")
 
-    # Eager calls from Python, for reference: each call pays the binding's and
-    # the HIP runtime's host-side launch cost, which can exceed the GPU time
-    # of a call of this size.
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(args.steps):
-        step()
-    stop.record()
+    # timed region: K whole psdf_batch calls between one event pair
+    a, z = _events(torch)
     torch.cuda.synchronize()
-    eager_ms = start.elapsed_time(stop) / args.steps
-
-    # Timed region: the same K whole psdf_grad calls, captured once (outside
-    # the timed region) into a HIP graph and replayed once, as a launch-bound
-    # loop of small calls is run in deployment.  An untimed replay first, then
-    # a check that the replayed calls reproduce the eager outputs bit for bit.
-    cap = torch.cuda.Stream()
-    cap.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(cap):
-        step()
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph, stream=cap):
-        for _ in range(args.steps):
-            step()
-    for x in out:
-        x.zero_()
-    graph.replay()
-    torch.cuda.synchronize()
-    if not all(torch.equal(a, b) for a, b in zip(out, ref)):
-        raise RuntimeError("graph replay of psdf_grad differs from the eager call")
     t0 = time.perf_counter()
-    start.record()
-    graph.replay()
-    stop.record()
+    a.record()
+    for _ in range(args.steps):
+        bg.run()
+    z.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_step = start.elapsed_time(stop) / args.steps
-    del graph
+    ms_step = a.elapsed_time(z) / args.steps
+    value = pairs / (ms_step * 1e-3)
+    log(f"c5 plain psdf_batch: {ms_step:.4f} ms per call, {value:.3e} evals/s")
 
-    # The dominant kernel alone: the same steps' per-stage-minimum launches
-    # with an event pair around each (dispatch overhead included), and
-    # back-to-back launches between one event pair on the launch stream.
+    # the persistent batch kernel alone: events recorded by each dispatch on
+    # its launch stream, over K eager calls
     _lib.timer_enable(args.steps)
     for _ in range(args.steps):
-        step()
+        be.run()
     torch.cuda.synchronize()
-    kms, launches = _lib.timer_read()
+    kms_total, launches = _lib.timer_read()
     _lib.timer_enable(0)
-    kernel_ms_bracketed = kms / max(1, launches)
-    kernel_ms = api.time_stage_min(inst.footprint, poses, edges, args.steps, params, ws=ws)
-
-    flop = flops.flops_instance(len(inst.footprint), N, inst.edges, inst.obst_off)
+    kernel_ms = kms_total / max(1, launches)
+    flop = sum(flops.flops_instance(len(i.footprint), i.N, i.edges, i.obst_off) for i in c5)
     achieved = flop / (kernel_ms * 1e-3) / 1e12
-    traffic, traffic_note = counted_traffic()
-    valu = counted_valu_insts()
-    valu_busy = None if valu is None else valu * 4 / (SIMDS * kernel_ms * 1e-3 * CLOCK_GHZ * 1e9)
-    value = N * E / (ms_step * 1e-3)
+    traffic, traffic_note = counted("batch_kernel", "hbm", "traffic_bytes_per_launch")
+    valu, _ = counted("batch_kernel", "valu", "valu_insts_per_launch")
+    info = be.info()
+    kname = f"batch_kernel<6, 4, {info['obstacles_per_tile'] // 64}>"
     res = dict(
         metric=METRIC, value=value, unit="stage×edge evals/s", n_gpus=1, steps=args.steps,
-        warmup=args.warmup, ms_per_step=ms_step, eager_ms_per_step=eager_ms,
-        eager_value=N * E / (eager_ms * 1e-3), timing="one HIP graph replay of the K calls",
-        higher_is_better=True, scaling="weak",
+        warmup=args.warmup, ms_per_step=ms_step, higher_is_better=True, scaling="weak",
         vs_baseline=None, dtype="f32", data="synthetic",
-        config=dict(workload="c2: hexagon footprint (m=6), N=50 path poses, E=16384 edges "
-                             "(4096 rectangles, 40x40 m), psdf_grad (value+winner+gradient)",
-                    N=N, E=E, M=M, m=len(inst.footprint), eta=params.eta),
+        timing="K psdf_batch calls (each a replay of the plan's HIP graph) between one event pair",
+        config=dict(workload="c5: 64 instances x N=50 path poses x E=65536 edges (16384 rectangles, "
+                             "32-component Gaussian mixture, sigma 2 m, 60x60 m), hexagon footprint "
+                             "(m=6), psdf_batch (value+winner+gradient)",
+                    instances=len(c5), N=50, E=65536, M=16384, m=6, eta=1000.0, pairs=pairs,
+                    launch_shape=info),
         roofline=dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                       frac=achieved / PEAK_FP32_TFLOPS,
-                      frac_of_unpacked=achieved / REACHABLE_FP32_TFLOPS, traffic=traffic,
-                      traffic_note=traffic_note,
-                      algorithmic_bytes=flops.bytes_instance(N, E, M),
-                      valu_busy=valu_busy, valu_insts_per_launch=valu,
-                      kernel="main_kernel (per-stage minimum)", kernel_us=kernel_ms * 1e3,
-                      kernel_us_event_bracketed=kernel_ms_bracketed * 1e3,
-                      flop_per_launch=flop, source_sha256=kernel_source_hash()),
+                      frac_of_unpacked=achieved / REACHABLE_FP32_TFLOPS,
+                      traffic=traffic, traffic_note=traffic_note,
+                      algorithmic_bytes=sum(flops.bytes_instance(i.N, i.E, i.M) for i in c5),
+                      valu_busy=None if valu is None else valu * 4 / (SIMDS * kernel_ms * 1e-3 * CLOCK_GHZ * 1e9),
+                      valu_insts_per_launch=valu, kernel=kname, kernel_us=kernel_ms * 1e3,
+                      kernel_launches_timed=launches, flop_per_launch=flop,
+                      source_sha256=source_hash("batch_kernel")),
         wall_s=wall,
     )
-    log(f"c2: {value:.3e} evals/s, {ms_step * 1e3:.2f} us per call (graph replay), "
-        f"{eager_ms * 1e3:.2f} us per eager call")
+    if args.screened:
+        res["screened"] = screened_forms(torch, api, inputs, c5, be, ref, args.steps)
+    bg.close()
+    be.close()
     if args.extras:
         res["extras"] = extras(torch, api, flops, inputs)
     if not args.no_cpu and args.cpu_seconds > 0:
-        res["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(c5, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 

@@ -328,6 +328,24 @@ int psdf_batch_screened(psdf_batch_plan* plan, const float* theta, int32_t pool,
                         int32_t* obst, float* grad, uint64_t* keys, int32_t* stage_cand,
                         int32_t* stage_cert, uint64_t* cand_keys, hipStream_t stream);
 
+/* Certified screened evaluation without a ranking (same outputs as
+ * psdf_batch, bit for bit).  Per stage, with the lower bounds LB_i of
+ * psdf_batch_screened: the obstacle with the smallest bound (the seed) is
+ * evaluated exactly; its sd bounds phi from above (phi is the minimum over
+ * obstacles, Sec. IV-D), so the bar T = max(sd_seed, tau) is at least
+ * max(phi, tau), and every obstacle with LB_i <= T is evaluated exactly.
+ * The obstacles left out then satisfy the certificate LB_i > max(phi_K,
+ * tau) by construction.  A stage still takes the full evaluation when more
+ * than 512 obstacles have LB_i <= T, when the bound of the obstacles outside
+ * its instance's horizon list is not above T, or when that list is unusable.
+ * Same assumptions, limits and optional outputs as psdf_batch_screened
+ * (stage_cand counts the seed). */
+int psdf_batch_screened_bound(psdf_batch_plan* plan, const float* poses, const float* ax,
+                              const float* ay, const float* bx, const float* by,
+                              const int32_t* obst_off, float* d, int32_t* edge, int32_t* obst,
+                              float* grad, uint64_t* keys, int32_t* stage_cand,
+                              int32_t* stage_cert, uint64_t* cand_keys, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Edge-screener MLP: 4 -> 64 -> 64 -> 1 with ReLU on per-(stage, edge)
  * features (the edge's endpoints in the robot frame, divided by 4 m).
@@ -374,10 +392,13 @@ int psdf_screen_labels(const psdf_batch_plan* plan, const float* poses, const fl
 int psdf_set_launch_shape(int32_t blk, int32_t sb);
 
 /* Kernel timer, an instrumentation aid for benchmarks.  With capacity > 0,
- * each launch of the dominant kernel of an entry point (the per-stage minimum
- * kernel of psdf_eval / psdf_grad, the persistent kernel or graph replay of
- * psdf_batch) is bracketed by a pair of HIP events recorded on the launch
- * stream, for up to `capacity` launches.
+ * each launch of the dominant kernel of an entry point is bracketed by a
+ * pair of HIP events recorded on its launch stream, for up to `capacity`
+ * launches: the per-stage minimum kernel of psdf_eval / psdf_grad and the
+ * persistent batch kernel of each footprint-size group of an eager
+ * psdf_batch call (events recorded by the dispatch itself), the graph
+ * replay of a graph psdf_batch call, the screening kernels of
+ * psdf_batch_screened / psdf_batch_screened_bound.
  * psdf_timer_read waits for those events, returns their summed duration in
  * milliseconds and the number of timed launches, and starts a new count.
  * capacity 0 turns the timer off and releases its events.  Not thread-safe

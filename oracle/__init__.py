@@ -28,19 +28,40 @@ DEFAULT_ETA = 1000.0
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with g++ (-O2, OpenMP) into ``oracle/liboracle.so``."""
+    """Compile the oracle with g++ (-O3, OpenMP) into ``oracle/liboracle.so``."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp]
+        cmd = ["g++", "-O3", "-ffp-contract=off", "-std=c++17", "-fopenmp", "-shared", "-fPIC",
+               _SRC, "-o", tmp]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def use_native_build(directory=None) -> str:
+    """Compile the oracle for the host it runs on (g++ -O3 -march=native,
+    OpenMP, no contraction of multiplies and adds) into ``directory`` (a
+    temporary directory by default) and load that build in place of
+    ``liboracle.so`` for the rest of the process: the CPU-baseline timing
+    uses it.  Same source, same arithmetic."""
+    global _lib, _LIB_PATH
+    import tempfile
+    directory = directory or tempfile.mkdtemp(prefix="psdf_oracle_")
+    path = os.path.join(directory, "liboracle_native.so")
+    cmd = ["g++", "-O3", "-march=native", "-ffp-contract=off", "-std=c++17", "-fopenmp",
+           "-shared", "-fPIC", _SRC, "-o", path]
+    subprocess.run(cmd, check=True)
+    _lib = None
+    _LIB_PATH = path
+    return path
 
 
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            if os.path.dirname(_LIB_PATH) != _HERE:
+                raise RuntimeError(f"{_LIB_PATH} is missing or older than {_SRC}")
             build()
         lib = ctypes.CDLL(_LIB_PATH)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -53,6 +74,16 @@ def _load():
         lib.oracle_obstacle.argtypes = [dp, ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_int,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         dp, ip, dp, dp, dp]
+        lib.oracle_obstacle_selections.restype = ctypes.c_int
+        lib.oracle_obstacle_selections.argtypes = [dp, ctypes.c_int, dp, dp, dp, dp, dp,
+                                                   ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                   ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                                   ctypes.c_int, ctypes.c_int, dp, dp, dp,
+                                                   ctypes.POINTER(ctypes.c_int64), ip]
+        lib.oracle_obstacle_axes.restype = ctypes.c_int
+        lib.oracle_obstacle_axes.argtypes = [dp, ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_int,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             dp, ip]
         lib.oracle_obstacle_geom_grad.restype = None
         lib.oracle_obstacle_geom_grad.argtypes = [dp, ctypes.c_int, dp, dp, dp, dp, dp,
                                                   ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -120,6 +151,80 @@ def obstacle(footprint, pose, edges, eps=DEFAULT_EPS, eps_sat=DEFAULT_EPS_SAT, e
                         mi, eps, eps_sat, eta, sdp, sepp, dsepp, poolp, gradp)
     return dict(sd=float(sd[0]), separated=bool(sep[0]), d_sep=float(dsep[0]),
                 edge_pool=pool[:mi].copy(), grad=grad.copy())
+
+
+def selection_grads(footprint, pose, edges, eps=DEFAULT_EPS, eps_sat=DEFAULT_EPS_SAT,
+                    eta=DEFAULT_ETA, tol=0.0, probe=-1, max_out=4096, samples=20000):
+    """Active-branch pose gradients of sd for one (pose, obstacle) (Sec. IV-D):
+    each min / max attained by several entries within ``tol`` and each ReLU
+    within ``tol`` of its kink takes one active branch; every combination of
+    the kinks that matter is visited up to 65536 of them, else ``samples``
+    random ones.  With probe = q >= 0 the quantity is axis q's term
+    max(delta(n_q), 0) instead of sd.  Returns dict(grads (k, 3) distinct
+    gradients, first (3,) the gradient with the first active entry at every
+    kink, mean (3,) the default-convention average (NaN when sampled),
+    combos, sampled)."""
+    lib = _load()
+    fp, fpp = _d(footprint)
+    ps, psp = _d(pose)
+    ed = np.ascontiguousarray(edges, dtype=np.float64).reshape(-1, 4)
+    mi = ed.shape[0]
+    cols = [_d(ed[:, k]) for k in range(4)]
+    out, outp = _d(np.zeros((max_out, 3)))
+    first, firstp = _d(np.zeros(3))
+    mean, meanp = _d(np.zeros(3))
+    combos = ctypes.c_int64(0)
+    sampled = ctypes.c_int32(0)
+    n = lib.oracle_obstacle_selections(fpp, fp.shape[0], psp, cols[0][1], cols[1][1], cols[2][1],
+                                       cols[3][1], mi, eps, eps_sat, eta, float(tol), int(probe),
+                                       max_out, int(samples), outp, firstp, meanp,
+                                       ctypes.byref(combos), ctypes.byref(sampled))
+    return dict(grads=out[:n].copy(), first=first.copy(), mean=mean.copy(),
+                combos=int(combos.value), sampled=bool(sampled.value))
+
+
+def branch_sets(footprint, pose, edges, eps=DEFAULT_EPS, eps_sat=DEFAULT_EPS_SAT, eta=DEFAULT_ETA,
+                tol=0.0):
+    """The structure of sd's active-branch gradients for one (pose,
+    obstacle), for the subgradient check of Sec. IV-D.
+
+    Separated (Sec. IV-C test): sd = d_sep and the gradients are
+    selection_grads of sd itself: terms = [(1.0, S)], mode "sum".
+    Penetration: sd = -depth.  With the soft-min, grad sd = -sum_q w_q
+    grad max(delta_q, 0), w = softmax(-eta max(delta, 0)), each axis's term
+    having its own active-branch set S_q: terms = [(-w_q, S_q)], mode "sum"
+    (every choice of one member per term).  With the hard minimum, grad sd
+    = -grad of one axis term attaining the minimum (within tol): terms =
+    [(-1, S_q)] over those axes, mode "union".  Axes with weight below 1e-16
+    are dropped."""
+    lib = _load()
+    fp, fpp = _d(footprint)
+    ps, psp = _d(pose)
+    ed = np.ascontiguousarray(edges, dtype=np.float64).reshape(-1, 4)
+    mi = ed.shape[0]
+    cols = [_d(ed[:, k]) for k in range(4)]
+    m = fp.shape[0]
+    dp_, dpp = _d(np.zeros(m + mi))
+    sep = ctypes.c_int32(0)
+    K = lib.oracle_obstacle_axes(fpp, m, psp, cols[0][1], cols[1][1], cols[2][1], cols[3][1], mi,
+                                 eps, eps_sat, eta, dpp, ctypes.byref(sep))
+    if sep.value:
+        return dict(separated=True, mode="sum",
+                    terms=[(1.0, selection_grads(footprint, pose, edges, eps, eps_sat, eta,
+                                                 tol=tol)["grads"])])
+    dplus = dp_[:K].copy()
+    hard = not (eta > 0) or np.isinf(eta)
+    mu = dplus.min()
+    if hard:
+        axes = np.flatnonzero(dplus <= mu + tol)
+        wts = {int(q): -1.0 for q in axes}
+    else:
+        e = np.exp(-eta * (dplus - mu))
+        w = e / e.sum()
+        wts = {int(q): -float(w[q]) for q in range(K) if w[q] > 1e-16}
+    terms = [(wq, selection_grads(footprint, pose, edges, eps, eps_sat, eta, tol=tol,
+                                  probe=q)["grads"]) for q, wq in wts.items()]
+    return dict(separated=False, mode="union" if hard else "sum", terms=terms, dplus=dplus)
 
 
 def geom_grad(footprint, pose, edges, eps=DEFAULT_EPS, eps_sat=DEFAULT_EPS_SAT, eta=DEFAULT_ETA):

@@ -76,9 +76,52 @@ inline double dcos(double a) { return std::cos(a); }
 inline double dsin(double a) { return std::sin(a); }
 inline double val(double a) { return a; }
 
+// Active-branch scan (test support for the subgradient check of Sec. IV-D).
+// While a scan is installed, every min / max whose extreme is attained by
+// several entries (within `tol` of it) and every ReLU whose argument lies
+// within `tol` of its kink passes on the tangent of ONE active branch,
+// picked by the scan's next digit, instead of the even split; the number of
+// active branches of each such kink and the weight the default convention
+// gives each (even split over bit-equal entries, ReLU'(0) = 0) are
+// recorded in evaluation order.  Which kinks occur, and their branch
+// counts, depend on the values only, never on the digits, so every run
+// meets the same kinks and all combinations can be visited.  Without a scan
+// (the default) nothing changes.
+struct TieScan {
+  double tol = 0.0;
+  std::vector<int> digit;                  // branch taken at each kink met so far
+  std::vector<int> count;                  // active branches of each kink
+  std::vector<std::vector<double>> weight; // each branch's weight in the default convention
+  size_t pos = 0;
+};
+thread_local TieScan* g_scan = nullptr;
+// With g_probe >= 0 the obstacle evaluation returns max(delta(n_q), 0) of
+// axis q = g_probe in place of sd (test support: the soft-min and the hard
+// minimum combine these per-axis terms).
+thread_local int g_probe = -1;
+
+int scan_choice(int n, const std::vector<double>& w) {
+  TieScan& t = *g_scan;
+  const size_t k = t.pos++;
+  if (t.count.size() <= k) {
+    t.count.push_back(n);
+    t.weight.push_back(w);
+  }
+  return k < t.digit.size() ? t.digit[k] % n : 0;
+}
+
 // ReLU with ReLU'(0) = 0; NaN propagates (as in a tensor ReLU).
 inline double relu(double a) { return (a > 0 || a != a) ? a : 0.0; }
-inline Dual relu(const Dual& a) { return (a.v > 0 || a.v != a.v) ? a : Dual(0.0); }
+inline Dual relu(const Dual& a) {
+  if (a.v != a.v) return a;
+  if (g_scan && std::fabs(a.v) <= g_scan->tol) {   // kink: the zero branch or the identity
+    Dual r(a.v > 0 ? a.v : 0.0);
+    if (scan_choice(2, {a.v > 0 ? 0.0 : 1.0, a.v > 0 ? 1.0 : 0.0}) == 1)
+      for (int k = 0; k < 3; ++k) r.g[k] = a.g[k];
+    return r;
+  }
+  return a.v > 0 ? a : Dual(0.0);
+}
 
 // Min / max over a list: the value is the extreme; the tangent is the mean of
 // the tangents of all bit-equal extreme entries (even split at ties).  A NaN
@@ -104,6 +147,21 @@ Dual reduce_split(const std::vector<Dual>& xs, Cmp better) {
     if (better(x.v, m)) m = x.v;
   }
   Dual r(m);
+  if (g_scan) {   // one active entry, picked by the scan
+    std::vector<size_t> act;
+    std::vector<double> w;   // the even split's weight of each active entry
+    int n_eq = 0;
+    for (size_t i = 0; i < xs.size(); ++i)
+      if (xs[i].v == m || std::fabs(xs[i].v - m) <= g_scan->tol) {
+        act.push_back(i);
+        w.push_back(xs[i].v == m ? 1.0 : 0.0);
+        n_eq += xs[i].v == m;
+      }
+    for (double& x : w) x /= n_eq;
+    const size_t c = act.size() > 1 ? (size_t)scan_choice((int)act.size(), w) : 0;
+    for (int k = 0; k < 3; ++k) r.g[k] = xs[act[c]].g[k];
+    return r;
+  }
   int cnt = 0;
   for (const Dual& x : xs)
     if (x.v == m) { for (int k = 0; k < 3; ++k) r.g[k] += x.g[k]; ++cnt; }
@@ -255,6 +313,10 @@ ObstacleEval<T> eval_obstacle_geo(const std::vector<P2<T>>& V0, const T& px, con
   // Smooth penetration depth: -(1/eta) log sum exp(-eta * max(delta, 0)).
   std::vector<T> dplus;
   for (const T& dl : delta) dplus.push_back(relu(dl));
+  if (g_probe >= 0) {   // test support: one axis's term alone
+    out.sd = g_probe < (int)dplus.size() ? dplus[g_probe] : T(std::nan(""));
+    return out;
+  }
   T pen;
   const bool hard = !(prm.eta > 0) || std::isinf(prm.eta);
   if (hard) {
@@ -392,6 +454,141 @@ void oracle_obstacle(const double* fp_xy, int m, const double* pose, const doubl
   *d_sep = ev.d_sep.v;
   for (int j = 0; j < mi; ++j) edge_pool[j] = ev.edge_pool[j];
   for (int k = 0; k < 3; ++k) grad[k] = ev.sd.g[k];
+}
+
+// Active-branch (selection) gradients of sd for one (stage, obstacle): the
+// pose gradient obtained when each kink of the pipeline (a min / max
+// attained by several entries within `tol`, a ReLU argument within `tol` of
+// zero) takes one of its active branches (Sec. IV-D: any active branch
+// gives a valid subgradient).  Kinks whose branch never changes the
+// gradient (those in a part of the pipeline that sd does not use) are found
+// by flipping each kink's branch at the first-branch combination and at 64
+// pseudo-random ones, and are held at their first branch.  With probe = q
+// >= 0 the enumerated quantity is axis q's term max(delta(n_q), 0) instead
+// of sd (the penetration branch combines these terms).  Up to 65536
+// combinations of the remaining kinks are all visited; beyond that,
+// `samples` pseudo-random combinations are.  The distinct gradients (up to
+// 1e-12 relative) go to out[k][3], at most max_out of them.  first[3]
+// receives the gradient with the first active entry at every kink (in the
+// pipeline's index order).  mean[3] receives the average over a complete
+// enumeration weighted as the default convention weighs the branches (even
+// split over bit-equal entries, ReLU'(0) = 0), which for tol = 0 is the
+// gradient of oracle_obstacle (NaN when sampled).  *combos gets the number
+// of combinations of the live kinks (capped at 2^62), *sampled 1 if they
+// were sampled.  Returns the number of distinct gradients.
+int oracle_obstacle_selections(const double* fp_xy, int m, const double* pose, const double* ax,
+                               const double* ay, const double* bx, const double* by, int mi,
+                               double eps, double eps_sat, double eta, double tol, int probe,
+                               int max_out, int samples, double* out, double* first,
+                               double* mean, int64_t* combos, int32_t* sampled) {
+  Footprint F = make_footprint(fp_xy, m);
+  g_probe = probe;
+  Params prm{eps, eps_sat, eta};
+  Dual px(pose[0]), py(pose[1]), th(pose[2]);
+  px.g[0] = 1; py.g[1] = 1; th.g[2] = 1;
+  TieScan scan;
+  scan.tol = tol;
+  g_scan = &scan;
+  auto run = [&](const std::vector<int>& digit, double g[3]) {
+    scan.digit = digit;
+    scan.pos = 0;
+    ObstacleEval<Dual> ev = eval_obstacle<Dual>(F, px, py, th, ax, ay, bx, by, mi, prm);
+    for (int k = 0; k < 3; ++k) g[k] = ev.sd.g[k];
+  };
+  auto same = [](const double* a, const double* b) {
+    double diff = 0, scale = 1;
+    for (int k = 0; k < 3; ++k) {
+      diff = std::max(diff, std::fabs(a[k] - b[k]));
+      scale = std::max(scale, std::fabs(b[k]));
+    }
+    return diff <= 1e-12 * scale || (a[0] != a[0] && b[0] != b[0]);
+  };
+  uint64_t lcg = 0x9e3779b97f4a7c15ull;
+  auto next = [&](uint64_t n) {
+    lcg = lcg * 6364136223846793005ull + 1442695040888963407ull;
+    return (int)((lcg >> 33) % n);
+  };
+  run({}, first);   // meets every kink and records its branches
+  const std::vector<int> count = scan.count;
+  const std::vector<std::vector<double>> weight = scan.weight;
+  const size_t nk = count.size();
+  std::vector<char> live(nk, 0);
+  for (int trial = 0; trial <= 64; ++trial) {
+    std::vector<int> base(nk, 0);
+    if (trial > 0)
+      for (size_t k = 0; k < nk; ++k) base[k] = next((uint64_t)count[k]);
+    double gb[3];
+    run(base, gb);
+    for (size_t k = 0; k < nk; ++k) {
+      if (live[k] || count[k] < 2) continue;
+      for (int c = 0; c < count[k] && !live[k]; ++c) {
+        if (c == base[k]) continue;
+        std::vector<int> alt = base;
+        alt[k] = c;
+        double ga[3];
+        run(alt, ga);
+        if (!same(ga, gb)) live[k] = 1;
+      }
+    }
+  }
+  std::vector<size_t> idx;
+  int64_t total = 1;
+  for (size_t k = 0; k < nk; ++k)
+    if (live[k]) {
+      idx.push_back(k);
+      total = total > ((int64_t)1 << 62) / count[k] ? ((int64_t)1 << 62) : total * count[k];
+    }
+  *combos = total;
+  const bool full = total <= 65536;
+  *sampled = full ? 0 : 1;
+  const int64_t visits = full ? total : std::max(1, samples);
+  std::vector<int> digit(nk, 0);
+  double acc[3] = {0, 0, 0};
+  int n = 0;
+  for (int64_t it = 0; it < visits; ++it) {
+    if (!full && it > 0)
+      for (size_t k : idx) digit[k] = next((uint64_t)count[k]);
+    double g[3];
+    run(digit, g);
+    double wgt = 1.0;
+    for (size_t k : idx) wgt *= weight[k][digit[k]];
+    for (int k = 0; k < 3; ++k) acc[k] += wgt == 0.0 ? 0.0 : wgt * g[k];
+    bool seen = false;
+    for (int q = 0; q < n && !seen; ++q) seen = same(g, out + 3 * q);
+    if (!seen && n < max_out) {
+      for (int k = 0; k < 3; ++k) out[3 * n + k] = g[k];
+      ++n;
+    }
+    if (full)
+      for (size_t d : idx) {   // next combination of the live kinks (odometer)
+        if (++digit[d] < count[d]) break;
+        digit[d] = 0;
+      }
+  }
+  g_scan = nullptr;
+  g_probe = -1;
+  for (int k = 0; k < 3; ++k) mean[k] = full ? acc[k] : std::nan("");
+  return n;
+}
+
+// The penetration branch's per-axis terms of one (stage, obstacle): K = m +
+// mi values max(delta(n_q), 0) in the pipeline's axis order (robot normals,
+// then obstacle normals) to dplus[K], and the separated flag.  Returns K.
+int oracle_obstacle_axes(const double* fp_xy, int m, const double* pose, const double* ax,
+                         const double* ay, const double* bx, const double* by, int mi,
+                         double eps, double eps_sat, double eta, double* dplus,
+                         int32_t* separated) {
+  Footprint F = make_footprint(fp_xy, m);
+  Params prm{eps, eps_sat, eta};
+  ObstacleEval<double> ev = eval_obstacle<double>(F, pose[0], pose[1], pose[2], ax, ay, bx, by,
+                                                  mi, prm);
+  *separated = ev.separated ? 1 : 0;
+  for (int q = 0; q < m + mi; ++q) {
+    g_probe = q;
+    dplus[q] = eval_obstacle<double>(F, pose[0], pose[1], pose[2], ax, ay, bx, by, mi, prm).sd;
+  }
+  g_probe = -1;
+  return m + mi;
 }
 
 // d sd / d(geometry) for one (stage, obstacle), by forward mode over every

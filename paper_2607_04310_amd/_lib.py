@@ -73,6 +73,7 @@ _SIGS = {
     "psdf_batch": (ctypes.c_int, [_VP] + [_VP] * 11 + [_VP]),
     "psdf_batch_autotune": (ctypes.c_int, [_VP] + [_VP] * 11 + [_VP, ctypes.POINTER(ctypes.c_float)]),
     "psdf_batch_screened": (ctypes.c_int, [_VP, _VP, _I32, _I32] + [_VP] * 11 + [_VP] * 3 + [_VP]),
+    "psdf_batch_screened_bound": (ctypes.c_int, [_VP] + [_VP] * 11 + [_VP] * 3 + [_VP]),
     "psdf_screen_labels": (ctypes.c_int, [_VP] + [_VP] * 5 + [_VP, _VP, _I32, _VP, _VP, _VP]),
     "psdf_mlp_forward": (ctypes.c_int, [_VP, _VP, _I32, _VP, _VP]),
     "psdf_mlp_ws_bytes": (ctypes.c_size_t, [_I32]),

@@ -355,6 +355,23 @@ class Batch:
         out = (self.d, self.edge, self.obst, self.grad, self.keys)
         return (out, (cand, cert, ck)) if stats else out
 
+    def screened_bound(self, stats=False):
+        """Certified screened evaluation without a ranking
+        (psdf_batch_screened_bound): the lowest-bound obstacle's exact sd sets
+        the bar; with stats=True also returns (stage_cand, stage_cert,
+        cand_keys)."""
+        S = int(self.poses.shape[0])
+        dev = self.poses.device
+        cand = torch.empty(S, dtype=torch.int32, device=dev) if stats else None
+        cert = torch.empty(S, dtype=torch.int32, device=dev) if stats else None
+        ck = torch.empty(S, dtype=torch.int64, device=dev) if stats else None
+        _lib.check(_lib.lib().psdf_batch_screened_bound(
+            self.plan, *self._args(), cand.data_ptr() if stats else None,
+            cert.data_ptr() if stats else None, ck.data_ptr() if stats else None,
+            _lib.stream_handle()))
+        out = (self.d, self.edge, self.obst, self.grad, self.keys)
+        return (out, (cand, cert, ck)) if stats else out
+
     def labels(self, stage, edge):
         """Features (n, 4) and exact pool-distance labels (n,) of (stage row,
         local edge) pairs (psdf_screen_labels)."""

@@ -22,8 +22,11 @@ namespace psdf {
 // instance, from its edges in one pass, r inflated to cover rounding.  An
 // empty obstacle gets cx = NaN (never screened); an invalid one (bad range,
 // more than MI edges or a non-finite coordinate) r = +inf (always a
-// candidate).  All MI edge loads are issued together (indices clamped into
-// the obstacle's range); edges past the obstacle's own count add nothing.
+// candidate), and so does an open chain of two or more edges: the axis test
+// sees the convex hull of its points, whose closing edge gives no axis, so
+// the certificate's separation argument does not hold for it.  All MI edge
+// loads are issued together (indices clamped into the obstacle's range);
+// edges past the obstacle's own count add nothing.
 template <int MI>
 __device__ float4 obstacle_circle(const BatchInst& in, const float* __restrict__ ax,
                                   const float* __restrict__ ay, const float* __restrict__ bx,
@@ -51,7 +54,20 @@ __device__ float4 obstacle_circle(const BatchInst& in, const float* __restrict__
                    isfinite(px[2 * j + 1]) && isfinite(py[2 * j + 1]);
         }
       }
-      if (finite) {
+      // closed polygon: B_j == A_{j+1} bitwise, around the boundary
+      bool closed = mi >= 3;
+#pragma unroll
+      for (int j = 0; j < MI; ++j)
+        if (j < mi) {
+          const int nx = j + 1 < mi ? j + 1 : 0;
+          float ax1 = px[0], ay1 = py[0];
+#pragma unroll
+          for (int q = 1; q < MI; ++q)
+            if (q == nx) { ax1 = px[2 * q]; ay1 = py[2 * q]; }
+          closed = closed && __float_as_uint(px[2 * j + 1]) == __float_as_uint(ax1) &&
+                   __float_as_uint(py[2 * j + 1]) == __float_as_uint(ay1);
+        }
+      if (finite && (closed || mi == 1)) {
         const float cx = sx / (2.f * mi), cy = sy / (2.f * mi);
         float r2 = 0.f;
 #pragma unroll
@@ -332,15 +348,16 @@ static_assert(sizeof(psdf_batch_plan::side) / sizeof(hipStream_t) == kGroups - 1
               "one side stream per group after the first, one event per group");
 int group_of(int m) { return m <= 8 ? m - 3 : 6; }
 
-hipError_t launch_batch(int mf, int mi_class, int nw, int grid, const BatchArgs& a, hipStream_t st) {
+hipError_t launch_batch(int mf, int mi_class, int nw, int grid, const BatchArgs& a, hipStream_t st,
+                        hipEvent_t ev0, hipEvent_t ev1) {
   switch (mf) {
-    case 3: return launch_batch_mf<3>(mi_class, nw, grid, a, st);
-    case 4: return launch_batch_mf<4>(mi_class, nw, grid, a, st);
-    case 5: return launch_batch_mf<5>(mi_class, nw, grid, a, st);
-    case 6: return launch_batch_mf<6>(mi_class, nw, grid, a, st);
-    case 7: return launch_batch_mf<7>(mi_class, nw, grid, a, st);
-    case 8: return launch_batch_mf<8>(mi_class, nw, grid, a, st);
-    default: return launch_batch_mf<16>(mi_class, nw, grid, a, st);
+    case 3: return launch_batch_mf<3>(mi_class, nw, grid, a, st, ev0, ev1);
+    case 4: return launch_batch_mf<4>(mi_class, nw, grid, a, st, ev0, ev1);
+    case 5: return launch_batch_mf<5>(mi_class, nw, grid, a, st, ev0, ev1);
+    case 6: return launch_batch_mf<6>(mi_class, nw, grid, a, st, ev0, ev1);
+    case 7: return launch_batch_mf<7>(mi_class, nw, grid, a, st, ev0, ev1);
+    case 8: return launch_batch_mf<8>(mi_class, nw, grid, a, st, ev0, ev1);
+    default: return launch_batch_mf<16>(mi_class, nw, grid, a, st, ev0, ev1);
   }
 }
 
@@ -544,7 +561,9 @@ int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay
         int32_t* obst, float* grad, uint64_t* keys, hipStream_t stream, bool use_graph) {
   if (p->total_stages == 0) return PSDF_OK;
   const BatchArgs a = make_args(p, poses, ax, ay, bx, by, off, d, edge, obst, grad, keys);
-  auto enqueue = [&](hipStream_t st) -> hipError_t {
+  // timed: events recorded by each batch-kernel dispatch itself (eager
+  // calls only; a captured graph is timed as a whole)
+  auto enqueue = [&](hipStream_t st, bool timed) -> hipError_t {
     // the groups write disjoint partial rows and count their items on
     // counters of their own, so they run concurrently (their tails overlap)
     const int ng = (int)p->groups.size();
@@ -562,7 +581,9 @@ int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay
       ga.n_items = g.count;
       ga.ctrl = a.ctrl + group_of(g.mf);
       hipStream_t gs = k == 0 ? st : p->side[k - 1];
-      err = launch_batch(g.mf, p->mi_class, p->shape.nw, g.grid, ga, gs);
+      hipEvent_t ev0 = nullptr, ev1 = nullptr;
+      if (!timed || !timer_kernel_events(&ev0, &ev1)) ev0 = ev1 = nullptr;
+      err = launch_batch(g.mf, p->mi_class, p->shape.nw, g.grid, ga, gs, ev0, ev1);
       if (err == hipSuccess && k > 0) err = hipEventRecord(p->ev[k], gs);
       if (err == hipSuccess && k > 0) err = hipStreamWaitEvent(st, p->ev[k], 0);
     }
@@ -572,18 +593,13 @@ int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay
         a.partial, a.aux, keys, d, edge, obst, grad, p->d_ctrl, kGroups, nullptr, nullptr, 0);
     return hipGetLastError();
   };
-  if (!use_graph) {
-    timer_begin(stream);
-    hipError_t err = enqueue(stream);
-    timer_end(stream);
-    return hip_status(err);
-  }
+  if (!use_graph) return hip_status(enqueue(stream, true));
   const std::vector<const void*> ptrs = {poses, ax, ay, bx, by, off, d, edge, obst, grad, keys};
   if (!p->exec || p->bound != ptrs) {
     free_graph(p);
     hipError_t err = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
     if (err != hipSuccess) return hip_status(err);
-    err = enqueue(p->cap_stream);
+    err = enqueue(p->cap_stream, false);
     hipGraph_t g = nullptr;
     hipError_t err2 = hipStreamEndCapture(p->cap_stream, &g);
     if (err != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_status(err); }
@@ -611,6 +627,19 @@ hipError_t launch_screen(int mf, int mi_class, int grid, const ScreenArgs& a, hi
   }
 }
 
+hipError_t launch_screen_bound(int mf, int mi_class, int grid, const ScreenArgs& a,
+                               hipStream_t st) {
+  switch (mf) {
+    case 3: return launch_screen_bound_mf<3>(mi_class, grid, a, st);
+    case 4: return launch_screen_bound_mf<4>(mi_class, grid, a, st);
+    case 5: return launch_screen_bound_mf<5>(mi_class, grid, a, st);
+    case 6: return launch_screen_bound_mf<6>(mi_class, grid, a, st);
+    case 7: return launch_screen_bound_mf<7>(mi_class, grid, a, st);
+    case 8: return launch_screen_bound_mf<8>(mi_class, grid, a, st);
+    default: return launch_screen_bound_mf<16>(mi_class, grid, a, st);
+  }
+}
+
 hipError_t launch_fallback(int mf, int mi_class, int grid, int tiles, const ScreenArgs& a,
                            hipStream_t st) {
   switch (mf) {
@@ -635,14 +664,19 @@ hipError_t launch_labels(const FpConst* fps, const BatchInst* insts, const int* 
 
 extern "C" {
 
-int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, int32_t topk,
-                        const float* poses, const float* ax, const float* ay, const float* bx,
-                        const float* by, const int32_t* off, float* d, int32_t* edge,
-                        int32_t* obst, float* grad, uint64_t* keys, int32_t* stage_cand,
-                        int32_t* stage_cert, uint64_t* cand_keys, hipStream_t stream) {
+// The screened call of either form: the horizon pass, per footprint-size
+// group the screening kernel (ranked top-K with the network or the edge
+// distance, or the bound-threshold form) and the fallback of the stages
+// that fail the certificate, then the finish kernel.
+static int screened_run(psdf_batch_plan* p, bool bound, const float* theta, int32_t pool,
+                        int32_t topk, const float* poses, const float* ax, const float* ay,
+                        const float* bx, const float* by, const int32_t* off, float* d,
+                        int32_t* edge, int32_t* obst, float* grad, uint64_t* keys,
+                        int32_t* stage_cand, int32_t* stage_cert, uint64_t* cand_keys,
+                        hipStream_t stream) {
   clear_error();
   if (!p) return set_error(PSDF_EINVAL, "plan is NULL");
-  if (pool < 1 || pool > kPoolCap || topk < 1)
+  if (!bound && (pool < 1 || pool > kPoolCap || topk < 1))
     return set_error(PSDF_EINVAL, "pool = %d (1..%d), topk = %d (>= 1)", pool, kPoolCap, topk);
   if (p->max_M > kScreenMaxM)
     return set_error(PSDF_ETOOBIG, "an instance has %d obstacles; screening supports %d", p->max_M,
@@ -653,6 +687,7 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
   if (!poses || !off || !d || !edge || !obst || !grad || !keys)
     return set_error(PSDF_EINVAL, "a pose, offset or output pointer is NULL");
   if (p->max_M > 0 && (!ax || !ay || !bx || !by)) return set_error(PSDF_EINVAL, "an edge array is NULL");
+  if (bound) theta = nullptr;
   ScreenArgs a;
   a.fps = p->d_fp; a.insts = p->d_inst; a.stage_inst = p->d_stage_inst;
   a.poses = poses; a.ax = ax; a.ay = ay; a.bx = bx; a.by = by; a.off = off;
@@ -685,7 +720,8 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
     ga.n_stages = g.count;
     ga.failed = p->d_failed + g.start;
     ga.ctrl = p->d_sctrl + 2 * group_of(g.mf);
-    err = launch_screen(g.mf, p->mi_class, g.count, ga, stream);
+    err = bound ? launch_screen_bound(g.mf, p->mi_class, g.count, ga, stream)
+                : launch_screen(g.mf, p->mi_class, g.count, ga, stream);
     if (err != hipSuccess) break;
     const int grid = std::max(1, std::min(g.count * g.max_tiles, 4 * p->cu));
     err = launch_fallback(g.mf, p->mi_class, grid, g.max_tiles, ga, stream);
@@ -701,6 +737,24 @@ int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, in
     err = hipGetLastError();
   }
   return hip_status(err);
+}
+
+int psdf_batch_screened(psdf_batch_plan* p, const float* theta, int32_t pool, int32_t topk,
+                        const float* poses, const float* ax, const float* ay, const float* bx,
+                        const float* by, const int32_t* off, float* d, int32_t* edge,
+                        int32_t* obst, float* grad, uint64_t* keys, int32_t* stage_cand,
+                        int32_t* stage_cert, uint64_t* cand_keys, hipStream_t stream) {
+  return screened_run(p, false, theta, pool, topk, poses, ax, ay, bx, by, off, d, edge, obst,
+                      grad, keys, stage_cand, stage_cert, cand_keys, stream);
+}
+
+int psdf_batch_screened_bound(psdf_batch_plan* p, const float* poses, const float* ax,
+                              const float* ay, const float* bx, const float* by,
+                              const int32_t* off, float* d, int32_t* edge, int32_t* obst,
+                              float* grad, uint64_t* keys, int32_t* stage_cand,
+                              int32_t* stage_cert, uint64_t* cand_keys, hipStream_t stream) {
+  return screened_run(p, true, nullptr, 1, 1, poses, ax, ay, bx, by, off, d, edge, obst, grad,
+                      keys, stage_cand, stage_cert, cand_keys, stream);
 }
 
 int psdf_screen_labels(const psdf_batch_plan* p, const float* poses, const float* ax,

@@ -13,6 +13,7 @@
 // L2 of the issuing XCD).  No work-group ever waits for another.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "psdf_device.hpp"
@@ -122,10 +123,15 @@ __global__ __launch_bounds__(64 * NW) void batch_kernel(BatchArgs A) {
   }
 }
 
+// ev0 / ev1 (may be null): events the dispatch itself records at its start
+// and end (kernel timer).
 template <int MF, int MI>
-hipError_t launch_batch_t(int nw, int grid, const BatchArgs& a, hipStream_t st) {
-  if (nw == 1) batch_kernel<MF, MI, 1><<<grid, 64, 0, st>>>(a);
-  else batch_kernel<MF, MI, 4><<<grid, 256, 0, st>>>(a);
+hipError_t launch_batch_t(int nw, int grid, const BatchArgs& a, hipStream_t st, hipEvent_t ev0,
+                          hipEvent_t ev1) {
+  if (nw == 1)
+    hipExtLaunchKernelGGL(batch_kernel<MF, MI, 1>, dim3(grid), dim3(64), 0, st, ev0, ev1, 0, a);
+  else
+    hipExtLaunchKernelGGL(batch_kernel<MF, MI, 4>, dim3(grid), dim3(256), 0, st, ev0, ev1, 0, a);
   return hipGetLastError();
 }
 
@@ -138,10 +144,11 @@ hipError_t batch_occupancy_t(int nw, int* blocks_per_cu) {
 
 // Per footprint-size entry points (instantiated in psdf_batch_mf*.hip).
 template <int MF>
-hipError_t launch_batch_mf(int mi_class, int nw, int grid, const BatchArgs& a, hipStream_t st) {
-  if (mi_class == 4) return launch_batch_t<MF, 4>(nw, grid, a, st);
-  if (mi_class == 8) return launch_batch_t<MF, 8>(nw, grid, a, st);
-  return launch_batch_t<MF, 16>(nw, grid, a, st);
+hipError_t launch_batch_mf(int mi_class, int nw, int grid, const BatchArgs& a, hipStream_t st,
+                           hipEvent_t ev0, hipEvent_t ev1) {
+  if (mi_class == 4) return launch_batch_t<MF, 4>(nw, grid, a, st, ev0, ev1);
+  if (mi_class == 8) return launch_batch_t<MF, 8>(nw, grid, a, st, ev0, ev1);
+  return launch_batch_t<MF, 16>(nw, grid, a, st, ev0, ev1);
 }
 
 template <int MF>
@@ -152,7 +159,8 @@ hipError_t batch_occupancy_mf(int mi_class, int nw, int* blocks_per_cu) {
 }
 
 #define PSDF_EXTERN_BATCH(MF)                                                                  \
-  extern template hipError_t launch_batch_mf<MF>(int, int, int, const BatchArgs&, hipStream_t); \
+  extern template hipError_t launch_batch_mf<MF>(int, int, int, const BatchArgs&, hipStream_t, \
+                                                 hipEvent_t, hipEvent_t);                      \
   extern template hipError_t batch_occupancy_mf<MF>(int, int, int*);
 PSDF_EXTERN_BATCH(3)
 PSDF_EXTERN_BATCH(4)

@@ -19,8 +19,10 @@
 //    obstacles left out of the instance's list;
 //  * excluded pool members, only when the circle bounds do not certify: for
 //    a closed convex polygon not containing p, dist(p, P^i) is the smallest
-//    point-segment distance from p to its edges (an open chain has no
-//    interior), so dist(P0(x), P^i) >= dist(p, P^i) - rmax.
+//    point-segment distance from p to its edges, so
+//    dist(P0(x), P^i) >= dist(p, P^i) - rmax; a free segment (one edge) has
+//    no interior, and an open chain of two or more edges gets -inf (the axis
+//    test sees its convex hull, whose closing edge gives no axis).
 // Both subtract gamma to absorb FP32 rounding; an invalid obstacle gets -inf.
 // Two convex sets at distance r > tau_sep are separated by the axis test
 // (the largest axis gap is at least kappa r), so their sd is d_sep >= r >= LB.
@@ -93,7 +95,7 @@ __device__ __forceinline__ float obstacle_lb(float px, float py, const float* __
     pos = pos && cr >= 0.f;
     neg = neg && cr <= 0.f;
   }
-  if (!finite || (closed && (pos || neg))) return -__builtin_huge_valf();
+  if (!finite || (closed && (pos || neg)) || (!closed && mi >= 2)) return -__builtin_huge_valf();
   return sqrtf(d2) - rmax - kLbGamma;
 }
 
@@ -477,6 +479,166 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
   }
 }
 
+// Certified screening by the bound alone (no ranking), one work-group per
+// stage.  The obstacle with the smallest lower bound (the seed) is evaluated
+// exactly; its sd is an upper bound of the stage's minimum phi, so the bar
+// T = max(sd_seed, tau_sep) satisfies T >= max(phi, tau_sep), and every
+// obstacle whose bound does not exceed T is evaluated exactly.  Every
+// obstacle left out then has LB_i > T >= max(phi_K, tau_sep), which is the
+// certificate of screen_kernel, met by construction; what can still send a
+// stage to the full evaluation is an instance bound (the obstacles outside
+// the horizon list) at or below T, more than kBoundCap candidates, or an
+// unusable horizon list.  The candidate set is the smallest that any
+// certificate built on these bounds can use when the seed is the winner or
+// the stage penetrates (T = tau_sep then).
+constexpr int kBoundCap = 512;   // candidates per stage (more: full evaluation)
+
+template <int MF, int MI>
+__global__ __launch_bounds__(kScreenThreads) void screen_bound_kernel(ScreenArgs A) {
+  __shared__ int scan[kScreenThreads];
+  __shared__ uint32_t red[kScreenThreads / 64];
+  __shared__ int cand_o[kBoundCap];
+  __shared__ uint64_t wkey[kScreenThreads / 64];
+  __shared__ float4 rf[MF];
+  __shared__ uint64_t s_seed_key;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int s = A.stages[blockIdx.x];
+  const int inst = __builtin_amdgcn_readfirstlane(A.stage_inst[s]);
+  const BatchInst in = A.insts[inst];
+  const FpConst& F = A.fps[inst];
+  const float* p = A.poses + 3 * s;
+  const float px = p[0], py = p[1];
+  float sn, cs;
+  sincosf(p[2], &sn, &cs);
+  const bool pose_ok = isfinite(px) && isfinite(py) && isfinite(cs) && isfinite(sn);
+  if (tid < MF) rf[tid] = rotated_slot(F, tid, cs, sn);   // read after the reductions below
+  const int Eend = in.edge_off + in.E;
+  const int* off = A.off + in.obst_off;
+
+  const int hc = A.hcount[inst];
+  if (hc < 0 || hc > kHorizonCap) {
+    if (tid == 0) {
+      A.keys[s] = kEmptyKey;
+      if (A.stage_cand) A.stage_cand[s] = 0;
+      if (A.stage_cert) A.stage_cert[s] = 0;
+      if (A.cand_keys) A.cand_keys[s] = kEmptyKey;
+      A.failed[atomicAdd(&A.ctrl[0], 1u)] = s;
+    }
+    return;
+  }
+
+  // ---- bounding-circle lower bounds over the horizon list (as screen_kernel)
+  uint32_t k[kStageKeys];
+  int hidx[kStageKeys];
+  const int n_h = hc;
+  const float4* hl = A.hlist + in.circ_off;
+  const float lb_off = F.rmax + kLbGamma;
+  const int nq = (n_h + kScreenThreads - 1) / kScreenThreads;
+  uint32_t lo = 0xffffffffu;
+#pragma unroll
+  for (int q = 0; q < kStageKeys; ++q) {
+    const int idx = tid + kScreenThreads * q;
+    uint32_t key = 0xffffffffu;
+    hidx[q] = 0;
+    if (q < nq && idx < n_h) {
+      const float4 c = hl[idx];
+      hidx[q] = __float_as_int(c.w);
+      const float dx = px - c.x, dy = py - c.y;
+      const float lbv = sqrtf(fmaf(dx, dx, dy * dy)) - c.z - lb_off;
+      key = orderable(pose_ok ? lbv : -__builtin_huge_valf());
+    }
+    k[q] = key;
+    lo = min(lo, key);
+  }
+  // ---- the seed: the smallest bound, lowest list slot on ties (its
+  // obstacle index is taken from the thread that holds it)
+  lo = block_min_u32(lo, red);
+  int slot = 0x7fffffff;
+#pragma unroll
+  for (int q = 0; q < kStageKeys; ++q)
+    if (q < nq && k[q] == lo && lo != 0xffffffffu) slot = min(slot, tid + kScreenThreads * q);
+  slot = (int)block_min_u32((uint32_t)slot, red);
+  uint64_t seed_key = kEmptyKey;
+  int seed_o = -1;
+  if (lo != 0xffffffffu) {
+    // the slot's owner evaluates the seed; everyone reads its key from LDS
+    if (tid == slot % kScreenThreads) {
+      int o = 0;
+#pragma unroll
+      for (int q = 0; q < kStageKeys; ++q)
+        if (q == slot / kScreenThreads) o = hidx[q];
+      const int a = off[o], mi = off[o + 1] - a;
+      Obst<MI> ob;
+      load_obstacle<MI>(ob, A.ax, A.ay, A.bx, A.by, in.edge_off + a, mi, Eend, F.eps);
+      if (a < 0) ob.bad = true;
+      const uint32_t kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, rf, px, py)) : 0u;
+      s_seed_key = ((uint64_t)kk << 32) | (uint32_t)o;
+    }
+    __syncthreads();
+    seed_key = s_seed_key;
+    seed_o = (int)(seed_key & 0xffffffffu);
+  }
+  // ---- the bar and the candidates (every list entry with LB <= T but the seed)
+  const float phi1 = seed_key == kEmptyKey ? __builtin_huge_valf()
+                                           : from_orderable((uint32_t)(seed_key >> 32));
+  const uint32_t tkey = orderable(fmaxf(phi1, F.tau_sep));
+  int mine = 0;
+#pragma unroll
+  for (int q = 0; q < kStageKeys; ++q)
+    if (q < nq && k[q] <= tkey && k[q] != 0xffffffffu && hidx[q] != seed_o) ++mine;
+  int n_cand = 0;
+  int at = block_scan(mine, scan, &n_cand);
+  const bool overflow = n_cand > kBoundCap;
+  if (!overflow) {
+#pragma unroll
+    for (int q = 0; q < kStageKeys; ++q)
+      if (q < nq && k[q] <= tkey && k[q] != 0xffffffffu && hidx[q] != seed_o) cand_o[at++] = hidx[q];
+  }
+  __syncthreads();
+
+  // ---- exact evaluation of the candidates (lane <-> candidate)
+  uint64_t best = seed_key;
+  if (!overflow) {
+    for (int c0 = 0; c0 < n_cand; c0 += kScreenThreads) {
+      const int c = c0 + tid;
+      const bool act = c < n_cand;
+      int e0 = 0, mi = 0, o = 0;
+      if (act) {
+        o = cand_o[c];
+        e0 = off[o];
+        mi = off[o + 1] - e0;
+        e0 += in.edge_off;
+      }
+      Obst<MI> ob;
+      load_obstacle<MI>(ob, A.ax, A.ay, A.bx, A.by, e0, mi, Eend, F.eps);
+      if (act && e0 < in.edge_off) ob.bad = true;
+      uint32_t kk = 0xffffffffu;
+      if (act && mi != 0) kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, rf, px, py)) : 0u;
+      const uint64_t key = kk == 0xffffffffu ? kEmptyKey : (((uint64_t)kk << 32) | (uint32_t)o);
+      const uint64_t wmin = fw_min_u64(key);
+      best = wmin < best ? wmin : best;
+    }
+  }
+  if (lane == 0) wkey[w] = best;
+  __syncthreads();
+  uint64_t keyK = wkey[0];
+#pragma unroll
+  for (int i = 1; i < kScreenThreads / 64; ++i) keyK = wkey[i] < keyK ? wkey[i] : keyK;
+  // ---- certificate: the list entries left out have LB > T by construction;
+  // the obstacles outside the list have the instance bound
+  const uint32_t rest = A.hrest[inst];
+  const bool cert = (keyK != kEmptyKey && (keyK >> 32) == 0)          // NaN wins anyway
+                    || (!overflow && (rest == 0xffffffffu || rest > tkey));
+  if (tid == 0) {
+    A.keys[s] = keyK;
+    if (A.stage_cand) A.stage_cand[s] = overflow ? 0 : n_cand + (seed_o >= 0 ? 1 : 0);
+    if (A.stage_cert) A.stage_cert[s] = cert ? 1 : 0;
+    if (A.cand_keys) A.cand_keys[s] = keyK;
+    if (!cert) A.failed[atomicAdd(&A.ctrl[0], 1u)] = s;
+  }
+}
+
 // Full evaluation of the failed stages: items (failed stage, tile of 256
 // obstacles), every item the same work, taken by the work-groups in turn
 // (item b, b + grid, ...); each work-group folds its tile's minimum into
@@ -541,6 +703,14 @@ hipError_t launch_screen_mf(int mi_class, int grid, const ScreenArgs& a, hipStre
 }
 
 template <int MF>
+hipError_t launch_screen_bound_mf(int mi_class, int grid, const ScreenArgs& a, hipStream_t st) {
+  if (mi_class == 4) screen_bound_kernel<MF, 4><<<grid, kScreenThreads, 0, st>>>(a);
+  else if (mi_class == 8) screen_bound_kernel<MF, 8><<<grid, kScreenThreads, 0, st>>>(a);
+  else screen_bound_kernel<MF, 16><<<grid, kScreenThreads, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+template <int MF>
 hipError_t launch_fallback_mf(int mi_class, int grid, int max_tiles, const ScreenArgs& a,
                               hipStream_t st) {
   if (mi_class == 4) screen_fallback_kernel<MF, 4><<<grid, 256, 0, st>>>(a, max_tiles);
@@ -551,6 +721,7 @@ hipError_t launch_fallback_mf(int mi_class, int grid, int max_tiles, const Scree
 
 #define PSDF_EXTERN_SCREEN(MF)                                                                  \
   extern template hipError_t launch_screen_mf<MF>(int, int, const ScreenArgs&, hipStream_t);    \
+  extern template hipError_t launch_screen_bound_mf<MF>(int, int, const ScreenArgs&, hipStream_t); \
   extern template hipError_t launch_fallback_mf<MF>(int, int, int, const ScreenArgs&, hipStream_t);
 PSDF_EXTERN_SCREEN(3)
 PSDF_EXTERN_SCREEN(4)

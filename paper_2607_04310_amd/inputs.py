@@ -275,6 +275,68 @@ def c5(n_instances: int = 64, cfg: int = 5):
     return [c5_instance(k, fp, cfg) for k in range(n_instances)]
 
 
+# Contact placements of an axis-aligned rectangle against an axis-aligned
+# rectangular footprint: (name, side, gap) with gap > 0 a clearance, 0
+# touching and < 0 an overlap, on the footprint's right / top face, or at its
+# top-right corner (diagonal offset: vertex to vertex when gap >= 0).
+CONTACTS = ([(f"face_{side}_{name}", side, g)
+             for side in ("right", "top")
+             for name, g in (("far", 0.25), ("near", 1.0 / 1024), ("touch", 0.0),
+                             ("shallow", -1.0 / 2048), ("mid", -1.0 / 16), ("deep", -0.15))]
+            + [(f"corner_{name}", "corner", g)
+               for name, g in (("far", 0.25), ("touch", 0.0), ("shallow", -1.0 / 2048),
+                               ("deep", -1.0 / 16))])
+
+
+def aligned_contacts(seed: int = 0, rotate=None) -> Instance:
+    """Scenes of exact contact geometry (tie-rich): footprint 0.625 x 0.375 m,
+    one stage per placement of CONTACTS (heading 0, stages 16 m apart), each
+    against its own axis-aligned rectangle (sides 0.5 x 0.75 m) placed at that
+    gap from the footprint's face or corner and slid along the face by a
+    seeded dyadic offset (flush, inside or overhanging).  Every coordinate is
+    a multiple of 2^-11 m, so the contact ties are exact in float32 and
+    float64.  rotate = (angle, tx, ty) applies one rigid motion to every pose
+    and edge (the ties then hold only to rounding)."""
+    rng = rng_for(40, seed)
+    fp = np.array([[-0.3125, -0.1875], [0.3125, -0.1875], [0.3125, 0.1875], [-0.3125, 0.1875]],
+                  dtype=np.float32)
+    hw, hh = 0.3125, 0.1875          # footprint half extents
+    ow, oh = 0.25, 0.375             # obstacle half extents
+    poses, edges = [], []
+    for k, (_, side, gap) in enumerate(CONTACTS):
+        px, py = 16.0 * (k % 4) - 24.0, 16.0 * (k // 4) - 24.0
+        slide = float(rng.integers(-512, 513)) / 2048.0     # along the face, |slide| <= 0.25
+        if side == "right":
+            cx, cy = px + hw + gap + ow, py + slide
+        elif side == "top":
+            cx, cy = px + slide, py + hh + gap + oh
+        else:
+            cx, cy = px + hw + gap + ow, py + hh + gap + oh
+        poses.append((px, py, 0.0))
+        x0, x1, y0, y1 = cx - ow, cx + ow, cy - oh, cy + oh
+        corners = [(x0, y0), (x1, y0), (x1, y1), (x0, y1)]
+        for j in range(4):
+            a, b = corners[j], corners[(j + 1) % 4]
+            edges.append((a[0], a[1], b[0], b[1]))
+    poses = np.array(poses, dtype=np.float64)
+    edges = np.array(edges, dtype=np.float64)
+    if rotate is not None:
+        ang, tx, ty = rotate
+        c, s = np.cos(ang), np.sin(ang)
+
+        def move(x, y):
+            return c * x - s * y + tx, s * x + c * y + ty
+        poses[:, 0], poses[:, 1] = move(poses[:, 0], poses[:, 1])
+        poses[:, 2] += ang
+        edges[:, 0], edges[:, 1] = move(edges[:, 0], edges[:, 1])
+        edges[:, 2], edges[:, 3] = move(edges[:, 2], edges[:, 3])
+    edges = edges.astype(np.float32)
+    edges[:, 2:] = np.roll(edges[:, :2].reshape(-1, 4, 2), -1, axis=1).reshape(-1, 2)
+    n = len(CONTACTS)
+    return Instance(fp, poses.astype(np.float32), edges, csr_offsets([4] * n), 4,
+                    dict(workload="aligned_contacts", contacts=[c[0] for c in CONTACTS]))
+
+
 def random_small(rng, n_obst=8, n_poses=16, lo=-2.0, hi=2.0, fp_m=None, segments=0):
     """Small mixed workloads for parity sweeps: random convex footprint,
     rectangles and free segments near the poses (so that many stages penetrate)."""

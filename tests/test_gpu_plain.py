@@ -344,6 +344,32 @@ def test_constraints_export(api):
     assert np.all(np.isposinf(hj[:, 0])) and np.all(hj[:, 1:] == 0)
 
 
+@pytest.mark.parametrize("case", ["c1", "c2", "contacts", "mixed"])
+def test_constraints_vs_oracle(api, case):
+    """psdf_constraints rows against the oracle's linearised constraint
+    (Sec. V: h = phi - d_min and J_g = -grad phi; Alg. 1, the export step):
+    h within 1e-5 m of phi - d_min, the winning obstacle (the keys) in the
+    oracle's tie set, -J_g the oracle's gradient (or an active branch at a
+    kink)."""
+    rng = np.random.default_rng(17)
+    inst = {"c1": lambda: inputs.c1(1), "c2": lambda: inputs.c2(1),
+            "contacts": lambda: inputs.aligned_contacts(0, rotate=(0.3, 3.1, -2.7)),
+            "mixed": lambda: inputs.random_small(rng, n_obst=30, n_poses=40, segments=5)}[case]()
+    d_min = 0.01
+    edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar)
+    poses = torch.tensor(inst.poses, device="cuda")
+    host = torch.empty((inst.N, 4), dtype=torch.float32, pin_memory=True)
+    hj, keys = api.psdf_constraints(inst.footprint, poses, edges, d_min, host=host)
+    torch.cuda.synchronize()
+    hj = host.numpy().astype(np.float64)
+    k = keys.cpu().numpy().view(np.uint64)
+    obst = np.where(k == np.uint64(0xffffffffffffffff), -1, (k & np.uint64(0xffffffff)).astype(np.int64))
+    obst = np.where(np.isnan(hj[:, 0]), -1, obst)
+    st = check_stages(inst.footprint, inst.poses, inst.edges, inst.obst_off, 1000.0,
+                      hj[:, 0] + d_min, None, obst, -hj[:, 1:])
+    assert st["stages"] >= inst.N - 2, st
+
+
 def test_time_stage_min(api):
     inst = inputs.c2(0)
     edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar)

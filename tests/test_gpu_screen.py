@@ -1,8 +1,11 @@
 """GPU tests of the screener: MLP kernels against the FP64 MLP oracle, label
 generation against the PSDF oracle, certified screened evaluation equal to
-the full evaluation bit for bit (MLP ranking, distance ranking, forced
-fallback), and the measured gain of the trained network over distance
-ranking."""
+the full evaluation bit for bit (MLP ranking, distance ranking, the
+bound-threshold form, forced fallback), the c5 workload (64 instances x 50
+stages x 65536 edges) checked against the FP64 oracle on the plain batch and
+on every screened form (the MLP trained on held-out instances), and a
+comparison of the trained network with the screens that use no network:
+certification rate, exact evaluations, winner recall and call time."""
 import math
 
 import numpy as np
@@ -11,6 +14,7 @@ import pytest
 import oracle
 from oracle import mlp_oracle as mo
 from paper_2607_04310_amd import inputs
+from parity import check_stages, oracle_reference
 
 pytestmark = pytest.mark.gpu
 
@@ -190,6 +194,11 @@ def test_screened_uneven_batch(api):
     out2 = b2.screened(torch.tensor(_rand_theta(5), device="cuda"), pool=16, topk=8)
     torch.cuda.synchronize()
     _assert_same([x.clone() for x in out2], ref2)
+    # the bound-threshold form on both batches (free segments, a NaN pose)
+    for bb, rr in ((b, ref), (b2, ref2)):
+        out3 = bb.screened_bound()
+        torch.cuda.synchronize()
+        _assert_same([x.clone() for x in out3], rr)
     b.close()
     b2.close()
 
@@ -225,6 +234,10 @@ def test_screened_obstacle_free_instances(api):
     torch.cuda.synchronize()
     _assert_same([x.clone() for x in out2], ref2)
     assert bool(cert.bool().cpu()[rows].all())
+    out3, (cand, cert, ck) = b2.screened_bound(stats=True)
+    torch.cuda.synchronize()
+    _assert_same([x.clone() for x in out3], ref2)
+    assert bool(cert.bool().cpu()[rows].all())
     b2.close()
 
 
@@ -234,8 +247,148 @@ def test_screened_repeated_calls(api):
     insts = inputs.c5(4)
     b = api.Batch(insts, graph=False)
     ref = _run_plain(b)
-    for pool, topk in ((1, 1), (128, 256), (1, 1), (1, 1), (128, 256)):
-        out = b.screened(None, pool=pool, topk=topk)
+    for pool, topk in ((1, 1), (128, 256), (0, 0), (1, 1), (1, 1), (0, 0), (128, 256)):
+        out = b.screened_bound() if pool == 0 else b.screened(None, pool=pool, topk=topk)
         torch.cuda.synchronize()
         _assert_same([x.clone() for x in out], ref)
+    b.close()
+
+
+# ---------------------------------------------------------------- c5 against the oracle
+
+@pytest.fixture(scope="module")
+def c5(api):
+    """The c5 batch, its plain outputs, a network trained on held-out c5
+    instances (other seeds) and the oracle's reference for the checked
+    stages: every stage of instances 0 and 1, and three stages of each of
+    the 64 instances."""
+    from paper_2607_04310_amd import screener
+    insts = inputs.c5(64)
+    print(f"[c5] {sum(i.N * i.E for i in insts):.3e} stage x edge pairs", flush=True)
+    b = api.Batch(insts, graph=False)
+    plain = _run_plain(b)
+    X, T = screener.training_set(inputs.c5(6, cfg=6), near=1024, far=1024, seed=1)
+    theta, hist = screener.train(X, T, epochs=10, batch=4096, lr=2e-3, seed=0)
+    print(f"[c5] trained on {X.shape[0]} held-out pairs, loss {hist[0]:.4f} -> {hist[-1]:.4f}",
+          flush=True)
+    rng = np.random.default_rng(11)
+    checked = {}
+    for k, inst in enumerate(insts):
+        stages = np.arange(inst.N) if k < 2 else np.sort(rng.choice(inst.N, 3, replace=False))
+        checked[k] = (stages, oracle_reference(inst.footprint, inst.poses, inst.edges,
+                                               inst.obst_off, 1000.0, stages))
+    print("[c5] oracle reference ready", flush=True)
+    yield dict(insts=insts, b=b, plain=plain, theta=theta, checked=checked)
+    b.close()
+
+
+def _check_c5(c5, outs, label):
+    d, e, o, g, _ = (x.cpu().numpy() for x in outs)
+    tot = dict(stages=0, obst_ties=0, edge_ties=0, kink_grads=0, pen=0)
+    for k, inst in enumerate(c5["insts"]):
+        po = c5["b"].desc[k][2]
+        sl = slice(po, po + inst.N)
+        stages, ref = c5["checked"][k]
+        st = check_stages(inst.footprint, inst.poses, inst.edges, inst.obst_off, 1000.0, d[sl],
+                          e[sl], o[sl], g[sl], stages=stages, reference=ref)
+        for key in tot:
+            tot[key] += st[key]
+    print(f"[c5 {label}] vs oracle: {tot}", flush=True)
+    assert tot["stages"] == sum(len(v[0]) for v in c5["checked"].values())
+
+
+def test_c5_plain_batch_vs_oracle(api, c5):
+    _check_c5(c5, c5["plain"], "plain")
+
+
+def _screen(c5, mode, theta=None):
+    b = c5["b"]
+    if mode == "bound":
+        return b.screened_bound(stats=True)
+    return b.screened(theta, pool=128, topk=256, stats=True)
+
+
+@pytest.mark.parametrize("mode", ["distance", "trained_mlp", "bound"])
+def test_c5_screened_vs_oracle(api, c5, mode):
+    out, (cand, cert, ck) = _screen(c5, mode, c5["theta"] if mode == "trained_mlp" else None)
+    torch.cuda.synchronize()
+    out = [x.clone() for x in out]
+    _assert_same(out, c5["plain"])
+    _check_c5(c5, out, mode)
+    print(f"[c5 {mode}] certified {cert.float().mean().item():.4f}, exact evaluations per "
+          f"stage {cand.float().mean().item():.1f}", flush=True)
+
+
+def _time_ms(fn, reps=10, warm=5):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    z.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(z) / reps
+
+
+def test_trained_network_against_screens_without_it(api, c5):
+    """What the trained network gains over the method without it, on c5
+    instances held out from its training set.  Every form is exact (bitwise
+    the plain batch).  Reported per form: certification rate, exact
+    (stage, obstacle) evaluations per stage, winner recall (the candidates'
+    minimum is already the answer) and the call time.  Asserted: the trained
+    network ranks better than an untrained one (higher winner recall, at
+    least as many certified stages), and the bound-threshold form, which needs
+    no ranking, certifies every stage with the fewest exact evaluations."""
+    rows = {}
+    forms = [("trained_mlp", c5["theta"]), ("untrained_mlp", torch.tensor(_rand_theta(3), device="cuda")),
+             ("distance", None), ("bound", None)]
+    for name, th in forms:
+        mode = "bound" if name == "bound" else "ranked"
+        out, (cand, cert, ck) = _screen(c5, mode, th)
+        torch.cuda.synchronize()
+        _assert_same([x.clone() for x in out], c5["plain"])
+        t = _time_ms(lambda: _screen(c5, mode, th))
+        keys = out[4]
+        rows[name] = dict(certified=cert.float().mean().item(), exact=cand.float().mean().item(),
+                          recall=(ck == keys).float().mean().item(), ms=t)
+    t_plain = _time_ms(lambda: c5["b"].run())
+    print(f"[gain] plain batch {t_plain:.3f} ms", flush=True)
+    for name, r in rows.items():
+        print(f"[gain] {name:>13}: certified {r['certified']:.4f}  exact/stage {r['exact']:7.1f}  "
+              f"winner recall {r['recall']:.4f}  {r['ms']:.3f} ms", flush=True)
+    tr, un = rows["trained_mlp"], rows["untrained_mlp"]
+    print(f"[gain] trained network vs distance ranking: time x{rows['distance']['ms'] / tr['ms']:.2f}, "
+          f"exact evaluations x{rows['distance']['exact'] / tr['exact']:.2f}; vs bound threshold: "
+          f"time x{rows['bound']['ms'] / tr['ms']:.2f}", flush=True)
+    assert tr["recall"] > un["recall"] and tr["certified"] >= un["certified"]
+    assert tr["certified"] >= 0.95 and tr["recall"] >= 0.95
+    assert rows["bound"]["certified"] == 1.0
+    assert rows["bound"]["exact"] <= min(r["exact"] for r in rows.values())
+
+
+@pytest.mark.parametrize("mode", ["ranked", "bound"])
+def test_screened_open_chain_around_pose(api, mode):
+    """An open chain of two edges whose convex hull holds the footprint (the
+    axis test finds no separating axis, so its sd is negative) while the
+    chain itself is 1 m from the pose: no certificate may exclude it (its
+    bounds are -inf), so the screened result is the plain one even when the
+    ranking picks a nearer rectangle as the only candidate."""
+    fp = inputs.hexagon_footprint(inputs.rng_for(2, 0))
+    poses = np.array([[3.0, 1.0, 0.0], [3.0, 1.0, 0.4]], np.float32)
+    chain = np.array([[0, 0, 4, 0], [4, 0, 4, 4]], np.float32)
+    rect = inputs.rect_edges(np.array([[3.0, 1.8]]), np.array([[0.2, 0.2]]), np.zeros(1))
+    edges = np.concatenate([chain, rect]).astype(np.float32)
+    off = np.array([0, 2, 6], np.int32)
+    inst = inputs.Instance(fp, poses, edges, off, 4, dict(workload="open_chain"))
+    ref = oracle.psdf(fp, poses, edges, off)
+    assert np.all(ref["obst"] == 0) and np.all(ref["phi"] < 0)   # the chain wins, penetrating
+    b = api.Batch([inst], graph=False)
+    plain = _run_plain(b)
+    out = b.screened_bound() if mode == "bound" else b.screened(None, pool=2, topk=1)
+    torch.cuda.synchronize()
+    _assert_same([x.clone() for x in out], plain)
+    d, e, o, g, _ = (x.cpu().numpy() for x in plain)
+    check_stages(fp, poses, edges, off, 1000.0, d, e, o, g)
     b.close()

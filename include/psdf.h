@@ -134,6 +134,26 @@ int psdf_grad(const float* footprint, int32_t m, const float* poses, int32_t N,
               int32_t* obst, float* grad, uint64_t* keys, void* ws, size_t ws_bytes,
               hipStream_t stream);
 
+/* psdf_grad_noalloc - psdf_grad for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, outputs and errors as psdf_grad,
+ * without ws / ws_bytes: the per-work-group partial minima go to a
+ * library-owned device buffer of PSDF_NOALLOC_WS_BYTES per GPU (a static
+ * device array, held by each GPU the library runs on until the process
+ * ends).  A problem whose psdf_workspace_bytes(N, M) exceeds that size
+ * returns PSDF_ETOOBIG before anything is enqueued (4 MiB holds, e.g.,
+ * N = 64 stages against 262144 obstacles).  The call allocates nothing: no
+ * hipMalloc, hipFree or allocating library routine.  Every call on one GPU
+ * uses that GPU's one buffer, so calls that overlap in time on one GPU
+ * (several streams or host threads) race and must be serialised by the
+ * caller; consecutive calls on one stream are safe (each call writes every
+ * partial it reads). */
+#define PSDF_NOALLOC_WS_BYTES (4u << 20)
+int psdf_grad_noalloc(const float* footprint, int32_t m, const float* poses, int32_t N,
+                      const psdf_edges* edges, const psdf_params* params, float* d,
+                      int32_t* edge, int32_t* obst, float* grad, uint64_t* keys,
+                      hipStream_t stream);
+
 /* psdf_constraints - the stage-wise parameters of the linearised safety
  * constraint h(x) = phi(x) - d_min >= 0 that an SQP step hands to its QP
  * (Sec. V: first-order expansion of h about the nominal poses, with

@@ -24,6 +24,7 @@ PSDF_EHIP = -6
 MAX_FP_VERTS = 16
 MAX_OBST_EDGES = 16
 MLP_PARAMS = 4545
+NOALLOC_WS_BYTES = 4 << 20
 
 
 class PsdfParams(ctypes.Structure):
@@ -66,6 +67,9 @@ _SIGS = {
     "psdf_grad": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
                                  ctypes.POINTER(PsdfParams), _VP, _VP, _VP, _VP, _VP, _VP,
                                  ctypes.c_size_t, _VP]),
+    "psdf_grad_noalloc": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
+                                         ctypes.POINTER(PsdfParams), _VP, _VP, _VP, _VP, _VP,
+                                         _VP]),
     "psdf_set_launch_shape": (ctypes.c_int, [_I32, _I32]),
     "psdf_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(PsdfBatchDesc),
                                               _I32, _VP, _I32, ctypes.POINTER(PsdfParams), _I32]),

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "psdf.h"
 #include "psdf_kernels.hpp"
@@ -532,6 +533,65 @@ int psdf_grad(const float* footprint, int32_t m, const float* poses, int32_t N,
               hipStream_t stream) {
   return plain_run(footprint, m, poses, N, edges, params, d, edge, obst, grad, keys, ws,
                    ws_bytes, 1, stream);
+}
+
+// ------------------------------------------------------------------ no-alloc form
+
+// Library-owned scratch of psdf_grad_noalloc: one copy per GPU, held until
+// the process ends.  In host code the name is only a stand-in for the
+// symbol; the device address comes from hipGetSymbolAddress, taken once per
+// device (with that device current) on the entry point's first call there.
+static __device__ __align__(256) uint8_t scratch[PSDF_NOALLOC_WS_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for_current_device(void** out) {
+  int dev = -1;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return hip_status(err);
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error(PSDF_EINVAL, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (err != hipSuccess) return hip_status(err);
+    if (!ptr) return set_error(PSDF_EHIP, "no device address for the scratch buffer");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PSDF_OK;
+}
+}  // namespace
+
+int psdf_grad_noalloc(const float* footprint, int32_t m, const float* poses, int32_t N,
+                      const psdf_edges* edges, const psdf_params* params, float* d,
+                      int32_t* edge, int32_t* obst, float* grad, uint64_t* keys,
+                      hipStream_t stream) {
+  clear_error();
+  FpConst F;
+  psdf_edges e;
+  int rc = plain_common(footprint, m, poses, N, edges, params, F, e);
+  if (rc) return rc;
+  if (N == 0) return PSDF_OK;
+  const size_t need = psdf_workspace_bytes(N, e.M);
+  if (need > PSDF_NOALLOC_WS_BYTES)
+    return set_error(PSDF_ETOOBIG,
+                     "N = %d stages and M = %d obstacles need %zu bytes of scratch; the "
+                     "no-alloc form holds %zu",
+                     N, e.M, need, (size_t)PSDF_NOALLOC_WS_BYTES);
+  void* ws = nullptr;
+  if (need > 0) {
+    rc = scratch_for_current_device(&ws);
+    if (rc) return rc;
+  }
+  // every partial the kernels read is written by the same call, so the
+  // buffer needs no clearing between calls
+  return plain_run(footprint, m, poses, N, edges, params, d, edge, obst, grad, keys, ws, need, 1,
+                   stream);
 }
 
 int psdf_constraints(const float* footprint, int32_t m, const float* poses, int32_t N,

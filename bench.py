@@ -53,10 +53,10 @@ SIMDS, CLOCK_GHZ = 1024, 2.4
 CSRC = os.path.join("paper_2607_04310_amd", "csrc")
 # each kernel's own sources (code, instantiation, launch choice, build flags)
 KERNELS = {
+    # the batch kernel's code; its launch shape is hashed with it
     "batch_kernel": dict(
         sources=[os.path.join(CSRC, f) for f in (
-            "psdf_device.hpp", "psdf_winner.hpp", "psdf_batch.hpp", "psdf_batch_mf6.hip",
-            "psdf_batch.hip", "psdf_host.cpp", "psdf_host.hpp")]
+            "psdf_device.hpp", "psdf_winner.hpp", "psdf_batch.hpp", "psdf_host.hpp")]
         + [os.path.join("paper_2607_04310_amd", "build.py")],
         valu=os.path.join(ROOT, "profiles", "batch_kernel_c5_valu_counters.md"),
         hbm=os.path.join(ROOT, "profiles", "batch_kernel_c5_hbm_counters.md")),
@@ -70,17 +70,21 @@ KERNELS = {
 }
 
 
-def source_hash(kernel):
+def source_hash(kernel, shape=None):
+    """Hash of the kernel's sources (and of its launch shape, when given)."""
     h = hashlib.sha256()
     for f in KERNELS[kernel]["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    if shape is not None:
+        h.update(json.dumps(shape, sort_keys=True).encode())
     return h.hexdigest()[:16]
 
 
-def counted(kernel, what, field):
+def counted(kernel, what, field, shape=None):
     """A figure recorded in a counter summary, or (None, why not) when the
-    summary is missing or the kernel has changed since it was taken."""
+    summary is missing or the kernel (or its launch shape) has changed since
+    it was taken."""
     try:
         text = open(KERNELS[kernel][what]).read()
     except OSError:
@@ -89,7 +93,7 @@ def counted(kernel, what, field):
     mv = re.search(field + r":\s*([0-9.eE+]+)", text)
     if not mh or not mv:
         return None, "counter summary incomplete"
-    if mh.group(1) != source_hash(kernel):
+    if mh.group(1) != source_hash(kernel, shape):
         return None, "kernel changed since the counters were taken"
     return float(mv.group(1)), "rocprofv3 counters"
 
@@ -101,8 +105,10 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
+    # the GPU's clock ramps up under load: the batch kernel runs ~15 % slower
+    # during the first ~40 launches (30 ms), so the default warmup covers that
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=24.0,
                     help="bound on the CPU-oracle sample (0 disables it)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -421,9 +427,12 @@ def main():
     kernel_ms = kms_total / max(1, launches)
     flop = sum(flops.flops_instance(len(i.footprint), i.N, i.edges, i.obst_off) for i in c5)
     achieved = flop / (kernel_ms * 1e-3) / 1e12
-    traffic, traffic_note = counted("batch_kernel", "hbm", "traffic_bytes_per_launch")
-    valu, _ = counted("batch_kernel", "valu", "valu_insts_per_launch")
     info = be.info()
+    traffic, traffic_note = counted("batch_kernel", "hbm", "traffic_bytes_per_launch", info)
+    valu, _ = counted("batch_kernel", "valu", "valu_insts_per_launch", info)
+    fp32_insts, _ = counted("batch_kernel", "valu", "fp32_insts_per_launch", info)
+    fp32_flop, _ = counted("batch_kernel", "valu", "fp32_flop_per_launch", info)
+    cycles = SIMDS * kernel_ms * 1e-3 * CLOCK_GHZ * 1e9
     kname = f"batch_kernel<6, 4, {info['obstacles_per_tile'] // 64}>"
     res = dict(
         metric=METRIC, value=value, unit="stage×edge evals/s", n_gpus=1, steps=args.steps,
@@ -440,10 +449,13 @@ def main():
                       frac_of_unpacked=achieved / REACHABLE_FP32_TFLOPS,
                       traffic=traffic, traffic_note=traffic_note,
                       algorithmic_bytes=sum(flops.bytes_instance(i.N, i.E, i.M) for i in c5),
-                      valu_busy=None if valu is None else valu * 4 / (SIMDS * kernel_ms * 1e-3 * CLOCK_GHZ * 1e9),
-                      valu_insts_per_launch=valu, kernel=kname, kernel_us=kernel_ms * 1e3,
+                      fp32_issue=None if fp32_insts is None else fp32_insts * 4 / cycles,
+                      valu_insts_x4_over_simd_cycles=None if valu is None else valu * 4 / cycles,
+                      executed_fp32_tflops=None if fp32_flop is None else fp32_flop / (kernel_ms * 1e-3) / 1e12,
+                      valu_insts_per_launch=valu, fp32_insts_per_launch=fp32_insts,
+                      kernel=kname, kernel_us=kernel_ms * 1e3,
                       kernel_launches_timed=launches, flop_per_launch=flop,
-                      source_sha256=source_hash("batch_kernel")),
+                      source_sha256=source_hash("batch_kernel", info)),
         wall_s=wall,
     )
     if args.screened:

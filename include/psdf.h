@@ -303,8 +303,9 @@ int psdf_batch(psdf_batch_plan* plan, const float* poses, const float* ax, const
                int32_t* edge, int32_t* obst, float* grad, uint64_t* keys, hipStream_t stream);
 
 /* Autotune the plan's launch shape on real inputs (same arguments as
- * psdf_batch): times each candidate (stages per work item x obstacles per
- * tile x persistent grid or one work-group per item) on `stream`,
+ * psdf_batch): times each candidate (stages per work item 1, 2, 4, ..., 64 x
+ * obstacles per tile 64 or 256 x persistent grid or one work-group per
+ * item) on `stream`,
  * synchronising it, keeps the fastest in the plan and in a
  * process-wide cache keyed by the batch's size signature (later plans of the
  * same signature start from it; with PSDF_TUNE_CACHE set to a file path the
@@ -314,6 +315,15 @@ int psdf_batch_autotune(psdf_batch_plan* plan, const float* poses, const float* 
                         const float* ay, const float* bx, const float* by,
                         const int32_t* obst_off, float* d, int32_t* edge, int32_t* obst,
                         float* grad, uint64_t* keys, hipStream_t stream, float* best_ms);
+
+/* Set the plan's launch shape explicitly (for sweeps and for reproducing a
+ * tuned shape): stages_per_item 1..64 (each instance's horizon is cut into
+ * ceil(N / stages_per_item) blocks of equal length), obstacles_per_tile 64
+ * or 256, direct 0 (persistent grid) or 1 (one work-group per item).  A
+ * captured graph is dropped and captured again on the next call.  Results
+ * do not depend on the shape. */
+int psdf_batch_set_shape(psdf_batch_plan* plan, int32_t stages_per_item,
+                         int32_t obstacles_per_tile, int32_t direct);
 
 /* The plan's current shape, work-item count, the largest grid of its
  * launches (one per footprint-size group) and whether items are dispatched

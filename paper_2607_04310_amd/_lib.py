@@ -85,6 +85,7 @@ _SIGS = {
     "psdf_mlp_train_step": (ctypes.c_int, [_VP, _VP, _VP, _I32, ctypes.c_float, _VP, _VP, _I32,
                                            _VP, _VP, ctypes.c_size_t, _VP]),
     "psdf_batch_plan_info": (ctypes.c_int, [_VP] + [ctypes.POINTER(_I32)] * 5),
+    "psdf_batch_set_shape": (ctypes.c_int, [_VP, _I32, _I32, _I32]),
     "psdf_bwd": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),
                                 ctypes.POINTER(PsdfParams), _VP, _VP, _VP, _VP]),
     "psdf_constraints": (ctypes.c_int, [_VP, _I32, _VP, _I32, ctypes.POINTER(PsdfEdges),

@@ -332,6 +332,11 @@ class Batch:
                                                   ctypes.byref(best)))
         return best.value
 
+    def set_shape(self, stages_per_item, obstacles_per_tile, direct=0):
+        """Set the launch shape explicitly (psdf_batch_set_shape)."""
+        _lib.check(_lib.lib().psdf_batch_set_shape(self.plan, int(stages_per_item),
+                                                   int(obstacles_per_tile), int(direct)))
+
     def info(self):
         vals = [ctypes.c_int32(0) for _ in range(5)]
         _lib.check(_lib.lib().psdf_batch_plan_info(self.plan, *[ctypes.byref(v) for v in vals]))

@@ -400,12 +400,14 @@ int build_items(psdf_batch_plan* p, Shape sh) {
     b.part_off = (int)part;
     b.circ_off = (int)circ;
     circ += d.M;
+    // ceil(N / sb) stage blocks of equal length (within one stage), so no
+    // block pays an item's setup for a short remainder
     const int nb = (d.N + sh.sb - 1) / sh.sb;
     part += (size_t)d.N * b.nt;
     if (d.M == 0) continue;
     const double per_edge = (double)d.E / std::max(1, d.M);
     for (int bi = 0; bi < nb; ++bi) {
-      const int s0 = bi * sh.sb, ns = std::min(sh.sb, d.N - s0);
+      const int s0 = (int)((long)bi * d.N / nb), ns = (int)((long)(bi + 1) * d.N / nb) - s0;
       for (int t = 0; t < b.nt; ++t) {
         const int o0 = t * tile, no = std::min(tile, d.M - o0);
         items.push_back(BatchItem{k, s0, ns, o0, no, t});
@@ -951,13 +953,14 @@ int psdf_batch_autotune(psdf_batch_plan* p, const float* poses, const float* ax,
   hipError_t err = hipEventCreate(&e0);
   if (err == hipSuccess) err = hipEventCreate(&e1);
   if (err != hipSuccess) return hip_status(err);
-  const int sbs[] = {1, 2, 4, 8, 16};
+  const int sbs[] = {1, 2, 4, 8, 16, 32, 64};
+  constexpr int kSb = sizeof(sbs) / sizeof(sbs[0]);
   const int nws[] = {1, 4};
   float best = INFINITY;
   Shape best_sh = p->shape;
   int rc = PSDF_OK;
-  for (int cand = 0; cand < 20 && rc == PSDF_OK; ++cand) {
-    const int nw = nws[(cand / 5) % 2], sb = sbs[cand % 5], direct = cand / 10;
+  for (int cand = 0; cand < 4 * kSb && rc == PSDF_OK; ++cand) {
+    const int nw = nws[(cand / kSb) % 2], sb = sbs[cand % kSb], direct = cand / (2 * kSb);
     {
       rc = build_items(p, Shape{sb, nw, direct});
       if (rc) break;
@@ -988,6 +991,17 @@ int psdf_batch_autotune(psdf_batch_plan* p, const float* poses, const float* ax,
   rc = run(p, poses, ax, ay, bx, by, off, d, edge, obst, grad, keys, stream, false);
   if (best_ms) *best_ms = best;
   return rc;
+}
+
+int psdf_batch_set_shape(psdf_batch_plan* p, int32_t stages_per_item, int32_t obstacles_per_tile,
+                         int32_t direct) {
+  clear_error();
+  if (!p) return set_error(PSDF_EINVAL, "plan is NULL");
+  if (stages_per_item < 1 || stages_per_item > kMaxStageBlock ||
+      (obstacles_per_tile != 64 && obstacles_per_tile != 256) || (direct != 0 && direct != 1))
+    return set_error(PSDF_EINVAL, "shape sb=%d tile=%d direct=%d (sb 1..%d, tile 64 or 256, direct 0 or 1)",
+                     stages_per_item, obstacles_per_tile, direct, kMaxStageBlock);
+  return build_items(p, Shape{stages_per_item, obstacles_per_tile / 64, direct});
 }
 
 int psdf_batch_plan_info(const psdf_batch_plan* p, int32_t* stages_per_item,

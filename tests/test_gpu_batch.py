@@ -128,6 +128,20 @@ def test_autotune_keeps_results(api, c4):
     b2.close()
 
 
+def test_explicit_shapes_keep_results(api, c4):
+    """psdf_batch_set_shape: every launch shape (stage blocks of any length,
+    cut evenly; 64- or 256-obstacle tiles; persistent or direct) gives the
+    same outputs bit for bit."""
+    b = api.Batch(c4[:48], graph=False)
+    ref = batch_out(b)
+    for sb, tile, direct in ((3, 64, 0), (7, 256, 1), (25, 256, 0), (64, 64, 1), (64, 256, 0)):
+        b.set_shape(sb, tile, direct)
+        info = b.info()
+        assert (info["stages_per_item"], info["obstacles_per_tile"], info["direct"]) == (sb, tile, direct)
+        assert_equal_outputs(batch_out(b), ref)
+    b.close()
+
+
 def test_batch_mixed_shapes_and_nan(api):
     rng = np.random.default_rng(77)
     insts = []

@@ -53,10 +53,11 @@ SIMDS, CLOCK_GHZ = 1024, 2.4
 CSRC = os.path.join("paper_2607_04310_amd", "csrc")
 # each kernel's own sources (code, instantiation, launch choice, build flags)
 KERNELS = {
-    # the batch kernel's code; its launch shape is hashed with it
+    # the batch kernel's code and its work items; its launch shape is hashed with it
     "batch_kernel": dict(
         sources=[os.path.join(CSRC, f) for f in (
-            "psdf_device.hpp", "psdf_winner.hpp", "psdf_batch.hpp", "psdf_host.hpp")]
+            "psdf_device.hpp", "psdf_winner.hpp", "psdf_batch.hpp", "psdf_batch.hip",
+            "psdf_host.hpp")]
         + [os.path.join("paper_2607_04310_amd", "build.py")],
         valu=os.path.join(ROOT, "profiles", "batch_kernel_c5_valu_counters.md"),
         hbm=os.path.join(ROOT, "profiles", "batch_kernel_c5_hbm_counters.md")),

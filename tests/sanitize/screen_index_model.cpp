@@ -1,0 +1,492 @@
+// Host model of the screening kernels' work-group index arithmetic, built
+// with the address and undefined-behaviour sanitizers by
+// tests/test_screen_index_model.py (test infrastructure only).
+//
+// It restates, for one 256-lane work-group executed phase by phase on the
+// host, every LDS and list index that psdf_screen.hpp and psdf_batch.hip
+// compute: the work-group reductions (block_sum_i32, block_min_u32,
+// block_scan, block_threshold with its alternating halves of the reduction
+// array), the pool and candidate compactions of screen_kernel, the seed and
+// candidate compaction of screen_bound_kernel, and the horizon list append
+// of horizon_kernel.  Every array has the kernel's size and checks its
+// index; the sweep covers every pool size the ABI allows (1..512), top-K
+// from 1 to past the pool's slot count, horizon lists of 0..2048 entries,
+// the three edge classes, and key sets with ties, unused slots and -inf.
+#include <algorithm>
+#include <cassert>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <random>
+#include <vector>
+
+namespace {
+
+constexpr int kThreads = 256, kWaves = 4;
+constexpr int kStageKeys = 8, kHorizonCap = kThreads * kStageKeys;   // 2048
+constexpr int kPoolCap = 512, kFeatSlots = 1024, kBoundCap = 512;
+constexpr int kHorizonPool = 512, kHorizonSplit = 16, kHorizonKeys = 4;
+constexpr uint32_t kUnused = 0xffffffffu;
+
+long g_checks = 0;
+
+[[noreturn]] void fail(const char* what, long i, long n) {
+  std::fprintf(stderr, "index out of range: %s[%ld], size %ld\n", what, i, n);
+  std::abort();
+}
+
+// An LDS / register array of the kernel's size with a checked index.
+template <class T, int N>
+struct Arr {
+  T v[N];
+  const char* name;
+  explicit Arr(const char* nm) : name(nm) { std::memset(v, 0, sizeof v); }
+  T& operator[](long i) {
+    ++g_checks;
+    if (i < 0 || i >= N) fail(name, i, N);
+    return v[i];
+  }
+};
+
+uint32_t orderable(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if (f != f) return 0u;
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+float from_orderable(uint32_t k) {
+  const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// ---- work-group reductions: one value per thread in, wave values written
+// by lane 0 of each wave to red[wave] (the kernels' layout)
+int block_sum_i32(const int* v, Arr<int, kThreads>& red) {
+  for (int w = 0; w < kWaves; ++w) {
+    int s = 0;
+    for (int l = 0; l < 64; ++l) s += v[64 * w + l];
+    red[w] = s;
+  }
+  int r = 0;
+  for (int i = 0; i < kWaves; ++i) r += red[i];
+  return r;
+}
+
+uint32_t block_min_u32(const uint32_t* v, Arr<uint32_t, kWaves>& red) {
+  for (int w = 0; w < kWaves; ++w) {
+    uint32_t m = kUnused;
+    for (int l = 0; l < 64; ++l) m = v[64 * w + l] < m ? v[64 * w + l] : m;
+    red[w] = m;
+  }
+  uint32_t r = red[0];
+  for (int i = 1; i < kWaves; ++i) r = red[i] < r ? red[i] : r;
+  return r;
+}
+
+// exclusive prefix per thread; scratch[wave] holds the wave totals
+void block_scan(const int* v, Arr<int, kThreads>& scratch, int* prefix, int* total) {
+  for (int w = 0; w < kWaves; ++w) {
+    int s = 0;
+    for (int l = 0; l < 64; ++l) s += v[64 * w + l];
+    scratch[w] = s;
+  }
+  int tot = 0;
+  for (int i = 0; i < kWaves; ++i) tot += scratch[i];
+  for (int t = 0; t < kThreads; ++t) {
+    int base = 0;
+    for (int i = 0; i < kWaves; ++i) base += i < (t >> 6) ? scratch[i] : 0;
+    int x = 0;   // inclusive wave scan of lanes <= t
+    for (int l = 64 * (t >> 6); l <= t; ++l) x += v[l];
+    prefix[t] = base + x - v[t];
+  }
+  *total = tot;
+}
+
+// block_threshold: keys k[t][q], slots q < nq looked at
+template <int KPT>
+uint32_t block_threshold(const uint32_t (*k)[KPT], int nq, uint32_t lo, uint32_t hi, int lo_n,
+                         int hi_n, Arr<int, kThreads>& red, int* rounds) {
+  int half = 0;
+  auto count = [&](uint32_t x) {
+    for (int w = 0; w < kWaves; ++w) {
+      int c = 0;
+      for (int q = 0; q < KPT; ++q) {
+        if (q >= nq) break;
+        for (int l = 0; l < 64; ++l) {
+          const uint32_t kk = k[64 * w + l][q];
+          c += (kk <= x && kk != kUnused) ? 1 : 0;
+        }
+      }
+      red[half * kWaves + w] = c;   // lane 0 of wave w
+    }
+    int t = 0;
+    for (int i = 0; i < kWaves; ++i) t += red[half * kWaves + i];
+    half ^= 1;
+    return t;
+  };
+  uint32_t a = lo, b = hi, res = a;
+  *rounds = 0;
+  const int c0 = count(a);
+  if (c0 < lo_n) {
+    for (;;) {
+      if (++*rounds > 200) { std::fprintf(stderr, "threshold search did not end\n"); std::abort(); }
+      if (b - a <= 1u) { res = a; break; }
+      uint32_t mid = orderable(0.5f * from_orderable(a) + 0.5f * from_orderable(b));
+      if (!(mid > a && mid < b)) mid = a + (b - a) / 2u;
+      const int c = count(mid);
+      if (c > hi_n) b = mid;
+      else if (c < lo_n) a = mid;
+      else { res = mid; break; }
+    }
+  }
+  return res;
+}
+
+template <int KPT>
+int count_le(const uint32_t (*k)[KPT], int nq, uint32_t x) {
+  int c = 0;
+  for (int t = 0; t < kThreads; ++t)
+    for (int q = 0; q < KPT && q < nq; ++q) c += (k[t][q] <= x && k[t][q] != kUnused) ? 1 : 0;
+  return c;
+}
+
+// random orderable keys: a spread of distances, ties, -inf, NaN
+uint32_t draw_key(std::mt19937& g, int mode) {
+  std::uniform_real_distribution<float> U(-2.f, 40.f);
+  switch (mode) {
+    case 0: return orderable(U(g));
+    case 1: return orderable((float)(g() % 7));                       // heavy ties
+    case 2: return (g() % 5 == 0) ? orderable(-INFINITY) : orderable(U(g));
+    case 3: return (g() % 11 == 0) ? 0u : orderable(U(g));            // NaN -> 0
+    default: return orderable(1.0f);                                 // all equal
+  }
+}
+
+// ---- one stage of screen_kernel (ranked top-K form): pool, scoring slots,
+// top-K, candidates, certificate loops
+template <int MI>
+void screen_stage(std::mt19937& g, int n_h, int P, int K, int mode, bool mlp) {
+  Arr<int, kThreads> scan("scan");
+  Arr<uint32_t, kWaves> red("red");
+  Arr<int, kPoolCap> pool_o("pool_o");
+  Arr<uint32_t, kPoolCap> pool_lb("pool_lb");
+  Arr<float, kPoolCap * MI> score("score");
+  Arr<uint32_t, kFeatSlots> feat("feat");
+  Arr<uint8_t, kPoolCap> cand("cand");
+  Arr<int, kPoolCap> cand_o("cand_o");
+  std::vector<int> obst_edges(n_h + 1);
+  for (auto& e : obst_edges) e = 1 + (int)(g() % MI);
+
+  static uint32_t k[kThreads][kStageKeys];
+  static int hidx[kThreads][kStageKeys];
+  const int nq = (n_h + kThreads - 1) / kThreads;
+  if (nq > kStageKeys) fail("stage key slot", nq, kStageKeys);
+  for (int t = 0; t < kThreads; ++t)
+    for (int q = 0; q < kStageKeys; ++q) {
+      const int idx = t + kThreads * q;
+      k[t][q] = kUnused;
+      hidx[t][q] = 0;
+      if (q < nq && idx < n_h) {
+        k[t][q] = draw_key(g, mode);
+        hidx[t][q] = idx;   // the list's local obstacle index (distinct)
+      }
+    }
+  P = P < 1 ? 1 : (P > kPoolCap ? kPoolCap : P);
+  uint32_t vmin[kThreads], vmax[kThreads];
+  int used[kThreads];
+  for (int t = 0; t < kThreads; ++t) {
+    vmin[t] = kUnused; vmax[t] = 0u; used[t] = 0;
+    for (int q = 0; q < kStageKeys; ++q) {
+      if (q >= nq) break;
+      if (k[t][q] != kUnused) {
+        vmin[t] = k[t][q] < vmin[t] ? k[t][q] : vmin[t];
+        vmax[t] = k[t][q] > vmax[t] ? k[t][q] : vmax[t];
+        ++used[t];
+      }
+    }
+  }
+  const uint32_t kmin = block_min_u32(vmin, red);
+  uint32_t nmax[kThreads];
+  for (int t = 0; t < kThreads; ++t) nmax[t] = ~vmax[t];
+  const uint32_t kmax = ~block_min_u32(nmax, red);
+  const int n_used = block_sum_i32(used, scan);
+  int rounds = 0;
+  const uint32_t T = n_used > P ? block_threshold<kStageKeys>(k, nq, kmin, kmax, (3 * P) / 4, P,
+                                                             scan, &rounds)
+                                : 0xfffffffeu;
+  const int cT = count_le<kStageKeys>(k, nq, T);
+  if (n_used > P && cT > P && T != kmin) { std::fprintf(stderr, "pool threshold above P\n"); std::abort(); }
+  int mine[kThreads], at[kThreads], pool_n = 0;
+  for (int t = 0; t < kThreads; ++t) {
+    mine[t] = 0;
+    for (int q = 0; q < kStageKeys; ++q) {
+      if (q >= nq) break;
+      mine[t] += k[t][q] <= T && k[t][q] != kUnused;
+    }
+  }
+  block_scan(mine, scan, at, &pool_n);
+  if (pool_n != cT) { std::fprintf(stderr, "pool count\n"); std::abort(); }
+  const bool overflow = pool_n > kPoolCap;
+  if (!overflow)
+    for (int t = 0; t < kThreads; ++t)
+      for (int q = 0; q < kStageKeys; ++q)
+        if (q < nq && k[t][q] <= T && k[t][q] != kUnused) {
+          pool_o[at[t]] = hidx[t][q];
+          pool_lb[at[t]] = k[t][q];
+          ++at[t];
+        }
+  if (overflow || pool_n == 0) return;
+
+  // ---- scoring slots
+  const int slots = pool_n * MI;
+  for (int t = 0; t < kThreads; ++t)
+    for (int e = t; e < kPoolCap * MI; e += kThreads) score[e] = INFINITY;
+  if (mlp) {
+    for (int c0 = 0; c0 < slots; c0 += kFeatSlots) {
+      const int cn = kFeatSlots < slots - c0 ? kFeatSlots : slots - c0;
+      for (int t = 0; t < kThreads; ++t)
+        for (int e = t; e < cn; e += kThreads) {
+          const int q = (c0 + e) / MI, j = (c0 + e) - q * MI;
+          const int o = pool_o[q];
+          if (j < obst_edges[o]) {
+            feat[e] = (uint32_t)(o * MI + j);
+            score[c0 + e] = 0.f;
+          }
+        }
+      for (int t = 0; t < kThreads; ++t) {
+        const int w = t >> 6, n = t & 15, gq = (t & 63) >> 4;
+        for (int base = w * 16; base < cn; base += 16 * kWaves) {
+          const int e = base + n;
+          const bool live = e < cn && score[c0 + e] != INFINITY;
+          if (gq == 0 && live) {
+            (void)feat[e];
+            score[c0 + e] = (float)(g() % 1000) / 100.f;
+          }
+        }
+      }
+    }
+  } else {
+    for (int t = 0; t < kThreads; ++t)
+      for (int e = t; e < slots; e += kThreads) {
+        const int q = e / MI, j = e - q * MI;
+        const int o = pool_o[q];
+        if (j < obst_edges[o]) score[e] = (float)(g() % 1000) / 100.f;
+      }
+  }
+
+  // ---- top-K edges -> candidates
+  constexpr int SPT = kPoolCap * MI / kThreads;
+  static uint32_t sk[kThreads][SPT];
+  int live[kThreads];
+  uint32_t smn[kThreads], smx[kThreads];
+  for (int t = 0; t < kThreads; ++t) {
+    live[t] = 0; smn[t] = kUnused; smx[t] = 0u;
+    for (int q = 0; q < SPT; ++q) {
+      const int e = t * SPT + q;
+      const float v = score[e];
+      sk[t][q] = (e < slots && v != INFINITY) ? orderable(v) : kUnused;
+      live[t] += sk[t][q] != kUnused;
+      if (sk[t][q] != kUnused) {
+        smn[t] = sk[t][q] < smn[t] ? sk[t][q] : smn[t];
+        smx[t] = sk[t][q] > smx[t] ? sk[t][q] : smx[t];
+      }
+    }
+  }
+  const uint32_t smin = block_min_u32(smn, red);
+  for (int t = 0; t < kThreads; ++t) nmax[t] = ~smx[t];
+  const uint32_t smax = ~block_min_u32(nmax, red);
+  const int n_live = block_sum_i32(live, scan);
+  const int KK = K < 1 ? 1 : K;
+  const uint32_t S = n_live > KK ? block_threshold<SPT>(sk, SPT, smin, smax, (7 * KK) / 8, KK, scan,
+                                                        &rounds)
+                                 : 0xfffffffeu;
+  for (int t = 0; t < kThreads; ++t)
+    for (int q = t; q < pool_n; q += kThreads) cand[q] = 0;
+  for (int t = 0; t < kThreads; ++t)
+    for (int q = 0; q < SPT; ++q)
+      if (sk[t][q] <= S && sk[t][q] != kUnused) cand[(t * SPT + q) / MI] = 1;
+  int cnt[kThreads], c_at[kThreads], n_cand = 0;
+  const int per = (pool_n + kThreads - 1) / kThreads;
+  for (int t = 0; t < kThreads; ++t) {
+    cnt[t] = 0;
+    for (int q = t * per; q < (pool_n < (t + 1) * per ? pool_n : (t + 1) * per); ++q) {
+      if (pool_lb[q] <= orderable(-INFINITY)) cand[q] = 1;
+      cnt[t] += cand[q];
+    }
+  }
+  block_scan(cnt, scan, c_at, &n_cand);
+  if (n_cand > pool_n) { std::fprintf(stderr, "more candidates than pool\n"); std::abort(); }
+  for (int t = 0; t < kThreads; ++t)
+    for (int q = t * per; q < (pool_n < (t + 1) * per ? pool_n : (t + 1) * per); ++q)
+      if (cand[q]) cand_o[c_at[t]++] = pool_o[q];
+  for (int c0 = 0; c0 < n_cand; c0 += kThreads)
+    for (int t = 0; t < kThreads; ++t)
+      if (c0 + t < n_cand) (void)cand_o[c0 + t];
+  for (int t = 0; t < kThreads; ++t)
+    for (int q = t; q < pool_n; q += kThreads) {
+      if (cand[q]) continue;
+      (void)pool_lb[q];
+      (void)pool_o[q];
+    }
+}
+
+// ---- one stage of screen_bound_kernel: seed, bar, candidate compaction
+void bound_stage(std::mt19937& g, int n_h, int mode) {
+  Arr<int, kThreads> scan("scan");
+  Arr<uint32_t, kWaves> red("red");
+  Arr<int, kBoundCap> cand_o("cand_o");
+  static uint32_t k[kThreads][kStageKeys];
+  static int hidx[kThreads][kStageKeys];
+  const int nq = (n_h + kThreads - 1) / kThreads;
+  uint32_t lo_t[kThreads];
+  for (int t = 0; t < kThreads; ++t) {
+    lo_t[t] = kUnused;
+    for (int q = 0; q < kStageKeys; ++q) {
+      const int idx = t + kThreads * q;
+      k[t][q] = kUnused;
+      hidx[t][q] = 0;
+      if (q < nq && idx < n_h) {
+        k[t][q] = draw_key(g, mode);
+        hidx[t][q] = idx;
+      }
+      lo_t[t] = k[t][q] < lo_t[t] ? k[t][q] : lo_t[t];
+    }
+  }
+  const uint32_t lo = block_min_u32(lo_t, red);
+  uint32_t slot_t[kThreads];
+  for (int t = 0; t < kThreads; ++t) {
+    int slot = 0x7fffffff;
+    for (int q = 0; q < kStageKeys; ++q)
+      if (q < nq && k[t][q] == lo && lo != kUnused) slot = slot < t + kThreads * q ? slot : t + kThreads * q;
+    slot_t[t] = (uint32_t)slot;
+  }
+  const int slot = (int)block_min_u32(slot_t, red);
+  int seed_o = -1;
+  uint32_t tkey = orderable(INFINITY);
+  if (lo != kUnused) {
+    const int owner = slot % kThreads, qs = slot / kThreads;
+    if (qs >= kStageKeys) fail("seed slot", qs, kStageKeys);
+    int o = 0;
+    for (int q = 0; q < kStageKeys; ++q)
+      if (q == qs) o = hidx[owner][q];
+    seed_o = o;
+    if (k[owner][qs] != lo) { std::fprintf(stderr, "seed is not the minimum\n"); std::abort(); }
+    tkey = orderable(std::fmax(from_orderable(lo) + (float)(g() % 100) / 50.f, 1e-3f));
+  }
+  int mine[kThreads], at[kThreads], n_cand = 0;
+  for (int t = 0; t < kThreads; ++t) {
+    mine[t] = 0;
+    for (int q = 0; q < kStageKeys; ++q)
+      if (q < nq && k[t][q] <= tkey && k[t][q] != kUnused && hidx[t][q] != seed_o) ++mine[t];
+  }
+  block_scan(mine, scan, at, &n_cand);
+  const bool overflow = n_cand > kBoundCap;
+  if (!overflow)
+    for (int t = 0; t < kThreads; ++t)
+      for (int q = 0; q < kStageKeys; ++q)
+        if (q < nq && k[t][q] <= tkey && k[t][q] != kUnused && hidx[t][q] != seed_o)
+          cand_o[at[t]++] = hidx[t][q];
+  if (!overflow)
+    for (int c0 = 0; c0 < n_cand; c0 += kThreads)
+      for (int t = 0; t < kThreads; ++t)
+        if (c0 + t < n_cand) (void)cand_o[c0 + t];
+}
+
+// ---- horizon_kernel: every block of an instance appends its lowest keys
+void horizon_instance(std::mt19937& g, int M, int mode) {
+  std::vector<int> appended(M, 0);
+  int hcount = 0;
+  const int chunk = (M + kHorizonSplit - 1) / kHorizonSplit;
+  if (chunk > kThreads * kHorizonKeys) fail("horizon chunk", chunk, kThreads * kHorizonKeys);
+  Arr<int, kThreads> scan("scan");
+  Arr<uint32_t, kWaves> red("red");
+  std::vector<int> order(kHorizonSplit);
+  for (int i = 0; i < kHorizonSplit; ++i) order[i] = i;
+  std::shuffle(order.begin(), order.end(), g);   // blocks run in any order
+  for (int part : order) {
+    const int o0 = part * chunk, o1 = M < o0 + chunk ? M : o0 + chunk;
+    if (o0 >= o1) continue;
+    static uint32_t k[kThreads][kHorizonKeys];
+    uint32_t mn[kThreads], mx[kThreads];
+    int used[kThreads];
+    for (int t = 0; t < kThreads; ++t) {
+      mn[t] = kUnused; mx[t] = 0u; used[t] = 0;
+      for (int q = 0; q < kHorizonKeys; ++q) {
+        const int o = o0 + t + kThreads * q;
+        k[t][q] = o < o1 ? draw_key(g, mode) : kUnused;
+        if (k[t][q] != kUnused) {
+          mn[t] = k[t][q] < mn[t] ? k[t][q] : mn[t];
+          mx[t] = k[t][q] > mx[t] ? k[t][q] : mx[t];
+          ++used[t];
+        }
+      }
+    }
+    const uint32_t kmin = block_min_u32(mn, red);
+    uint32_t nmx[kThreads];
+    for (int t = 0; t < kThreads; ++t) nmx[t] = ~mx[t];
+    const uint32_t kmax = ~block_min_u32(nmx, red);
+    const int n_used = block_sum_i32(used, scan);
+    constexpr int P = kHorizonPool / kHorizonSplit;
+    int rounds = 0;
+    const uint32_t T = n_used > P ? block_threshold<kHorizonKeys>(k, kHorizonKeys, kmin, kmax, P / 2,
+                                                                  P, scan, &rounds)
+                                  : 0xfffffffeu;
+    int mine[kThreads], at[kThreads], total = 0;
+    for (int t = 0; t < kThreads; ++t) {
+      mine[t] = 0;
+      for (int q = 0; q < kHorizonKeys; ++q)
+        if (k[t][q] != kUnused && k[t][q] <= T) ++mine[t];
+    }
+    block_scan(mine, scan, at, &total);
+    const int base = hcount;   // atomicAdd on the instance's count
+    hcount += total;
+    for (int t = 0; t < kThreads; ++t)
+      for (int q = 0; q < kHorizonKeys; ++q)
+        if (k[t][q] != kUnused && k[t][q] <= T) {
+          const int slot = base + at[t]++;
+          if (slot < 0 || slot >= M) fail("hlist (instance's M slots)", slot, M);
+          const int o = o0 + t + kThreads * q;
+          if (appended[o]++) { std::fprintf(stderr, "obstacle appended twice\n"); std::abort(); }
+        }
+  }
+}
+
+}  // namespace
+
+int main() {
+  std::mt19937 g(12345);
+  long stages = 0;
+  const int edge_h[] = {0, 1, 63, 64, 255, 256, 257, 511, 1024, 2047, 2048};
+  const int edge_p[] = {1, 2, 3, 127, 128, 255, 256, 511, 512};
+  for (int mode = 0; mode < 5; ++mode) {
+    for (int n_h : edge_h)
+      for (int P : edge_p)
+        for (int K : {1, 7, 256, 2048, 8192}) {
+          const bool mlp = (n_h + P + K + mode) % 2 == 0;
+          screen_stage<4>(g, n_h, P, K, mode, mlp);
+          screen_stage<8>(g, n_h, P, K, mode, !mlp);
+          screen_stage<16>(g, n_h, P, K, mode, mlp);
+          stages += 3;
+        }
+    for (int trial = 0; trial < 400; ++trial) {
+      const int n_h = (int)(g() % (kHorizonCap + 1));
+      const int P = 1 + (int)(g() % kPoolCap);
+      const int K = 1 + (int)(g() % 8192);
+      screen_stage<4>(g, n_h, P, K, mode, trial % 2);
+      screen_stage<16>(g, n_h, P, K, mode, trial % 3 == 0);
+      stages += 2;
+    }
+    for (int n_h : edge_h) { bound_stage(g, n_h, mode); ++stages; }
+    for (int trial = 0; trial < 400; ++trial) {
+      bound_stage(g, (int)(g() % (kHorizonCap + 1)), mode);
+      ++stages;
+    }
+    for (int M : {1, 15, 16, 17, 512, 4096, 16383, 16384}) horizon_instance(g, M, mode);
+  }
+  std::printf("ok %ld stages, %ld checked indices\n", stages, g_checks);
+  return 0;
+}

@@ -479,8 +479,8 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
   }
 }
 
-// Certified screening by the bound alone (no ranking), one work-group per
-// stage.  The obstacle with the smallest lower bound (the seed) is evaluated
+// Certified screening by the bound alone (no ranking), one wave per stage.
+// The obstacle with the smallest lower bound (the seed) is evaluated
 // exactly; its sd is an upper bound of the stage's minimum phi, so the bar
 // T = max(sd_seed, tau_sep) satisfies T >= max(phi, tau_sep), and every
 // obstacle whose bound does not exceed T is evaluated exactly.  Every
@@ -491,18 +491,19 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
 // unusable horizon list.  The candidate set is the smallest that any
 // certificate built on these bounds can use when the seed is the winner or
 // the stage penetrates (T = tau_sep then).
+//
+// One wave per stage: the list is read twice (the bounds are recomputed in
+// the second pass instead of held in registers), the seed comes from a
+// wave minimum of (bound key, list slot), the candidates are compacted into
+// LDS with ballots, and no work-group barrier is needed.
 constexpr int kBoundCap = 512;   // candidates per stage (more: full evaluation)
 
 template <int MF, int MI>
-__global__ __launch_bounds__(kScreenThreads) void screen_bound_kernel(ScreenArgs A) {
-  __shared__ int scan[kScreenThreads];
-  __shared__ uint32_t red[kScreenThreads / 64];
+__global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
   __shared__ int cand_o[kBoundCap];
-  __shared__ uint64_t wkey[kScreenThreads / 64];
   __shared__ float4 rf[MF];
-  __shared__ uint64_t s_seed_key;
 
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lane = threadIdx.x;
   const int s = A.stages[blockIdx.x];
   const int inst = __builtin_amdgcn_readfirstlane(A.stage_inst[s]);
   const BatchInst in = A.insts[inst];
@@ -512,13 +513,13 @@ __global__ __launch_bounds__(kScreenThreads) void screen_bound_kernel(ScreenArgs
   float sn, cs;
   sincosf(p[2], &sn, &cs);
   const bool pose_ok = isfinite(px) && isfinite(py) && isfinite(cs) && isfinite(sn);
-  if (tid < MF) rf[tid] = rotated_slot(F, tid, cs, sn);   // read after the reductions below
+  if (lane < MF) rf[lane] = rotated_slot(F, lane, cs, sn);
   const int Eend = in.edge_off + in.E;
   const int* off = A.off + in.obst_off;
 
   const int hc = A.hcount[inst];
   if (hc < 0 || hc > kHorizonCap) {
-    if (tid == 0) {
+    if (lane == 0) {
       A.keys[s] = kEmptyKey;
       if (A.stage_cand) A.stage_cand[s] = 0;
       if (A.stage_cert) A.stage_cert[s] = 0;
@@ -527,81 +528,67 @@ __global__ __launch_bounds__(kScreenThreads) void screen_bound_kernel(ScreenArgs
     }
     return;
   }
-
-  // ---- bounding-circle lower bounds over the horizon list (as screen_kernel)
-  uint32_t k[kStageKeys];
-  int hidx[kStageKeys];
-  const int n_h = hc;
   const float4* hl = A.hlist + in.circ_off;
   const float lb_off = F.rmax + kLbGamma;
-  const int nq = (n_h + kScreenThreads - 1) / kScreenThreads;
-  uint32_t lo = 0xffffffffu;
-#pragma unroll
-  for (int q = 0; q < kStageKeys; ++q) {
-    const int idx = tid + kScreenThreads * q;
-    uint32_t key = 0xffffffffu;
-    hidx[q] = 0;
-    if (q < nq && idx < n_h) {
-      const float4 c = hl[idx];
-      hidx[q] = __float_as_int(c.w);
-      const float dx = px - c.x, dy = py - c.y;
-      const float lbv = sqrtf(fmaf(dx, dx, dy * dy)) - c.z - lb_off;
-      key = orderable(pose_ok ? lbv : -__builtin_huge_valf());
-    }
-    k[q] = key;
-    lo = min(lo, key);
+  // bounding-circle lower bound of list entry idx (as screen_kernel), and
+  // its obstacle (local index)
+  auto lb_key = [&](int idx, int& o) {
+    const float4 c = hl[idx];
+    o = __float_as_int(c.w);
+    const float dx = px - c.x, dy = py - c.y;
+    const float lbv = sqrtf(fmaf(dx, dx, dy * dy)) - c.z - lb_off;
+    return orderable(pose_ok ? lbv : -__builtin_huge_valf());
+  };
+
+  // ---- pass 1: the seed, the smallest bound (lowest list slot on ties)
+  uint64_t lo = ~0ull;
+  for (int idx = lane; idx < hc; idx += 64) {
+    int o;
+    const uint64_t v = ((uint64_t)lb_key(idx, o) << 32) | (uint32_t)idx;
+    lo = v < lo ? v : lo;
   }
-  // ---- the seed: the smallest bound, lowest list slot on ties (its
-  // obstacle index is taken from the thread that holds it)
-  lo = block_min_u32(lo, red);
-  int slot = 0x7fffffff;
-#pragma unroll
-  for (int q = 0; q < kStageKeys; ++q)
-    if (q < nq && k[q] == lo && lo != 0xffffffffu) slot = min(slot, tid + kScreenThreads * q);
-  slot = (int)block_min_u32((uint32_t)slot, red);
+  lo = wave_min_u64(lo);
+  wave_sync();   // rf is written
   uint64_t seed_key = kEmptyKey;
   int seed_o = -1;
-  if (lo != 0xffffffffu) {
-    // the slot's owner evaluates the seed; everyone reads its key from LDS
-    if (tid == slot % kScreenThreads) {
-      int o = 0;
-#pragma unroll
-      for (int q = 0; q < kStageKeys; ++q)
-        if (q == slot / kScreenThreads) o = hidx[q];
-      const int a = off[o], mi = off[o + 1] - a;
+  if (lo != ~0ull) {
+    seed_o = __float_as_int(hl[(int)(uint32_t)lo].w);
+    uint32_t kk = 0u;
+    if (lane == 0) {
+      const int a = off[seed_o], mi = off[seed_o + 1] - a;
       Obst<MI> ob;
       load_obstacle<MI>(ob, A.ax, A.ay, A.bx, A.by, in.edge_off + a, mi, Eend, F.eps);
       if (a < 0) ob.bad = true;
-      const uint32_t kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, rf, px, py)) : 0u;
-      s_seed_key = ((uint64_t)kk << 32) | (uint32_t)o;
+      kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, rf, px, py)) : 0u;
     }
-    __syncthreads();
-    seed_key = s_seed_key;
-    seed_o = (int)(seed_key & 0xffffffffu);
+    kk = lane_u32(kk, 0);
+    seed_key = ((uint64_t)kk << 32) | (uint32_t)seed_o;
   }
-  // ---- the bar and the candidates (every list entry with LB <= T but the seed)
+
+  // ---- pass 2: every other list entry with LB <= T, compacted into LDS
   const float phi1 = seed_key == kEmptyKey ? __builtin_huge_valf()
                                            : from_orderable((uint32_t)(seed_key >> 32));
   const uint32_t tkey = orderable(fmaxf(phi1, F.tau_sep));
-  int mine = 0;
-#pragma unroll
-  for (int q = 0; q < kStageKeys; ++q)
-    if (q < nq && k[q] <= tkey && k[q] != 0xffffffffu && hidx[q] != seed_o) ++mine;
+  const uint64_t below = (1ull << lane) - 1ull;
   int n_cand = 0;
-  int at = block_scan(mine, scan, &n_cand);
-  const bool overflow = n_cand > kBoundCap;
-  if (!overflow) {
-#pragma unroll
-    for (int q = 0; q < kStageKeys; ++q)
-      if (q < nq && k[q] <= tkey && k[q] != 0xffffffffu && hidx[q] != seed_o) cand_o[at++] = hidx[q];
+  for (int i0 = 0; i0 < hc; i0 += 64) {
+    const int idx = i0 + lane;
+    int o = -1;
+    bool take = false;
+    if (idx < hc) take = lb_key(idx, o) <= tkey && o != seed_o;
+    const uint64_t m = __ballot(take);
+    const int at = n_cand + (int)__popcll(m & below);
+    if (take && at < kBoundCap) cand_o[at] = o;
+    n_cand += (int)__popcll(m);
   }
-  __syncthreads();
+  const bool overflow = n_cand > kBoundCap;
+  wave_sync();
 
   // ---- exact evaluation of the candidates (lane <-> candidate)
-  uint64_t best = seed_key;
+  uint64_t keyK = seed_key;
   if (!overflow) {
-    for (int c0 = 0; c0 < n_cand; c0 += kScreenThreads) {
-      const int c = c0 + tid;
+    for (int c0 = 0; c0 < n_cand; c0 += 64) {
+      const int c = c0 + lane;
       const bool act = c < n_cand;
       int e0 = 0, mi = 0, o = 0;
       if (act) {
@@ -617,20 +604,15 @@ __global__ __launch_bounds__(kScreenThreads) void screen_bound_kernel(ScreenArgs
       if (act && mi != 0) kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, rf, px, py)) : 0u;
       const uint64_t key = kk == 0xffffffffu ? kEmptyKey : (((uint64_t)kk << 32) | (uint32_t)o);
       const uint64_t wmin = fw_min_u64(key);
-      best = wmin < best ? wmin : best;
+      keyK = wmin < keyK ? wmin : keyK;
     }
   }
-  if (lane == 0) wkey[w] = best;
-  __syncthreads();
-  uint64_t keyK = wkey[0];
-#pragma unroll
-  for (int i = 1; i < kScreenThreads / 64; ++i) keyK = wkey[i] < keyK ? wkey[i] : keyK;
   // ---- certificate: the list entries left out have LB > T by construction;
   // the obstacles outside the list have the instance bound
   const uint32_t rest = A.hrest[inst];
   const bool cert = (keyK != kEmptyKey && (keyK >> 32) == 0)          // NaN wins anyway
                     || (!overflow && (rest == 0xffffffffu || rest > tkey));
-  if (tid == 0) {
+  if (lane == 0) {
     A.keys[s] = keyK;
     if (A.stage_cand) A.stage_cand[s] = overflow ? 0 : n_cand + (seed_o >= 0 ? 1 : 0);
     if (A.stage_cert) A.stage_cert[s] = cert ? 1 : 0;
@@ -704,9 +686,9 @@ hipError_t launch_screen_mf(int mi_class, int grid, const ScreenArgs& a, hipStre
 
 template <int MF>
 hipError_t launch_screen_bound_mf(int mi_class, int grid, const ScreenArgs& a, hipStream_t st) {
-  if (mi_class == 4) screen_bound_kernel<MF, 4><<<grid, kScreenThreads, 0, st>>>(a);
-  else if (mi_class == 8) screen_bound_kernel<MF, 8><<<grid, kScreenThreads, 0, st>>>(a);
-  else screen_bound_kernel<MF, 16><<<grid, kScreenThreads, 0, st>>>(a);
+  if (mi_class == 4) screen_bound_kernel<MF, 4><<<grid, 64, 0, st>>>(a);
+  else if (mi_class == 8) screen_bound_kernel<MF, 8><<<grid, 64, 0, st>>>(a);
+  else screen_bound_kernel<MF, 16><<<grid, 64, 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -334,66 +334,66 @@ void screen_stage(std::mt19937& g, int n_h, int P, int K, int mode, bool mlp) {
     }
 }
 
-// ---- one stage of screen_bound_kernel: seed, bar, candidate compaction
+// ---- one stage of screen_bound_kernel (one wave): seed, bar, candidate
+// compaction by ballots into the LDS list
 void bound_stage(std::mt19937& g, int n_h, int mode) {
-  Arr<int, kThreads> scan("scan");
-  Arr<uint32_t, kWaves> red("red");
   Arr<int, kBoundCap> cand_o("cand_o");
-  static uint32_t k[kThreads][kStageKeys];
-  static int hidx[kThreads][kStageKeys];
-  const int nq = (n_h + kThreads - 1) / kThreads;
-  uint32_t lo_t[kThreads];
-  for (int t = 0; t < kThreads; ++t) {
-    lo_t[t] = kUnused;
-    for (int q = 0; q < kStageKeys; ++q) {
-      const int idx = t + kThreads * q;
-      k[t][q] = kUnused;
-      hidx[t][q] = 0;
-      if (q < nq && idx < n_h) {
-        k[t][q] = draw_key(g, mode);
-        hidx[t][q] = idx;
-      }
-      lo_t[t] = k[t][q] < lo_t[t] ? k[t][q] : lo_t[t];
+  std::vector<uint32_t> key(n_h);
+  std::vector<int> obst(n_h);
+  for (int i = 0; i < n_h; ++i) {
+    key[i] = draw_key(g, mode);
+    obst[i] = i;   // the list holds each obstacle once
+  }
+  // pass 1: wave minimum of (key << 32 | slot), lane l taking slots l, l + 64, ...
+  uint64_t lane_lo[64];
+  for (int l = 0; l < 64; ++l) {
+    lane_lo[l] = ~0ull;
+    for (int idx = l; idx < n_h; idx += 64) {
+      const uint64_t v = ((uint64_t)key[idx] << 32) | (uint32_t)idx;
+      lane_lo[l] = v < lane_lo[l] ? v : lane_lo[l];
     }
   }
-  const uint32_t lo = block_min_u32(lo_t, red);
-  uint32_t slot_t[kThreads];
-  for (int t = 0; t < kThreads; ++t) {
-    int slot = 0x7fffffff;
-    for (int q = 0; q < kStageKeys; ++q)
-      if (q < nq && k[t][q] == lo && lo != kUnused) slot = slot < t + kThreads * q ? slot : t + kThreads * q;
-    slot_t[t] = (uint32_t)slot;
-  }
-  const int slot = (int)block_min_u32(slot_t, red);
+  uint64_t lo = ~0ull;
+  for (int l = 0; l < 64; ++l) lo = lane_lo[l] < lo ? lane_lo[l] : lo;
   int seed_o = -1;
   uint32_t tkey = orderable(INFINITY);
-  if (lo != kUnused) {
-    const int owner = slot % kThreads, qs = slot / kThreads;
-    if (qs >= kStageKeys) fail("seed slot", qs, kStageKeys);
-    int o = 0;
-    for (int q = 0; q < kStageKeys; ++q)
-      if (q == qs) o = hidx[owner][q];
-    seed_o = o;
-    if (k[owner][qs] != lo) { std::fprintf(stderr, "seed is not the minimum\n"); std::abort(); }
-    tkey = orderable(std::fmax(from_orderable(lo) + (float)(g() % 100) / 50.f, 1e-3f));
+  if (lo != ~0ull) {
+    const int slot = (int)(uint32_t)lo;
+    if (slot < 0 || slot >= n_h) fail("seed slot", slot, n_h);
+    seed_o = obst[slot];
+    for (int i = 0; i < n_h; ++i)
+      if (key[i] < key[slot] || (key[i] == key[slot] && i < slot)) {
+        std::fprintf(stderr, "seed is not the first minimum\n");
+        std::abort();
+      }
+    tkey = orderable(std::fmax(from_orderable(key[slot]) + (float)(g() % 100) / 50.f, 1e-3f));
   }
-  int mine[kThreads], at[kThreads], n_cand = 0;
-  for (int t = 0; t < kThreads; ++t) {
-    mine[t] = 0;
-    for (int q = 0; q < kStageKeys; ++q)
-      if (q < nq && k[t][q] <= tkey && k[t][q] != kUnused && hidx[t][q] != seed_o) ++mine[t];
+  // pass 2: chunks of 64 slots, ballot, prefix of the lanes below
+  int n_cand = 0, written = 0;
+  for (int i0 = 0; i0 < n_h; i0 += 64) {
+    uint64_t m = 0;
+    bool take[64];
+    for (int l = 0; l < 64; ++l) {
+      const int idx = i0 + l;
+      take[l] = idx < n_h && key[idx] <= tkey && obst[idx] != seed_o;
+      if (take[l]) m |= 1ull << l;
+    }
+    for (int l = 0; l < 64; ++l) {
+      const uint64_t below = (1ull << l) - 1ull;
+      const int at = n_cand + __builtin_popcountll(m & below);
+      if (take[l] && at < kBoundCap) { cand_o[at] = obst[i0 + l]; ++written; }
+    }
+    n_cand += __builtin_popcountll(m);
   }
-  block_scan(mine, scan, at, &n_cand);
+  int ref = 0;
+  for (int i = 0; i < n_h; ++i) ref += key[i] <= tkey && obst[i] != seed_o;
+  if (ref != n_cand) { std::fprintf(stderr, "candidate count\n"); std::abort(); }
   const bool overflow = n_cand > kBoundCap;
+  if (!overflow && written != n_cand) { std::fprintf(stderr, "candidates written\n"); std::abort(); }
   if (!overflow)
-    for (int t = 0; t < kThreads; ++t)
-      for (int q = 0; q < kStageKeys; ++q)
-        if (q < nq && k[t][q] <= tkey && k[t][q] != kUnused && hidx[t][q] != seed_o)
-          cand_o[at[t]++] = hidx[t][q];
-  if (!overflow)
-    for (int c0 = 0; c0 < n_cand; c0 += kThreads)
-      for (int t = 0; t < kThreads; ++t)
-        if (c0 + t < n_cand) (void)cand_o[c0 + t];
+    for (int c0 = 0; c0 < n_cand; c0 += 64)
+      for (int l = 0; l < 64; ++l)
+        if (c0 + l < n_cand) (void)cand_o[c0 + l];
 }
 
 // ---- horizon_kernel: every block of an instance appends its lowest keys

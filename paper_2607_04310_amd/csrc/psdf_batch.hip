@@ -15,220 +15,9 @@
 #include "psdf_batch.hpp"
 #include "psdf_host.hpp"
 #include "psdf_screen.hpp"
+#include "psdf_horizon.hpp"
 
 namespace psdf {
-
-// Bounding circle (cx, cy, r, 0) of an obstacle with edges [a, b) of an
-// instance, from its edges in one pass, r inflated to cover rounding.  An
-// empty obstacle gets cx = NaN (never screened); an invalid one (bad range,
-// more than MI edges or a non-finite coordinate) r = +inf (always a
-// candidate), and so does an open chain of two or more edges: the axis test
-// sees the convex hull of its points, whose closing edge gives no axis, so
-// the certificate's separation argument does not hold for it.  All MI edge
-// loads are issued together (indices clamped into the obstacle's range);
-// edges past the obstacle's own count add nothing.
-template <int MI>
-__device__ float4 obstacle_circle(const BatchInst& in, const float* __restrict__ ax,
-                                  const float* __restrict__ ay, const float* __restrict__ bx,
-                                  const float* __restrict__ by, int a, int b) {
-  const int mi = b - a;
-  float4 c = make_float4(__builtin_nanf(""), 0.f, 0.f, 0.f);
-  if (mi != 0) {
-    c = make_float4(0.f, 0.f, __builtin_huge_valf(), 0.f);
-    if (mi > 0 && mi <= MI && a >= 0 && b <= in.E) {
-      float px[2 * MI], py[2 * MI];
-#pragma unroll
-      for (int j = 0; j < MI; ++j) {
-        const int e = in.edge_off + a + min(j, mi - 1);
-        px[2 * j] = ax[e]; py[2 * j] = ay[e];
-        px[2 * j + 1] = bx[e]; py[2 * j + 1] = by[e];
-      }
-      float sx = 0.f, sy = 0.f;
-      bool finite = true;
-#pragma unroll
-      for (int j = 0; j < MI; ++j) {
-        if (j < mi) {
-          sx += px[2 * j] + px[2 * j + 1];
-          sy += py[2 * j] + py[2 * j + 1];
-          finite = finite && isfinite(px[2 * j]) && isfinite(py[2 * j]) &&
-                   isfinite(px[2 * j + 1]) && isfinite(py[2 * j + 1]);
-        }
-      }
-      // closed polygon: B_j == A_{j+1} bitwise, around the boundary
-      bool closed = mi >= 3;
-#pragma unroll
-      for (int j = 0; j < MI; ++j)
-        if (j < mi) {
-          const int nx = j + 1 < mi ? j + 1 : 0;
-          float ax1 = px[0], ay1 = py[0];
-#pragma unroll
-          for (int q = 1; q < MI; ++q)
-            if (q == nx) { ax1 = px[2 * q]; ay1 = py[2 * q]; }
-          closed = closed && __float_as_uint(px[2 * j + 1]) == __float_as_uint(ax1) &&
-                   __float_as_uint(py[2 * j + 1]) == __float_as_uint(ay1);
-        }
-      if (finite && (closed || mi == 1)) {
-        const float cx = sx / (2.f * mi), cy = sy / (2.f * mi);
-        float r2 = 0.f;
-#pragma unroll
-        for (int j = 0; j < 2 * MI; ++j)
-          if (j < 2 * mi) {
-            const float dx = px[j] - cx, dy = py[j] - cy;
-            r2 = fmaxf(r2, fmaf(dx, dx, dy * dy));
-          }
-        c = make_float4(cx, cy, sqrtf(r2) * (1.0f + 1e-6f) + 1e-6f, 0.f);
-      }
-    }
-  }
-  return c;
-}
-
-// Horizon list of each instance: every stage position of the instance lies
-// within R of the centre c_p of their bounding box, so for every stage s and
-// obstacle i
-//   |p_s - c_i| - r_i - rmax - gamma >= |c_p - c_i| - R - r_i - rmax - gamma =: hb_i,
-// a lower bound of the stage's circle bound and hence of sd_i.  Grid
-// (kHorizonSplit, instances): work-group c takes the c-th block of the
-// instance's obstacles, computes their bounding circles (obstacle_circle),
-// and appends its (about) kHorizonPool / kHorizonSplit lowest-hb obstacles to
-// the list as (circle, index); the list thus holds every obstacle among the
-// kHorizonPool / kHorizonSplit lowest of the whole instance.  The smallest hb
-// left out (atomic minimum over the blocks) bounds every excluded obstacle at
-// every stage.  A non-finite stage position disables the list (-1); a list
-// longer than kHorizonCap (tie blocks) is not used by the stage pass either:
-// the instance's stages then take the full evaluation.  On entry the
-// instance's count is 0 and its bound +inf (plan creation, then the finish
-// kernel of every screened call).  With a network the grid has one more
-// column, whose first work-group builds the network's fragment table.
-// List length: each stage's lower-bound pass reads the whole list, and the
-// bound of the obstacles left out must stay above the stages' minima for the
-// certificate (on c5, 512 certifies every stage; 256 fails 6 % of them).
-constexpr int kHorizonPool = 512;
-constexpr int kHorizonSplit = 16;
-constexpr int kHorizonKeys = kScreenMaxM / kHorizonSplit / kScreenThreads;   // 4
-
-template <int MI>
-__global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
-    const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
-    const float* __restrict__ poses, const float* __restrict__ ax, const float* __restrict__ ay,
-    const float* __restrict__ bx, const float* __restrict__ by, const int* __restrict__ off,
-    float4* __restrict__ hlist, int* __restrict__ hcount, uint32_t* __restrict__ hrest,
-    const float* __restrict__ theta, uint4* __restrict__ frag) {
-  __shared__ int scan[kScreenThreads];
-  __shared__ uint32_t red[kScreenThreads / 64];
-  __shared__ int s_base;
-  if (blockIdx.x == kHorizonSplit) {
-    // the extra column: the screener network's per-lane weight fragments,
-    // once per call (one wave), so that every stage's work-group reads them
-    // with coalesced vector loads instead of gathering the parameters
-    if (blockIdx.y == 0 && theta && threadIdx.x < 64) {
-      MlpFrag f;
-      mlp_load(theta, f);
-      mlp_frag_store(f, frag);
-    }
-    return;
-  }
-  const int inst = blockIdx.y, part = blockIdx.x, tid = threadIdx.x;
-  const BatchInst in = insts[inst];
-  const FpConst& F = fps[inst];
-  const int M = in.M;
-  const int chunk = (M + kHorizonSplit - 1) / kHorizonSplit;
-  const int o0 = part * chunk, o1 = min(M, o0 + chunk);
-  if (o0 >= o1) return;   // empty block: nothing to add
-  // bounding box of the stage positions (orderable keys: min of x, y, -x, -y)
-  uint32_t bx0 = 0xffffffffu, by0 = 0xffffffffu, bx1 = 0xffffffffu, by1 = 0xffffffffu;
-  int bad = 0;
-  for (int t = tid; t < in.N; t += kScreenThreads) {
-    const float* p = poses + 3 * (in.pose_off + t);
-    const float x = p[0], y = p[1];
-    if (!(isfinite(x) && isfinite(y))) { bad = 1; continue; }
-    bx0 = min(bx0, orderable(x)); by0 = min(by0, orderable(y));
-    bx1 = min(bx1, orderable(-x)); by1 = min(by1, orderable(-y));
-  }
-  bad = block_sum_i32(bad, scan);
-  bx0 = block_min_u32(bx0, red); by0 = block_min_u32(by0, red);
-  bx1 = block_min_u32(bx1, red); by1 = block_min_u32(by1, red);
-  if (bad > 0 || in.N == 0) {
-    if (tid == 0 && part == 0) hcount[inst] = -1;
-    return;
-  }
-  const float cx = 0.5f * (from_orderable(bx0) - from_orderable(bx1));
-  const float cy = 0.5f * (from_orderable(by0) - from_orderable(by1));
-  // R = max distance of a stage position from the centre (max via the
-  // orderable image of -d)
-  uint32_t nr = 0xffffffffu;
-  for (int t = tid; t < in.N; t += kScreenThreads) {
-    const float* p = poses + 3 * (in.pose_off + t);
-    const float dx = p[0] - cx, dy = p[1] - cy;
-    nr = min(nr, orderable(-sqrtf(fmaf(dx, dx, dy * dy))));
-  }
-  nr = block_min_u32(nr, red);
-  const float R = -from_orderable(nr) * (1.0f + 1e-6f) + 1e-6f;
-  const float hoff = R + F.rmax + kLbGamma;
-  uint32_t k[kHorizonKeys];
-  float4 cq[kHorizonKeys];
-  uint32_t kmin = 0xffffffffu, kmax = 0u;
-  int used = 0;
-  // the edge ranges of the thread's obstacles, loaded together (an index
-  // past the block is clamped to its last obstacle, o1 - 1 < M)
-  int ea[kHorizonKeys], eb[kHorizonKeys];
-#pragma unroll
-  for (int q = 0; q < kHorizonKeys; ++q) {
-    const int o = min(o0 + tid + kScreenThreads * q, o1 - 1);
-    ea[q] = off[in.obst_off + o];
-    eb[q] = off[in.obst_off + o + 1];
-  }
-#pragma unroll
-  for (int q = 0; q < kHorizonKeys; ++q) {
-    const int o = o0 + tid + kScreenThreads * q;
-    uint32_t key = 0xffffffffu;
-    cq[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (o < o1) {
-      const float4 c = obstacle_circle<MI>(in, ax, ay, bx, by, ea[q], eb[q]);
-      cq[q] = c;
-      if (c.x == c.x) {
-        const float dx = cx - c.x, dy = cy - c.y;
-        key = orderable(sqrtf(fmaf(dx, dx, dy * dy)) - c.z - hoff);
-      }
-    }
-    k[q] = key;
-    if (key != 0xffffffffu) { kmin = min(kmin, key); kmax = max(kmax, key); ++used; }
-  }
-  kmin = block_min_u32(kmin, red);
-  kmax = ~block_min_u32(~kmax, red);
-  const int n_used = block_sum_i32(used, scan);
-  constexpr int P = kHorizonPool / kHorizonSplit;
-  const uint32_t T = n_used > P ? block_threshold<kHorizonKeys>(k, kHorizonKeys, kmin, kmax,
-                                                                P / 2, P, scan)
-                                : 0xfffffffeu;
-  int mine = 0;
-  uint32_t rest = 0xffffffffu;
-#pragma unroll
-  for (int q = 0; q < kHorizonKeys; ++q) {
-    if (k[q] == 0xffffffffu) continue;
-    if (k[q] <= T) ++mine;
-    else rest = min(rest, k[q]);
-  }
-  rest = block_min_u32(rest, red);
-  int total = 0;
-  int at = block_scan(mine, scan, &total);
-  if (tid == 0) {
-    s_base = total > 0 ? atomicAdd(&hcount[inst], total) : 0;
-    if (rest != 0xffffffffu) atomicMin(&hrest[inst], rest);
-  }
-  __syncthreads();
-  at += s_base;
-  // the instance's list has M slots and holds each obstacle at most once,
-  // as its circle with the local index in .w
-#pragma unroll
-  for (int q = 0; q < kHorizonKeys; ++q)
-    if (k[q] != 0xffffffffu && k[q] <= T) {
-      const int o = o0 + tid + kScreenThreads * q;
-      float4 c = cq[q];
-      c.w = __int_as_float(o);
-      hlist[in.circ_off + at++] = c;
-    }
-}
 
 struct Shape {
   int sb;       // stages per work item

@@ -392,3 +392,58 @@ def test_screened_open_chain_around_pose(api, mode):
     d, e, o, g, _ = (x.cpu().numpy() for x in plain)
     check_stages(fp, poses, edges, off, 1000.0, d, e, o, g)
     b.close()
+
+
+def _copies_instance(n_obst, at, side, n_poses, seed):
+    """n_obst copies of one square at `at` and a short horizon near the
+    origin: every copy has the same horizon bound bit for bit (a tie block
+    the horizon pass cannot split)."""
+    edges = inputs.rect_edges(np.array([at], np.float64), np.array([[side, side]]), np.zeros(1))
+    edges = np.tile(edges, (n_obst, 1))
+    rng = np.random.default_rng(seed)
+    poses = np.concatenate([rng.uniform(-0.2, 0.2, (n_poses, 2)),
+                            rng.uniform(-np.pi, np.pi, (n_poses, 1))], 1).astype(np.float32)
+    fp = inputs.hexagon_footprint(inputs.rng_for(2, 0))
+    return inputs.Instance(fp, poses, edges.astype(np.float32), inputs.csr_offsets([4] * n_obst), 4,
+                           dict(workload="copies"))
+
+
+def test_screened_fallback_triggers(api):
+    """The stages that no certificate may cover go to the full evaluation and
+    still equal the plain batch: (a) more than 512 obstacles under the
+    bound-threshold form's bar (600 squares stacked on the pose), (b) a
+    horizon list longer than 2048 from a tie block of 2500 equal bounds
+    (copies of one square),
+    (c) an ordinary instance beside them that certifies."""
+    rng = np.random.default_rng(4)
+    fp = inputs.hexagon_footprint(inputs.rng_for(2, 0))
+    stacked = inputs.rect_edges(rng.uniform(-0.3, 0.3, (600, 2)), np.full((600, 2), 0.2),
+                                rng.uniform(-np.pi, np.pi, 600))
+    dense = inputs.Instance(fp, np.array([[0.0, 0.0, 0.3], [0.1, -0.1, 1.0]], np.float32),
+                            stacked.astype(np.float32), inputs.csr_offsets([4] * 600), 4,
+                            dict(workload="stacked"))
+    ring = _copies_instance(2500, (10.0, 0.0), 0.3, 6, 5)
+    normal = inputs.c5_instance(3)
+    b = api.Batch([dense, ring, normal], graph=False)
+    ref = _run_plain(b)
+    for form in ("bound", "distance"):
+        if form == "bound":
+            out, (cand, cert, ck) = b.screened_bound(stats=True)
+        else:
+            out, (cand, cert, ck) = b.screened(None, pool=512, topk=256, stats=True)
+        torch.cuda.synchronize()
+        _assert_same([x.clone() for x in out], ref)
+        cert = cert.cpu().numpy()
+        print(f"[fallback {form}] certified per row {cert.tolist()[:8]} ..., "
+              f"normal instance {cert[8:].mean():.3f}", flush=True)
+        if form == "bound":
+            assert cert[:2].sum() == 0          # more than 512 candidates under the bar
+        assert cert[2:8].sum() == 0             # the tied horizon list is unusable
+        assert cert[8:].mean() > 0.9
+    d, e, o, g, _ = (x.cpu().numpy() for x in ref)
+    for k, inst in enumerate((dense, ring)):
+        po = b.desc[k][2]
+        sl = slice(po, po + inst.N)
+        check_stages(inst.footprint, inst.poses, inst.edges, inst.obst_off, 1000.0, d[sl], e[sl],
+                     o[sl], g[sl])
+    b.close()

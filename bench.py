@@ -25,7 +25,8 @@ Prints one JSON line:
                sources are unchanged;
   cpu_baseline the FP64 oracle on the host's cores (all, and one), built for
                the host (-O3 -march=native), on a bounded c5 sample;
-  extras       c2 latency (one psdf_grad call), c2 x 256, the uneven batch c4
+  extras       c2 latency (one psdf_grad call, on the edges and on the staged
+               edge set), c2 x 256, the uneven batch c4
                against its per-instance loop, one pose against growing edge
                sets, the paper's Table I query shapes.
 """
@@ -68,6 +69,14 @@ KERNELS = {
         + [os.path.join("paper_2607_04310_amd", "build.py")],
         valu=os.path.join(ROOT, "profiles", "main_kernel_c2_valu_counters.md"),
         hbm=os.path.join(ROOT, "profiles", "main_kernel_c2_hbm_counters.md")),
+    # the same per-stage minimum reading a staged edge set
+    "main_staged_kernel": dict(
+        sources=[os.path.join(CSRC, f) for f in (
+            "psdf_device.hpp", "psdf_kernels.hpp", "psdf_staged.hpp", "psdf_winner.hpp",
+            "psdf_inst_mf6.hip", "psdf_host.cpp", "psdf_host.hpp")]
+        + [os.path.join("paper_2607_04310_amd", "build.py")],
+        valu=os.path.join(ROOT, "profiles", "main_staged_kernel_c2_valu_counters.md"),
+        hbm=os.path.join(ROOT, "profiles", "main_staged_kernel_c2_hbm_counters.md")),
 }
 
 
@@ -246,7 +255,26 @@ def extras(torch, api, flops, inputs):
         main_kernel_valu_busy=None if valu is None else valu * 4 / (SIMDS * kms * 1e-3 * CLOCK_GHZ * 1e9))
     log(f"c2: {t_graph * 1e3:.2f} us per call (graph), {t_eager * 1e3:.2f} eager, main kernel "
         f"{kms * 1e3:.2f} us")
-    del es, poses, ws, o
+    # the same call on the staged edge set (the obstacles' pose-independent
+    # constants taken once, when the environment changes)
+    ref = [x.clone() for x in o]
+    es.stage()
+    t_graph_s = graph_calls(torch, c2_step, 200, list(o))
+    if not all(torch.equal(x, y) for x, y in zip(o, ref)):
+        raise RuntimeError("psdf_grad on the staged edge set differs from the plain call")
+    t_eager_s = timed_calls(torch, c2_step, 200, 20)
+    kms_s = api.time_stage_min(inst.footprint, poses, es, 200, ws=ws)
+    valu_s, _ = counted("main_staged_kernel", "valu", "valu_insts_per_launch")
+    out["c2_latency"]["staged"] = dict(
+        us_per_call=t_graph_s * 1e3, eager_us_per_call=t_eager_s * 1e3,
+        evals_per_s=inst.N * inst.E / (t_graph_s * 1e-3),
+        main_kernel_us=kms_s * 1e3, main_kernel_tflops=fl / (kms_s * 1e-3) / 1e12,
+        main_kernel_frac=fl / (kms_s * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+        main_kernel_valu_busy=None if valu_s is None
+        else valu_s * 4 / (SIMDS * kms_s * 1e-3 * CLOCK_GHZ * 1e9))
+    log(f"c2 staged: {t_graph_s * 1e3:.2f} us per call (graph), {t_eager_s * 1e3:.2f} eager, "
+        f"main kernel {kms_s * 1e3:.2f} us")
+    del es, poses, ws, o, ref
 
     log("c4: building 512 instances")
     c4 = inputs.c4(512)
@@ -368,6 +396,9 @@ def main():
         es = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar, device="cuda")
         poses = torch.tensor(inst.poses, device="cuda")
         ws = api.workspace(inst.N, inst.M, "cuda")
+        for _ in range(args.steps):
+            api.psdf_grad(inst.footprint, poses, es, ws=ws)
+        es.stage()      # then as many calls on the staged edge set
         for _ in range(args.steps):
             api.psdf_grad(inst.footprint, poses, es, ws=ws)
     log("c5: building 64 instances")

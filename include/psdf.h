@@ -92,6 +92,15 @@ typedef struct {
   float eta;     /* default 1000 1/m */
 } psdf_params;
 
+/* Staged constants of an edge set (filled by psdf_stage_edges, below). */
+typedef struct {
+  void* table;      /* device, caller-owned, psdf_staged_bytes(M, mbar) bytes */
+  size_t bytes;     /* its size */
+  int32_t E, M;     /* the edge set it was made for */
+  int32_t mi_class; /* edge class of that set's mbar: 4, 8 or 16 */
+  float eps;        /* params->eps it was made with */
+} psdf_staged;
+
 /* Edge set of one environment (see the conventions above). */
 typedef struct {
   const float* ax; /* device float32[E] */
@@ -102,6 +111,7 @@ typedef struct {
   int32_t E;
   int32_t M;
   int32_t mbar;
+  const psdf_staged* staged; /* host, optional (NULL): see psdf_stage_edges */
 } psdf_edges;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -220,6 +230,43 @@ int psdf_bwd_geometry(const float* footprint, int32_t m, const float* poses, int
 int psdf_sd_matrix(const float* footprint, int32_t m, const float* poses, int32_t N,
                    const psdf_edges* edges, const psdf_params* params, float* sd,
                    hipStream_t stream);
+
+/* psdf_staged_bytes - size of a staged table for M obstacles under the bound
+ * mbar: (40 * edge class + 16) bytes per obstacle, M rounded up to 64 (0
+ * when M <= 0, M > 2^28 or mbar outside 1..PSDF_MAX_OBST_EDGES). */
+size_t psdf_staged_bytes(int32_t M, int32_t mbar);
+
+/* psdf_stage_edges - the pose-independent part of the evaluation, done once
+ * per edge set instead of in every call: EncodeEdges of Alg. 1, which runs
+ * only when the environment changes while the per-stage evaluation runs at
+ * every control step.  For each obstacle it stores, laid out for coalesced
+ * loads, the edge start points, the unit edge directions u_j = (B_j - A_j) /
+ * (|B_j - A_j| + eps) that give the obstacle normals n'_j = rot90(u_j)
+ * (Sec. IV-C), the edge lengths of the point-segment pools (Sec. IV-B), the
+ * obstacle's own interval on each of its axes (Sec. IV-C: it does not depend
+ * on the pose), its extra V_obs points (open chains), and its closed and
+ * invalid flags.
+ *   edges   the edge set (edges->staged is ignored)
+ *   params  NULL selects the defaults; only eps enters the table
+ *   table   device, 16-byte aligned, at least psdf_staged_bytes(M, mbar)
+ *           bytes, caller-owned; overwritten on `stream`
+ *   out     host; receives (table, bytes, E, M, edge class, eps)
+ * M above 2^28 gives PSDF_ETOOBIG, a table below the size PSDF_EWS.
+ * Point edges->staged at *out for the calls that should use it: psdf_eval,
+ * psdf_grad, psdf_grad_noalloc, psdf_constraints and psdf_time_stage_min then
+ * read each obstacle from the table in their per-stage minimum kernel, with
+ * results bit for bit those of the same call without it (the one-launch form
+ * for at most 256 obstacles of at most four edges, and every other entry
+ * point, do not use it).  Given a table made for another E, M, edge class or
+ * eps, or smaller than needed, those calls and psdf_bwd / psdf_sd_matrix
+ * return PSDF_EINVAL (psdf_bwd_geometry and psdf_validate_edges ignore the
+ * field).  The
+ * table describes the edge arrays' contents at staging time: after changing
+ * them, stage again before the next call (a stale table gives the old
+ * obstacles' distances).  The edge arrays themselves stay in use (the winner
+ * adjoint reads them). */
+int psdf_stage_edges(const psdf_edges* edges, const psdf_params* params, void* table,
+                     size_t table_bytes, psdf_staged* out, hipStream_t stream);
 
 /* psdf_validate_edges - debug scan of a device edge set (the staging step of
  * Sec. IV-A / Alg. 1 EncodeEdges, checked): counts the obstacles outside the

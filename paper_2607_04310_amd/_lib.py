@@ -31,10 +31,16 @@ class PsdfParams(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_float), ("eps_sat", ctypes.c_float), ("eta", ctypes.c_float)]
 
 
+class PsdfStaged(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_void_p), ("bytes", ctypes.c_size_t), ("E", ctypes.c_int32),
+                ("M", ctypes.c_int32), ("mi_class", ctypes.c_int32), ("eps", ctypes.c_float)]
+
+
 class PsdfEdges(ctypes.Structure):
     _fields_ = [("ax", ctypes.c_void_p), ("ay", ctypes.c_void_p), ("bx", ctypes.c_void_p),
                 ("by", ctypes.c_void_p), ("obst_off", ctypes.c_void_p), ("E", ctypes.c_int32),
-                ("M", ctypes.c_int32), ("mbar", ctypes.c_int32)]
+                ("M", ctypes.c_int32), ("mbar", ctypes.c_int32),
+                ("staged", ctypes.POINTER(PsdfStaged))]
 
 
 class PsdfBatchDesc(ctypes.Structure):
@@ -102,6 +108,9 @@ _SIGS = {
     "psdf_timer_enable": (ctypes.c_int, [_I32]),
     "psdf_timer_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "psdf_validate_edges": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "psdf_staged_bytes": (ctypes.c_size_t, [_I32, _I32]),
+    "psdf_stage_edges": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
     "psdf_encode_padded": (ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP,
                                           _VP, ctypes.c_size_t, _VP]),
 }

@@ -60,10 +60,43 @@ class EdgeSet:
         self.mbar = int(mbar)
         return self
 
-    def c(self):
+    _staged = None   # ctypes PsdfStaged, while staged
+    _table = None    # its device table
+
+    def stage(self, params: Params | None = None):
+        """Take the edge set's pose-independent constants once
+        (psdf_stage_edges, Alg. 1 EncodeEdges): later calls with this EdgeSet
+        read them from a device table.  Stage again after changing the edge
+        tensors in place."""
+        params = params or Params()
+        nbytes = int(_lib.lib().psdf_staged_bytes(self.M, self.mbar))
+        table = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=self.ax.device)
+        st = _lib.PsdfStaged()
+        ec, pc = self._plain(), params.c()
+        _lib.check(_lib.lib().psdf_stage_edges(ctypes.byref(ec), ctypes.byref(pc),
+                                               table.data_ptr(), table.numel(),
+                                               ctypes.byref(st), _lib.stream_handle()))
+        self._table, self._staged = table, st
+        return self
+
+    def unstage(self):
+        self._table = self._staged = None
+        return self
+
+    @property
+    def staged(self):
+        return self._staged is not None
+
+    def _plain(self):
         return _lib.PsdfEdges(self.ax.data_ptr(), self.ay.data_ptr(), self.bx.data_ptr(),
                               self.by.data_ptr(), self.obst_off.data_ptr(), self.E, self.M,
                               self.mbar)
+
+    def c(self):
+        ec = self._plain()
+        if self._staged is not None:
+            ec.staged = ctypes.pointer(self._staged)
+        return ec
 
 
 def _fp(footprint):

@@ -18,6 +18,7 @@
 #include "psdf.h"
 #include "psdf_device.hpp"
 #include "psdf_host.hpp"
+#include "psdf_staged.hpp"
 #include "psdf_winner.hpp"
 
 namespace psdf {
@@ -77,14 +78,104 @@ __global__ __launch_bounds__(BLK) void main_kernel(FpConst F, const float* __res
   }
 }
 
+// main_kernel on a staged edge set (psdf_staged.hpp): the lane's obstacle
+// row (its slots, intervals and flags) comes from coalesced table loads,
+// issued before the stage table is built, instead of from the offsets and
+// edges plus the per-lane setup.  Same stage loop, same partials, bit for
+// bit.
+template <int MF, int MI, int BLK>
+__global__ __launch_bounds__(BLK) void main_staged_kernel(FpConst F, const float* __restrict__ poses,
+                                                           int N, int SB, StagedView v, int M,
+                                                           ulonglong2* __restrict__ partial) {
+  constexpr int NW = BLK / 64;
+  __shared__ float4 st[kMaxStageBlock];
+  __shared__ float4 rft[kMaxStageBlock * MF];
+  __shared__ uint64_t wk[NW][kMaxStageBlock];
+  __shared__ uint64_t wa[NW][kMaxStageBlock];
+  const int s0 = blockIdx.y * SB;
+  const int ns = min(SB, N - s0);
+  const int gx = gridDim.x;
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave_base = blockIdx.x * BLK + w * 64;
+
+  const int i = wave_base + lane;
+  const bool active = i < M;
+  int4 meta = make_int4(0, 0, 0, 0);
+  float4 r0[MI], r1[MI];
+#pragma unroll
+  for (int j = 0; j < MI; ++j) {
+    r0[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    r1[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  if (active) {
+    meta = v.meta[i];
+#pragma unroll
+    for (int j = 0; j < MI; ++j) {
+      r0[j] = v.rec0[(size_t)j * v.Mp + i];
+      r1[j] = v.rec1[(size_t)j * v.Mp + i];
+    }
+  }
+
+  fill_stage_table<MF>(F, poses, s0, ns, st, rft, BLK);
+  __syncthreads();
+
+  if (wave_base < M) {
+    auto emit = [&](int t, uint64_t key, uint64_t a) {
+      if (lane == 0) {
+        if (NW == 1) {
+          partial[(size_t)(s0 + t) * gx + blockIdx.x] = make_ulonglong2(key, a);
+        } else {
+          wk[w][t] = key;
+          wa[w][t] = a;
+        }
+      }
+    };
+    const int e0 = meta.x, mi = meta.y;
+    const bool segments = __ballot(active && mi > 1) == 0;
+    if (MI > 1 && segments) {
+      Obst<1> o;
+      staged_obstacle<1, MI>(o, v, i, active, r0, r1, mi, meta.z);
+      wave_stage_loop<MF, 1>(F, o, e0, mi, active, wave_base, ns, st, rft, emit);
+    } else {
+      Obst<MI> o;
+      staged_obstacle<MI, MI>(o, v, i, active, r0, r1, mi, meta.z);
+      wave_stage_loop<MF, MI>(F, o, e0, mi, active, wave_base, ns, st, rft, emit);
+    }
+  } else if (NW > 1 && lane == 0) {
+    for (int t = 0; t < ns; ++t) { wk[w][t] = kEmptyKey; wa[w][t] = 0; }
+  }
+  if (NW > 1) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < ns; t += BLK) {
+      uint64_t k = wk[0][t], a = wa[0][t];
+#pragma unroll
+      for (int u = 1; u < NW; ++u)
+        if (wk[u][t] < k) { k = wk[u][t]; a = wa[u][t]; }
+      partial[(size_t)(s0 + t) * gx + blockIdx.x] = make_ulonglong2(k, a);
+    }
+  }
+}
+
 // ev0 / ev1 (may be null): events that the dispatch itself records at its
-// start and end (kernel timer).
+// start and end (kernel timer).  A staged table (e.staged) selects
+// main_staged_kernel.
 template <int MF, int MI>
 hipError_t launch_main_t(const LaunchShape& ls, const FpConst& F, const float* poses, int N,
                          const psdf_edges& e, uint64_t* partial, hipStream_t st, hipEvent_t ev0,
                          hipEvent_t ev1) {
   dim3 grid((e.M + ls.blk - 1) / ls.blk, (N + ls.sb - 1) / ls.sb);
   ulonglong2* pk = reinterpret_cast<ulonglong2*>(partial);
+  if (e.staged) {
+    const StagedView v = staged_view(e.staged->table, e.M, MI);
+    if (ls.blk == 64)
+      hipExtLaunchKernelGGL(main_staged_kernel<MF, MI, 64>, grid, dim3(64), 0, st, ev0, ev1, 0,
+                            F, poses, N, ls.sb, v, e.M, pk);
+    else
+      hipExtLaunchKernelGGL(main_staged_kernel<MF, MI, 256>, grid, dim3(256), 0, st, ev0, ev1, 0,
+                            F, poses, N, ls.sb, v, e.M, pk);
+    return hipGetLastError();
+  }
   if (ls.blk == 64)
     hipExtLaunchKernelGGL(main_kernel<MF, MI, 64>, grid, dim3(64), 0, st, ev0, ev1, 0, F, poses,
                           N, ls.sb, e.ax, e.ay, e.bx, e.by, e.obst_off, e.E, e.M, pk);

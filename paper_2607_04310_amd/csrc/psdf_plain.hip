@@ -436,6 +436,31 @@ const char* psdf_last_error(void) { return last_error(); }
 
 const char* psdf_version(void) { return "psdf-gfx950 0.1"; }
 
+// A staged table attached to the edge set must have been made for it (same
+// E, M and edge class) with the call's eps, and be large enough.
+static int check_staged(const psdf_edges& e, const FpConst& F) {
+  const psdf_staged* s = e.staged;
+  if (!s) return PSDF_OK;
+  const int cls = obst_class(e.mbar);
+  if (s->E != e.E || s->M != e.M || s->mi_class != cls)
+    return set_error(PSDF_EINVAL,
+                     "staged table made for E = %d, M = %d, edge class %d; the edge set has "
+                     "E = %d, M = %d, edge class %d",
+                     s->E, s->M, s->mi_class, e.E, e.M, cls);
+  if (__builtin_memcmp(&s->eps, &F.eps, sizeof(float)) != 0)
+    return set_error(PSDF_EINVAL, "staged table made with eps = %g, the call has eps = %g",
+                     (double)s->eps, (double)F.eps);
+  if (e.M > 0) {
+    if (!s->table) return set_error(PSDF_EINVAL, "staged table pointer is NULL");
+    if ((reinterpret_cast<uintptr_t>(s->table) & 15u) != 0)
+      return set_error(PSDF_EINVAL, "staged table is not 16-byte aligned");
+    if (s->bytes < staged_table_bytes(e.M, cls))
+      return set_error(PSDF_EINVAL, "staged table of %zu bytes, %zu needed", s->bytes,
+                       staged_table_bytes(e.M, cls));
+  }
+  return PSDF_OK;
+}
+
 static int plain_common(const float* footprint, int32_t m, const float* poses, int32_t N,
                         const psdf_edges* edges, const psdf_params* params, FpConst& F,
                         psdf_edges& e) {
@@ -443,8 +468,57 @@ static int plain_common(const float* footprint, int32_t m, const float* poses, i
   if (rc) return rc;
   rc = check_edges(edges, &e);
   if (rc) return rc;
+  rc = check_staged(e, F);
+  if (rc) return rc;
   if (N < 0) return set_error(PSDF_EINVAL, "N = %d is negative", N);
   if (N > 0 && !poses) return set_error(PSDF_EINVAL, "poses is NULL");
+  return PSDF_OK;
+}
+
+size_t psdf_staged_bytes(int32_t M, int32_t mbar) {
+  if (M <= 0 || M > kStagedMaxM || mbar < 1 || mbar > kMaxObst) return 0;
+  return staged_table_bytes(M, obst_class(mbar));
+}
+
+int psdf_stage_edges(const psdf_edges* edges, const psdf_params* params, void* table,
+                     size_t table_bytes, psdf_staged* out, hipStream_t stream) {
+  clear_error();
+  psdf_edges e;
+  int rc = check_edges(edges, &e);
+  if (rc) return rc;
+  if (!out) return set_error(PSDF_EINVAL, "out is NULL");
+  const float eps = params ? params->eps : 1e-12f;
+  if (!(eps >= 0.f)) return set_error(PSDF_EINVAL, "eps must be >= 0");
+  const int cls = obst_class(e.mbar);
+  if (e.M > kStagedMaxM)
+    return set_error(PSDF_ETOOBIG, "M = %d obstacles, at most %d can be staged", e.M, kStagedMaxM);
+  const size_t need = psdf_staged_bytes(e.M, e.mbar);
+  if (need > 0) {
+    if (!table) return set_error(PSDF_EINVAL, "table is NULL");
+    if ((reinterpret_cast<uintptr_t>(table) & 15u) != 0)
+      return set_error(PSDF_EINVAL, "table is not 16-byte aligned");
+    if (table_bytes < need)
+      return set_error(PSDF_EWS, "table of %zu bytes, %zu needed", table_bytes, need);
+    const StagedView v = staged_view(table, e.M, cls);
+    const int grid = (v.Mp + 255) / 256;
+    if (cls == 4)
+      stage_edges_kernel<4><<<grid, 256, 0, stream>>>(e.ax, e.ay, e.bx, e.by, e.obst_off, e.E,
+                                                      e.M, eps, v);
+    else if (cls == 8)
+      stage_edges_kernel<8><<<grid, 256, 0, stream>>>(e.ax, e.ay, e.bx, e.by, e.obst_off, e.E,
+                                                      e.M, eps, v);
+    else
+      stage_edges_kernel<16><<<grid, 256, 0, stream>>>(e.ax, e.ay, e.bx, e.by, e.obst_off, e.E,
+                                                       e.M, eps, v);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return hip_status(err);
+  }
+  out->table = table;
+  out->bytes = table_bytes;
+  out->E = e.E;
+  out->M = e.M;
+  out->mi_class = cls;
+  out->eps = eps;
   return PSDF_OK;
 }
 

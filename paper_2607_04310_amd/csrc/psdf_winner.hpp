@@ -171,23 +171,17 @@ __device__ __forceinline__ void fill_stage_table(const FpConst& F, const float* 
   }
 }
 
-// Per-stage minimum over one wave's obstacles (lane <-> obstacle, edges
-// [e0, e0 + mi) held in registers) for the ns stages of the table st (c, s,
-// px, py) with their rotated footprints rft[t * MF + l] (rotated_slot).  For each stage emit(t, key, aux) receives the wave's minimum key
-// (orderable(sd) << 32 | obase + lane of the first minimum, or the empty
-// key) and that lane's (e0 << 32 | mi).  A wave whose obstacles all have at
-// most one edge (free segments) takes the one-edge specialisation, which is
-// the same arithmetic on one slot instead of MI.
+// Per-stage minimum over one wave's obstacles (lane <-> obstacle o, the
+// lane's obstacle with its pose-independent constants in registers, edges
+// [e0, e0 + mi)) for the ns stages of the table st (c, s, px, py) with their
+// rotated footprints rft[t * MF + l] (rotated_slot).  For each stage
+// emit(t, key, aux) receives the wave's minimum key (orderable(sd) << 32 |
+// obase + lane of the first minimum, or the empty key) and that lane's
+// (e0 << 32 | mi).
 template <int MF, int MIX, class Emit>
-__device__ __forceinline__ void wave_stages_t(const FpConst& F, const float* __restrict__ ax,
-                                              const float* __restrict__ ay,
-                                              const float* __restrict__ bx,
-                                              const float* __restrict__ by, int e0, int mi,
-                                              int Eend, bool active, bool bad, int obase, int ns,
-                                              const float4* st, const float4* rft, Emit emit) {
-  Obst<MIX> o;
-  load_obstacle<MIX>(o, ax, ay, bx, by, e0, mi, Eend, F.eps);
-  o.bad = o.bad || bad;
+__device__ __forceinline__ void wave_stage_loop(const FpConst& F, Obst<MIX>& o, int e0, int mi,
+                                                bool active, int obase, int ns,
+                                                const float4* st, const float4* rft, Emit emit) {
   const bool contributes = active && (mi != 0);
   for (int t = 0; t < ns; ++t) {
     const float4 q = st[t];
@@ -207,6 +201,23 @@ __device__ __forceinline__ void wave_stages_t(const FpConst& F, const float* __r
     }
     emit(t, key, a);
   }
+}
+
+// wave_stage_loop with the obstacle loaded from the edge arrays.  A wave
+// whose obstacles all have at most one edge (free segments) takes the
+// one-edge specialisation (wave_stages), the same arithmetic on one slot
+// instead of MI.
+template <int MF, int MIX, class Emit>
+__device__ __forceinline__ void wave_stages_t(const FpConst& F, const float* __restrict__ ax,
+                                              const float* __restrict__ ay,
+                                              const float* __restrict__ bx,
+                                              const float* __restrict__ by, int e0, int mi,
+                                              int Eend, bool active, bool bad, int obase, int ns,
+                                              const float4* st, const float4* rft, Emit emit) {
+  Obst<MIX> o;
+  load_obstacle<MIX>(o, ax, ay, bx, by, e0, mi, Eend, F.eps);
+  o.bad = o.bad || bad;
+  wave_stage_loop<MF, MIX>(F, o, e0, mi, active, obase, ns, st, rft, emit);
 }
 
 template <int MF, int MI, class Emit>

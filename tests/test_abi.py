@@ -161,3 +161,59 @@ def test_validate_edges_argument_checks():
     assert lib.psdf_validate_edges(ctypes.byref(e), None, None) == _lib.PSDF_EINVAL
     bad_mbar = _lib.PsdfEdges(1, 1, 1, 1, 1, 4, 1, 17)
     assert lib.psdf_validate_edges(ctypes.byref(bad_mbar), ctypes.c_void_p(16), None) == _lib.PSDF_ETOOBIG
+
+
+def _staged(E=4, M=1, cls=4, eps=1e-12, table=256, nbytes=1 << 20):
+    return _lib.PsdfStaged(table, nbytes, E, M, cls, eps)
+
+
+def test_staged_table_size():
+    lib = _lib.lib()
+    assert lib.psdf_staged_bytes(0, 4) == 0 and lib.psdf_staged_bytes(10, 0) == 0
+    assert lib.psdf_staged_bytes(10, 17) == 0 and lib.psdf_staged_bytes((1 << 28) + 1, 4) == 0
+    # (40 * class + 16) bytes per row, rows = M rounded up to 64
+    assert lib.psdf_staged_bytes(1, 4) == 64 * 176
+    assert lib.psdf_staged_bytes(4096, 3) == 4096 * 176
+    assert lib.psdf_staged_bytes(65, 5) == 128 * 336
+    assert lib.psdf_staged_bytes(64, 16) == 64 * 656
+
+
+def test_stage_edges_argument_checks():
+    lib = _lib.lib()
+    e = _lib.PsdfEdges(1, 1, 1, 1, 1, 4, 1, 4)
+    p = _lib.PsdfParams(1e-12, 1e-6, 1000.0)
+    out = _lib.PsdfStaged()
+    need = lib.psdf_staged_bytes(1, 4)
+
+    def stage(edges=e, params=p, table=256, nbytes=need, o=out):
+        return lib.psdf_stage_edges(ctypes.byref(edges), ctypes.byref(params) if params else None,
+                                    table, nbytes, ctypes.byref(o) if o is not None else None,
+                                    None)
+    assert stage(o=None) == _lib.PSDF_EINVAL
+    assert stage(table=None) == _lib.PSDF_EINVAL
+    assert stage(table=264) == _lib.PSDF_EINVAL                 # not 16-byte aligned
+    assert stage(nbytes=need - 1) == _lib.PSDF_EWS
+    assert stage(params=_lib.PsdfParams(float("nan"), 1e-6, 1.0)) == _lib.PSDF_EINVAL
+    assert stage(edges=_lib.PsdfEdges(1, 1, 1, 1, 1, 4, 1, 0)) == _lib.PSDF_ETOOBIG
+    assert stage(edges=_lib.PsdfEdges(1, 1, 1, 1, 1, 4, (1 << 28) + 1, 4)) == _lib.PSDF_ETOOBIG
+    # an empty edge set needs no table and enqueues nothing
+    empty = _lib.PsdfEdges(0, 0, 0, 0, 1, 0, 0, 4)
+    assert stage(edges=empty, table=None, nbytes=0) == _lib.PSDF_OK
+    assert (out.E, out.M, out.mi_class) == (0, 0, 4)
+
+
+@pytest.mark.parametrize("fields,ok", [
+    (dict(), True),
+    (dict(E=8), False),                      # made for another edge count
+    (dict(M=2), False),                      # another obstacle count
+    (dict(cls=8), False),                    # another edge class
+    (dict(eps=1e-9), False),                 # another eps
+    (dict(table=None), False),
+    (dict(table=264), False),                # misaligned
+    (dict(nbytes=100), False),               # too small
+])
+def test_staged_table_must_match_the_call(fields, ok):
+    st = _staged(**fields)
+    e = _lib.PsdfEdges(1, 1, 1, 1, 1, 4, 1, 4, ctypes.pointer(st))
+    rc = _call_eval(RECT, edges=e)         # N = 0: only the host checks run
+    assert rc == (_lib.PSDF_OK if ok else _lib.PSDF_EINVAL)

@@ -1,0 +1,232 @@
+"""Staged edge sets (psdf_stage_edges; Alg. 1 EncodeEdges, run when the
+environment changes): the calls that read an obstacle's pose-independent
+constants from the staged table give bit for bit the outputs of the same call
+on the edges alone, across edge classes, obstacle kinds, invalid input and
+launch shapes, and the staged c2 call matches the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2607_04310_amd import inputs
+from parity import check_stages
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_04310_amd import api as _api
+    return _api
+
+
+def _same(a, b):
+    a, b = a.cpu(), b.cpu()
+    if a.dtype.is_floating_point:
+        return torch.equal(torch.nan_to_num(a, 7.0), torch.nan_to_num(b, 7.0)) and \
+            torch.equal(torch.isnan(a), torch.isnan(b))
+    return torch.equal(a, b)
+
+
+def _grad(api, inst, edges, params):
+    poses = torch.tensor(inst.poses, device="cuda")
+    out = api.psdf_grad(inst.footprint, poses, edges, params)
+    torch.cuda.synchronize()
+    return out
+
+
+def staged_vs_plain(api, inst, eta=1000.0):
+    """psdf_grad without and with the staged table; returns the staged outputs."""
+    print(f"[staged] {inst.meta.get('workload')} N={inst.N} E={inst.E} M={inst.M} "
+          f"m={len(inst.footprint)} mbar={inst.mbar} eta={eta}", flush=True)
+    p = api.Params(eta=eta)
+    edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar)
+    ref = [x.clone() for x in _grad(api, inst, edges, p)]
+    edges.stage(p)
+    got = _grad(api, inst, edges, p)
+    for x, y, name in zip(got, ref, ("d", "edge", "obst", "grad", "keys")):
+        assert _same(x, y), name
+    return got
+
+
+@pytest.mark.parametrize("eta", [1000.0, math.inf, 50.0])
+def test_c2_staged_bitwise(api, eta):
+    staged_vs_plain(api, inputs.c2(0), eta)
+
+
+def test_c2_staged_vs_oracle(api):
+    inst = inputs.c2(1)
+    d, e, o, g, _ = staged_vs_plain(api, inst)
+    st = check_stages(inst.footprint, inst.poses, inst.edges, inst.obst_off, 1000.0,
+                      d.cpu().numpy(), e.cpu().numpy(), o.cpu().numpy(), g.cpu().numpy())
+    assert st["stages"] >= 45
+
+
+def _polygons(rng, n, kmax, lo, hi):
+    edges, sizes = [], []
+    for _ in range(n):
+        k = int(rng.integers(3, kmax + 1))
+        ang = np.sort(rng.uniform(0, 2 * np.pi, k))
+        c = rng.uniform(lo, hi, 2)
+        pts = (c + rng.uniform(0.1, 0.6) * np.stack([np.cos(ang), np.sin(ang)], 1))
+        pts = inputs._hull_ccw(pts.astype(np.float32)).astype(np.float32)
+        if rng.random() < 0.5:
+            pts = pts[::-1]
+        edges.append(np.concatenate([pts, np.roll(pts, -1, 0)], 1))
+        sizes.append(len(pts))
+    return np.concatenate(edges).astype(np.float32), inputs.csr_offsets(sizes)
+
+
+@pytest.mark.parametrize("kmax,m", [(8, 5), (16, 7), (16, 12), (6, 16)])
+def test_general_polygons(api, kmax, m):
+    """The 8- and 16-edge classes and the padded footprint (300 polygons, so
+    that the two-kernel form runs)."""
+    rng = np.random.default_rng(kmax * 100 + m)
+    edges, off = _polygons(rng, 300, kmax, -4, 4)
+    ang = np.linspace(0, 2 * np.pi, m, endpoint=False) + 0.1
+    fp = (0.4 * np.stack([np.cos(ang), 0.7 * np.sin(ang)], 1)).astype(np.float32)
+    inst = inputs.Instance(fp, inputs.uniform_poses(rng, 50, -4, 4), edges, off,
+                           int(np.diff(off).max()), dict(workload="polygons"))
+    staged_vs_plain(api, inst)
+
+
+def _chains_and_segments(rng, n_chain, n_seg, n_rect, lo, hi):
+    """Open chains of 2-4 edges (B_j == A_{j+1} but not closed), free
+    segments and rectangles, shuffled."""
+    parts = []
+    for _ in range(n_chain):
+        k = int(rng.integers(2, 5))
+        pts = rng.uniform(lo, hi, 2) + np.cumsum(rng.normal(0, 0.4, (k + 1, 2)), 0)
+        parts.append(np.concatenate([pts[:-1], pts[1:]], 1))
+    for _ in range(n_seg):
+        c, a, L = rng.uniform(lo, hi, 2), rng.uniform(0, np.pi), rng.uniform(0.1, 1.0)
+        u = 0.5 * L * np.array([np.cos(a), np.sin(a)])
+        parts.append(np.concatenate([c - u, c + u])[None])
+    rects = inputs.random_rects(rng, n_rect, 0.1, 0.8, lo, hi)
+    parts += [rects[4 * i:4 * i + 4] for i in range(n_rect)]
+    order = rng.permutation(len(parts))
+    parts = [parts[i] for i in order]
+    return (np.concatenate(parts).astype(np.float32),
+            inputs.csr_offsets([len(p) for p in parts]))
+
+
+def test_open_chains_segments_rectangles(api):
+    rng = np.random.default_rng(11)
+    edges, off = _chains_and_segments(rng, 150, 150, 200, -5, 5)
+    inst = inputs.Instance(inputs.random_convex_footprint(rng, 5), inputs.uniform_poses(rng, 60, -5, 5),
+                           edges, off, 4, dict(workload="chains+segments+rects"))
+    staged_vs_plain(api, inst)
+
+
+def test_segments_only(api):
+    """Every wave of free segments takes the one-edge specialisation."""
+    rng = np.random.default_rng(12)
+    edges, off = _chains_and_segments(rng, 0, 600, 0, -5, 5)
+    inst = inputs.Instance(inputs.rect_footprint(), inputs.uniform_poses(rng, 40, -5, 5), edges,
+                           off, 4, dict(workload="segments"))
+    staged_vs_plain(api, inst)
+
+
+@pytest.mark.parametrize("M,N", [(257, 130), (1000, 7), (3000, 129)])
+def test_ragged_sizes(api, M, N):
+    rng = np.random.default_rng(M * 7 + N)
+    edges = inputs.random_rects(rng, M, 0.1, 0.8, -6, 6)
+    inst = inputs.Instance(inputs.rect_footprint(), inputs.uniform_poses(rng, N, -6, 6), edges,
+                           inputs.csr_offsets([4] * M), 4, dict(workload="ragged"))
+    staged_vs_plain(api, inst)
+
+
+def test_invalid_input(api):
+    """Empty obstacles between real ones, an obstacle above its edge class, a
+    non-finite coordinate and non-finite poses."""
+    rng = np.random.default_rng(13)
+    M = 400
+    edges = inputs.random_rects(rng, M, 0.2, 1.0, -5, 5)
+    sizes = [4] * M
+    inst = inputs.Instance(inputs.rect_footprint(), inputs.uniform_poses(rng, 30, -5, 5), edges,
+                           inputs.csr_offsets(sizes), 4, dict(workload="invalid"))
+    inst.poses = inst.poses.copy()
+    inst.poses[3, 0] = np.nan
+    inst.poses[7, 2] = np.inf
+    d = staged_vs_plain(api, inst)[0].cpu().numpy()
+    assert np.isnan(d[3]) and np.isnan(d[7]) and np.isfinite(np.delete(d, [3, 7])).all()
+    # empty obstacles (S = 0 padding) in between
+    sizes2 = []
+    for s in sizes:
+        sizes2 += [s, 0] if rng.random() < 0.3 else [s]
+    inst.obst_off = inputs.csr_offsets(sizes2)
+    staged_vs_plain(api, inst)
+    # obstacle 9 with five edges (above class 4): every stage NaN
+    off = inputs.csr_offsets(sizes).copy()
+    off[10] += 1
+    inst.obst_off = off
+    d = staged_vs_plain(api, inst)[0].cpu().numpy()
+    assert np.isnan(d).all()
+    # a non-finite coordinate
+    inst.obst_off = inputs.csr_offsets(sizes)
+    inst.edges = inst.edges.copy()
+    inst.edges[41, 2] = np.inf
+    d = staged_vs_plain(api, inst)[0].cpu().numpy()
+    assert np.isnan(d).all()
+
+
+@pytest.mark.parametrize("blk,sb", [(64, 1), (64, 7), (256, 1), (256, 4), (256, 64)])
+def test_launch_shapes(api, blk, sb):
+    inst = inputs.c2(1)
+    ref = staged_vs_plain(api, inst)
+    api.set_launch_shape(blk, sb)
+    try:
+        got = staged_vs_plain(api, inst)
+    finally:
+        api.set_launch_shape(0, 0)
+    for x, y in zip(got, ref):
+        assert _same(x, y)
+
+
+def test_eval_constraints_time(api):
+    inst = inputs.c2(2)
+    p = api.Params()
+    poses = torch.tensor(inst.poses, device="cuda")
+    edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar)
+    ref_e = [x.clone() for x in api.psdf_eval(inst.footprint, poses, edges, p)]
+    ref_c = api.psdf_constraints(inst.footprint, poses, edges, 0.1, p)[0].clone()
+    edges.stage(p)
+    got_e = api.psdf_eval(inst.footprint, poses, edges, p)
+    got_c = api.psdf_constraints(inst.footprint, poses, edges, 0.1, p)[0]
+    torch.cuda.synchronize()
+    for x, y in zip(got_e, ref_e):
+        assert _same(x, y)
+    assert _same(got_c, ref_c)
+    ms = api.time_stage_min(inst.footprint, poses, edges, 20, p)
+    assert 0.0 < ms < 5.0
+
+
+def test_restage_after_edges_change(api):
+    """Staging again after changing the edge tensors in place gives the new
+    edge set's outputs."""
+    inst = inputs.c2(3)
+    p = api.Params()
+    edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar).stage(p)
+    _grad(api, inst, edges, p)
+    for col in (edges.ax, edges.bx):
+        col.add_(0.37)
+    fresh = api.EdgeSet.from_device(edges.ax, edges.ay, edges.bx, edges.by, edges.obst_off,
+                                    edges.mbar)
+    ref = [x.clone() for x in _grad(api, inst, fresh, p)]
+    edges.stage(p)
+    got = _grad(api, inst, edges, p)
+    for x, y in zip(got, ref):
+        assert _same(x, y)
+
+
+def test_table_made_with_another_eps_is_refused(api):
+    inst = inputs.c2(0)
+    edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar).stage(api.Params(eps=1e-9))
+    with pytest.raises(Exception, match="eps"):
+        _grad(api, inst, edges, api.Params())
+    edges.unstage()
+    _grad(api, inst, edges, api.Params())

@@ -17,7 +17,8 @@ Prints one JSON line:
                forms on the same inputs: the bound-threshold form, and the
                top-K forms ranked by the edge distance and by the screener
                network trained on held-out instances; rate, certification,
-               exact evaluations per stage, winner recall;
+               exact evaluations per stage, winner recall; and each form again
+               with the obstacles' bounding circles taken once per edge set;
   roofline     the persistent batch kernel: algorithmic FLOP per launch over
                its mean duration from HIP events that each dispatch records
                on its launch stream; VALU issue and HBM bytes from the
@@ -375,6 +376,19 @@ def screened_forms(torch, api, inputs, c5, b, ref, steps):
                          winner_recall=float((ck == b.keys).float().mean()))
         log(f"c5 screened {name}: {ms:.4f} ms, certified {res[name]['certified']:.4f}, "
             f"{res[name]['exact_evals_per_stage']:.1f} exact per stage")
+    # the same forms with the bounding circles taken once per edge set
+    # (psdf_batch_stage), as when the environment is static between calls
+    b.stage()
+    res["staged_circles"] = {}
+    for name, fn in forms.items():
+        ms = graph_calls(torch, fn, steps, outs)
+        torch.cuda.synchronize()
+        if not all(torch.equal(x, y) or torch.equal(torch.nan_to_num(x, 7.0), torch.nan_to_num(y, 7.0))
+                   for x, y in zip(outs, ref)):
+            raise RuntimeError(f"screened ({name}, staged circles) outputs differ from the plain batch")
+        res["staged_circles"][name] = dict(ms=ms, evals_per_s=pairs / (ms * 1e-3), exact=True)
+        log(f"c5 screened {name}, staged circles: {ms:.4f} ms")
+    b.unstage()
     return res
 
 

@@ -99,6 +99,7 @@ typedef struct {
   int32_t E, M;     /* the edge set it was made for */
   int32_t mi_class; /* edge class of that set's mbar: 4, 8 or 16 */
   float eps;        /* params->eps it was made with */
+  const void* src[5]; /* that set's ax, ay, bx, by, obst_off */
 } psdf_staged;
 
 /* Edge set of one environment (see the conventions above). */
@@ -250,15 +251,16 @@ size_t psdf_staged_bytes(int32_t M, int32_t mbar);
  *   params  NULL selects the defaults; only eps enters the table
  *   table   device, 16-byte aligned, at least psdf_staged_bytes(M, mbar)
  *           bytes, caller-owned; overwritten on `stream`
- *   out     host; receives (table, bytes, E, M, edge class, eps)
+ *   out     host; receives (table, bytes, E, M, edge class, eps, the five
+ *           array pointers)
  * M above 2^28 gives PSDF_ETOOBIG, a table below the size PSDF_EWS.
  * Point edges->staged at *out for the calls that should use it: psdf_eval,
  * psdf_grad, psdf_grad_noalloc, psdf_constraints and psdf_time_stage_min then
  * read each obstacle from the table in their per-stage minimum kernel, with
  * results bit for bit those of the same call without it (the one-launch form
  * for at most 256 obstacles of at most four edges, and every other entry
- * point, do not use it).  Given a table made for another E, M, edge class or
- * eps, or smaller than needed, those calls and psdf_bwd / psdf_sd_matrix
+ * point, do not use it).  Given a table made for other arrays, another E, M,
+ * edge class or eps, or smaller than needed, those calls and psdf_bwd / psdf_sd_matrix
  * return PSDF_EINVAL (psdf_bwd_geometry and psdf_validate_edges ignore the
  * field).  The
  * table describes the edge arrays' contents at staging time: after changing
@@ -383,7 +385,8 @@ int psdf_batch_plan_info(const psdf_batch_plan* plan, int32_t* stages_per_item,
 /* Certified screened evaluation of a batch (same outputs as psdf_batch, bit
  * for bit).  Per stage: a conservative lower bound LB_i <= sd_i for every
  * obstacle (distance from the pose origin to the obstacle's bounding circle,
- * which a first kernel computes per call, minus the footprint's radius
+ * which a first kernel computes per call unless psdf_batch_stage took them
+ * once, minus the footprint's radius
  * about that origin, minus 1e-3 m), a pool of about `pool` lowest-LB
  * obstacles (1..512) whose bounds are tightened to the distance to the
  * polygon itself (-inf if the origin is inside), a ranking of
@@ -422,6 +425,25 @@ int psdf_batch_screened_bound(psdf_batch_plan* plan, const float* poses, const f
                               const int32_t* obst_off, float* d, int32_t* edge, int32_t* obst,
                               float* grad, uint64_t* keys, int32_t* stage_cand,
                               int32_t* stage_cert, uint64_t* cand_keys, hipStream_t stream);
+
+/* psdf_batch_stage - the bounding circles of every obstacle of the plan's
+ * instances (the pose-independent part of the screened forms' first
+ * kernel), taken once per edge set instead of in every screened call: Alg. 1
+ * re-encodes the environment only when it changes.  Until
+ * psdf_batch_unstage, psdf_batch_screened and psdf_batch_screened_bound read
+ * them, with outputs bit for bit those of the unstaged call; they return
+ * PSDF_EINVAL when called with edge or offset pointers other than the ones
+ * staged.  The circles describe the arrays' contents at staging time: after
+ * changing them in place, stage again (a stale circle can make the
+ * certificate exclude the true winner).  The first call allocates 16 bytes
+ * per obstacle of device memory, held by the plan; each call enqueues one
+ * kernel on `stream`.  Same limits as psdf_batch_screened. */
+int psdf_batch_stage(psdf_batch_plan* plan, const float* ax, const float* ay, const float* bx,
+                     const float* by, const int32_t* obst_off, hipStream_t stream);
+
+/* psdf_batch_unstage - screened calls derive the circles from the edges
+ * again (the staged circles stay allocated until the plan is destroyed). */
+int psdf_batch_unstage(psdf_batch_plan* plan);
 
 /* ------------------------------------------------------------------------
  * Edge-screener MLP: 4 -> 64 -> 64 -> 1 with ReLU on per-(stage, edge)

@@ -33,7 +33,8 @@ class PsdfParams(ctypes.Structure):
 
 class PsdfStaged(ctypes.Structure):
     _fields_ = [("table", ctypes.c_void_p), ("bytes", ctypes.c_size_t), ("E", ctypes.c_int32),
-                ("M", ctypes.c_int32), ("mi_class", ctypes.c_int32), ("eps", ctypes.c_float)]
+                ("M", ctypes.c_int32), ("mi_class", ctypes.c_int32), ("eps", ctypes.c_float),
+                ("src", ctypes.c_void_p * 5)]
 
 
 class PsdfEdges(ctypes.Structure):
@@ -109,6 +110,8 @@ _SIGS = {
     "psdf_timer_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "psdf_validate_edges": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "psdf_staged_bytes": (ctypes.c_size_t, [_I32, _I32]),
+    "psdf_batch_stage": (ctypes.c_int, [ctypes.c_void_p] * 7),
+    "psdf_batch_unstage": (ctypes.c_int, [ctypes.c_void_p]),
     "psdf_stage_edges": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
     "psdf_encode_padded": (ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP,

@@ -376,6 +376,19 @@ class Batch:
         return dict(stages_per_item=vals[0].value, obstacles_per_tile=vals[1].value,
                     n_items=vals[2].value, grid=vals[3].value, direct=vals[4].value)
 
+    def stage(self):
+        """Take the obstacles' bounding circles once for the screened forms
+        (psdf_batch_stage); stage again after changing the edge tensors in
+        place."""
+        _lib.check(_lib.lib().psdf_batch_stage(
+            self.plan, self.ax.data_ptr(), self.ay.data_ptr(), self.bx.data_ptr(),
+            self.by.data_ptr(), self.obst_off.data_ptr(), _lib.stream_handle()))
+        return self
+
+    def unstage(self):
+        _lib.check(_lib.lib().psdf_batch_unstage(self.plan))
+        return self
+
     def screened(self, theta=None, pool=256, topk=256, stats=False):
         """Certified screened evaluation (psdf_batch_screened); theta None
         ranks the pool's edges by distance instead of the MLP.  With

@@ -64,6 +64,12 @@ struct psdf_batch_plan {
   struct SGroup { int mf, start, count, max_tiles; };
   std::vector<SGroup> sgroups;
   int max_M = 0;
+  size_t sum_M = 0;
+  // bounding circles taken once per edge set (psdf_batch_stage), indexed
+  // like the horizon lists, and the edge arrays they were taken from
+  float4* d_circ = nullptr;
+  bool circ_staged = false;
+  const void* circ_src[5] = {};
   // graph
   hipStream_t cap_stream = nullptr;
   // footprint-size groups run concurrently: group k > 0 on side[k - 1],
@@ -479,6 +485,16 @@ static int screened_run(psdf_batch_plan* p, bool bound, const float* theta, int3
     return set_error(PSDF_EINVAL, "a pose, offset or output pointer is NULL");
   if (p->max_M > 0 && (!ax || !ay || !bx || !by)) return set_error(PSDF_EINVAL, "an edge array is NULL");
   if (bound) theta = nullptr;
+  const float4* circ = nullptr;
+  if (p->circ_staged) {
+    const void* src[5] = {ax, ay, bx, by, off};
+    for (int k = 0; k < 5; ++k)
+      if (src[k] != p->circ_src[k])
+        return set_error(PSDF_EINVAL,
+                         "the edge arrays differ from the ones psdf_batch_stage took the circles "
+                         "from (stage again, or psdf_batch_unstage)");
+    circ = p->d_circ;
+  }
   ScreenArgs a;
   a.fps = p->d_fp; a.insts = p->d_inst; a.stage_inst = p->d_stage_inst;
   a.poses = poses; a.ax = ax; a.ay = ay; a.bx = bx; a.by = by; a.off = off;
@@ -492,16 +508,16 @@ static int screened_run(psdf_batch_plan* p, bool bound, const float* theta, int3
     const dim3 grid(kHorizonSplit + (theta ? 1 : 0), p->n_inst);
     if (p->mi_class == 4)
       horizon_kernel<4><<<grid, kScreenThreads, 0, stream>>>(
-          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest,
-          theta, p->d_frag);
+          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, circ, p->d_hlist, p->d_hcount,
+          p->d_hrest, theta, p->d_frag);
     else if (p->mi_class == 8)
       horizon_kernel<8><<<grid, kScreenThreads, 0, stream>>>(
-          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest,
-          theta, p->d_frag);
+          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, circ, p->d_hlist, p->d_hcount,
+          p->d_hrest, theta, p->d_frag);
     else
       horizon_kernel<16><<<grid, kScreenThreads, 0, stream>>>(
-          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, p->d_hlist, p->d_hcount, p->d_hrest,
-          theta, p->d_frag);
+          p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, circ, p->d_hlist, p->d_hcount,
+          p->d_hrest, theta, p->d_frag);
     err = hipGetLastError();
   }
   for (const auto& g : p->sgroups) {
@@ -548,6 +564,47 @@ int psdf_batch_screened_bound(psdf_batch_plan* p, const float* poses, const floa
                       keys, stage_cand, stage_cert, cand_keys, stream);
 }
 
+int psdf_batch_stage(psdf_batch_plan* p, const float* ax, const float* ay, const float* bx,
+                     const float* by, const int32_t* off, hipStream_t stream) {
+  clear_error();
+  if (!p) return set_error(PSDF_EINVAL, "plan is NULL");
+  if (p->max_M > kScreenMaxM)
+    return set_error(PSDF_ETOOBIG, "an instance has %d obstacles; screening supports %d", p->max_M,
+                     kScreenMaxM);
+  if (p->n_inst > 65535)
+    return set_error(PSDF_ETOOBIG, "%d instances; screening supports 65535", p->n_inst);
+  if (p->sum_M > 0) {
+    if (!off) return set_error(PSDF_EINVAL, "obst_off is NULL");
+    if (!ax || !ay || !bx || !by) return set_error(PSDF_EINVAL, "an edge array is NULL");
+    hipError_t err = hipSuccess;
+    if (!p->d_circ) err = hipMalloc(&p->d_circ, p->sum_M * sizeof(float4));
+    if (err != hipSuccess) {
+      p->d_circ = nullptr;
+      return hip_status(err);
+    }
+    const dim3 grid((p->max_M + 255) / 256, p->n_inst);
+    if (p->mi_class == 4)
+      circle_kernel<4><<<grid, 256, 0, stream>>>(p->d_inst, ax, ay, bx, by, off, p->d_circ);
+    else if (p->mi_class == 8)
+      circle_kernel<8><<<grid, 256, 0, stream>>>(p->d_inst, ax, ay, bx, by, off, p->d_circ);
+    else
+      circle_kernel<16><<<grid, 256, 0, stream>>>(p->d_inst, ax, ay, bx, by, off, p->d_circ);
+    err = hipGetLastError();
+    if (err != hipSuccess) return hip_status(err);
+  }
+  p->circ_staged = true;
+  const void* src[5] = {ax, ay, bx, by, off};
+  for (int k = 0; k < 5; ++k) p->circ_src[k] = src[k];
+  return PSDF_OK;
+}
+
+int psdf_batch_unstage(psdf_batch_plan* p) {
+  clear_error();
+  if (!p) return set_error(PSDF_EINVAL, "plan is NULL");
+  p->circ_staged = false;
+  return PSDF_OK;
+}
+
 int psdf_screen_labels(const psdf_batch_plan* p, const float* poses, const float* ax,
                        const float* ay, const float* bx, const float* by, const int32_t* stage,
                        const int32_t* edge, int32_t n, float* X, float* T, hipStream_t stream) {
@@ -583,6 +640,7 @@ void psdf_batch_plan_destroy(psdf_batch_plan* p) {
   (void)hipFree(p->d_failed);
   (void)hipFree(p->d_sctrl);
   (void)hipFree(p->d_hlist);
+  (void)hipFree(p->d_circ);
   (void)hipFree(p->d_frag);
   (void)hipFree(p->d_hcount);
   (void)hipFree(p->d_hrest);
@@ -676,6 +734,7 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
     }
     size_t sumM = 0;
     for (int k = 0; k < n_inst; ++k) sumM += desc[k].M;
+    p->sum_M = sumM;
     err = hipMalloc(&p->d_hlist, std::max<size_t>(1, sumM) * sizeof(float4));
     if (err == hipSuccess) err = hipMalloc(&p->d_frag, (size_t)kFragWords * 64 * sizeof(uint4));
     if (err == hipSuccess)

@@ -114,6 +114,11 @@ __device__ float4 obstacle_circle(const BatchInst& in, const float* __restrict__
 // instance's count is 0 and its bound +inf (plan creation, then the finish
 // kernel of every screened call).  With a network the grid has one more
 // column, whose first work-group builds the network's fragment table.
+// circ (may be null): the instances' bounding circles taken once per edge
+// set (circle_kernel, psdf_batch_stage), indexed like the lists; without it
+// the circles are derived from the edges here.  The circle (or offset)
+// loads are issued before the stage positions' bounding box is reduced, so
+// their latency overlaps that phase.
 // List length: each stage's lower-bound pass reads the whole list, and the
 // bound of the obstacles left out must stay above the stages' minima for the
 // certificate (on c5, 512 certifies every stage; 256 fails 6 % of them).
@@ -126,8 +131,8 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
     const float* __restrict__ poses, const float* __restrict__ ax, const float* __restrict__ ay,
     const float* __restrict__ bx, const float* __restrict__ by, const int* __restrict__ off,
-    float4* __restrict__ hlist, int* __restrict__ hcount, uint32_t* __restrict__ hrest,
-    const float* __restrict__ theta, uint4* __restrict__ frag) {
+    const float4* __restrict__ circ, float4* __restrict__ hlist, int* __restrict__ hcount,
+    uint32_t* __restrict__ hrest, const float* __restrict__ theta, uint4* __restrict__ frag) {
   __shared__ int scan[kScreenThreads];
   __shared__ uint32_t red[kScreenThreads / 64];
   __shared__ int s_base;
@@ -149,6 +154,23 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   const int chunk = (M + kHorizonSplit - 1) / kHorizonSplit;
   const int o0 = part * chunk, o1 = min(M, o0 + chunk);
   if (o0 >= o1) return;   // empty block: nothing to add
+  // the thread's obstacles: their staged circles, or their edge ranges,
+  // loaded together (an index past the block is clamped to its last
+  // obstacle, o1 - 1 < M)
+  float4 cq[kHorizonKeys];
+  int ea[kHorizonKeys], eb[kHorizonKeys];
+#pragma unroll
+  for (int q = 0; q < kHorizonKeys; ++q) {
+    const int o = min(o0 + tid + kScreenThreads * q, o1 - 1);
+    if (circ) {
+      cq[q] = circ[in.circ_off + o];
+      ea[q] = eb[q] = 0;
+    } else {
+      cq[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      ea[q] = off[in.obst_off + o];
+      eb[q] = off[in.obst_off + o + 1];
+    }
+  }
   // bounding box of the stage positions (orderable keys: min of x, y, -x, -y)
   uint32_t bx0 = 0xffffffffu, by0 = 0xffffffffu, bx1 = 0xffffffffu, by1 = 0xffffffffu;
   int bad = 0;
@@ -180,26 +202,15 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   const float R = -from_orderable(nr) * (1.0f + 1e-6f) + 1e-6f;
   const float hoff = R + F.rmax + kLbGamma;
   uint32_t k[kHorizonKeys];
-  float4 cq[kHorizonKeys];
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   int used = 0;
-  // the edge ranges of the thread's obstacles, loaded together (an index
-  // past the block is clamped to its last obstacle, o1 - 1 < M)
-  int ea[kHorizonKeys], eb[kHorizonKeys];
-#pragma unroll
-  for (int q = 0; q < kHorizonKeys; ++q) {
-    const int o = min(o0 + tid + kScreenThreads * q, o1 - 1);
-    ea[q] = off[in.obst_off + o];
-    eb[q] = off[in.obst_off + o + 1];
-  }
 #pragma unroll
   for (int q = 0; q < kHorizonKeys; ++q) {
     const int o = o0 + tid + kScreenThreads * q;
     uint32_t key = 0xffffffffu;
-    cq[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (o < o1) {
-      const float4 c = obstacle_circle<MI>(in, ax, ay, bx, by, ea[q], eb[q]);
-      cq[q] = c;
+      if (!circ) cq[q] = obstacle_circle<MI>(in, ax, ay, bx, by, ea[q], eb[q]);
+      const float4 c = cq[q];
       if (c.x == c.x) {
         const float dx = cx - c.x, dy = cy - c.y;
         key = orderable(sqrtf(fmaf(dx, dx, dy * dy)) - c.z - hoff);
@@ -242,6 +253,21 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
       c.w = __int_as_float(o);
       hlist[in.circ_off + at++] = c;
     }
+}
+
+// Bounding circles of every obstacle of every instance (obstacle_circle),
+// taken once per edge set: grid (ceil(max M / 256), instances), circ
+// indexed like the horizon lists (circ_off + obstacle).
+template <int MI>
+__global__ __launch_bounds__(256) void circle_kernel(
+    const BatchInst* __restrict__ insts, const float* __restrict__ ax,
+    const float* __restrict__ ay, const float* __restrict__ bx, const float* __restrict__ by,
+    const int* __restrict__ off, float4* __restrict__ circ) {
+  const BatchInst in = insts[blockIdx.y];
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o >= in.M) return;
+  circ[in.circ_off + o] =
+      obstacle_circle<MI>(in, ax, ay, bx, by, off[in.obst_off + o], off[in.obst_off + o + 1]);
 }
 
 }  // namespace psdf

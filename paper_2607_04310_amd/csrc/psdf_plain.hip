@@ -447,6 +447,11 @@ static int check_staged(const psdf_edges& e, const FpConst& F) {
                      "staged table made for E = %d, M = %d, edge class %d; the edge set has "
                      "E = %d, M = %d, edge class %d",
                      s->E, s->M, s->mi_class, e.E, e.M, cls);
+  const void* src[5] = {e.ax, e.ay, e.bx, e.by, e.obst_off};
+  for (int k = 0; k < 5; ++k)
+    if (s->src[k] != src[k])
+      return set_error(PSDF_EINVAL,
+                       "staged table made from other edge arrays (stage this edge set again)");
   if (__builtin_memcmp(&s->eps, &F.eps, sizeof(float)) != 0)
     return set_error(PSDF_EINVAL, "staged table made with eps = %g, the call has eps = %g",
                      (double)s->eps, (double)F.eps);
@@ -519,6 +524,8 @@ int psdf_stage_edges(const psdf_edges* edges, const psdf_params* params, void* t
   out->M = e.M;
   out->mi_class = cls;
   out->eps = eps;
+  const void* src[5] = {e.ax, e.ay, e.bx, e.by, e.obst_off};
+  for (int k = 0; k < 5; ++k) out->src[k] = src[k];
   return PSDF_OK;
 }
 

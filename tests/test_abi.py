@@ -163,8 +163,8 @@ def test_validate_edges_argument_checks():
     assert lib.psdf_validate_edges(ctypes.byref(bad_mbar), ctypes.c_void_p(16), None) == _lib.PSDF_ETOOBIG
 
 
-def _staged(E=4, M=1, cls=4, eps=1e-12, table=256, nbytes=1 << 20):
-    return _lib.PsdfStaged(table, nbytes, E, M, cls, eps)
+def _staged(E=4, M=1, cls=4, eps=1e-12, table=256, nbytes=1 << 20, src=(1, 1, 1, 1, 1)):
+    return _lib.PsdfStaged(table, nbytes, E, M, cls, eps, (ctypes.c_void_p * 5)(*src))
 
 
 def test_staged_table_size():
@@ -200,6 +200,13 @@ def test_stage_edges_argument_checks():
     empty = _lib.PsdfEdges(0, 0, 0, 0, 1, 0, 0, 4)
     assert stage(edges=empty, table=None, nbytes=0) == _lib.PSDF_OK
     assert (out.E, out.M, out.mi_class) == (0, 0, 4)
+    assert list(out.src) == [None, None, None, None, 1]
+
+
+def test_batch_stage_argument_checks():
+    lib = _lib.lib()
+    assert lib.psdf_batch_stage(None, 1, 1, 1, 1, 1, None) == _lib.PSDF_EINVAL
+    assert lib.psdf_batch_unstage(None) == _lib.PSDF_EINVAL
 
 
 @pytest.mark.parametrize("fields,ok", [
@@ -211,6 +218,7 @@ def test_stage_edges_argument_checks():
     (dict(table=None), False),
     (dict(table=264), False),                # misaligned
     (dict(nbytes=100), False),               # too small
+    (dict(src=(1, 1, 1, 2, 1)), False),      # made from other arrays
 ])
 def test_staged_table_must_match_the_call(fields, ok):
     st = _staged(**fields)

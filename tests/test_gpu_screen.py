@@ -447,3 +447,76 @@ def test_screened_fallback_triggers(api):
         check_stages(inst.footprint, inst.poses, inst.edges, inst.obst_off, 1000.0, d[sl], e[sl],
                      o[sl], g[sl])
     b.close()
+
+
+# ---------------------------------------------------------------- staged circles
+
+def _all_forms(b, theta):
+    outs = {}
+    for name, fn in (("bound", lambda: b.screened_bound()),
+                     ("distance", lambda: b.screened(None, pool=128, topk=256)),
+                     ("mlp", lambda: b.screened(theta, pool=128, topk=256)),
+                     ("fallback", lambda: b.screened(None, pool=1, topk=1))):
+        out = fn()
+        torch.cuda.synchronize()
+        outs[name] = [x.clone() for x in out]
+    return outs
+
+
+def test_staged_circles_same_results(api):
+    """psdf_batch_stage: every screened form reads the circles taken once per
+    edge set and gives the unstaged call's outputs bit for bit, on c5
+    instances, an uneven mixed batch (free segments, a NaN pose, an open
+    chain, empty instances) and the fallback-trigger batch."""
+    rng = np.random.default_rng(31)
+    mixed = [inputs.random_small(rng, n_obst=40, n_poses=30, segments=6, lo=-3, hi=3) for _ in range(5)]
+    mixed[1].poses = mixed[1].poses.copy()
+    mixed[1].poses[4, 0] = np.nan
+    mixed.append(inputs.random_small(rng, n_obst=0, n_poses=10))
+    fp = inputs.hexagon_footprint(inputs.rng_for(2, 0))
+    chain = inputs.Instance(fp, np.array([[3.0, 1.0, 0.0], [3.0, 1.0, 0.4]], np.float32),
+                            np.array([[0, 0, 4, 0], [4, 0, 4, 4]], np.float32),
+                            np.array([0, 2], np.int32), 4, dict(workload="open_chain"))
+    batches = [inputs.c5(8), mixed + [chain], [_copies_instance(2500, (10.0, 0.0), 0.3, 6, 5),
+                                             inputs.c5_instance(5)]]
+    theta = torch.tensor(_rand_theta(7), device="cuda")
+    for insts in batches:
+        b = api.Batch(insts, graph=False)
+        print(f"[staged circles] {len(insts)} instances, {sum(i.M for i in insts)} obstacles",
+              flush=True)
+        plain = _run_plain(b)
+        ref = _all_forms(b, theta)
+        b.stage()
+        got = _all_forms(b, theta)
+        for name in ref:
+            _assert_same(got[name], ref[name])
+            _assert_same(got[name], plain)
+        b.unstage()
+        _assert_same(_all_forms(b, theta)["bound"], plain)
+        b.close()
+
+
+def test_staged_circles_checks_and_restage(api):
+    """A screened call with other edge tensors than the staged ones is
+    refused; after an in-place change of the edges, staging again gives the
+    new edge set's outputs."""
+    from paper_2607_04310_amd import _lib
+    insts = inputs.c5(4)
+    b = api.Batch(insts, graph=False).stage()
+    old_ax = b.ax
+    b.ax = b.ax.clone()
+    with pytest.raises(_lib.PsdfError):
+        b.screened_bound()
+    b.ax = old_ax
+    b.screened_bound()
+    for col in (b.ax, b.bx):
+        col.add_(0.61)
+    b.stage()
+    plain = _run_plain(b)
+    out = b.screened_bound()
+    torch.cuda.synchronize()
+    _assert_same([x.clone() for x in out], plain)
+    out = b.screened(None, pool=128, topk=256)
+    torch.cuda.synchronize()
+    _assert_same([x.clone() for x in out], plain)
+    b.close()

@@ -426,18 +426,20 @@ int psdf_batch_screened_bound(psdf_batch_plan* plan, const float* poses, const f
                               float* grad, uint64_t* keys, int32_t* stage_cand,
                               int32_t* stage_cert, uint64_t* cand_keys, hipStream_t stream);
 
-/* psdf_batch_stage - the bounding circles of every obstacle of the plan's
- * instances (the pose-independent part of the screened forms' first
- * kernel), taken once per edge set instead of in every screened call: Alg. 1
- * re-encodes the environment only when it changes.  Until
+/* psdf_batch_stage - the pose-independent part of the screened forms, taken
+ * once per edge set instead of in every screened call (Alg. 1 re-encodes the
+ * environment only when it changes): every obstacle's bounding circle, and
+ * its row of constants for the exact evaluations (unit edge directions,
+ * lengths, own-axis intervals of Sec. IV-C, flags).  Until
  * psdf_batch_unstage, psdf_batch_screened and psdf_batch_screened_bound read
  * them, with outputs bit for bit those of the unstaged call; they return
  * PSDF_EINVAL when called with edge or offset pointers other than the ones
  * staged.  The circles describe the arrays' contents at staging time: after
  * changing them in place, stage again (a stale circle can make the
- * certificate exclude the true winner).  The first call allocates 16 bytes
- * per obstacle of device memory, held by the plan; each call enqueues one
- * kernel on `stream`.  Same limits as psdf_batch_screened. */
+ * certificate exclude the true winner).  The first call allocates device
+ * memory held by the plan: 16 bytes per obstacle for the circles and
+ * 40 * edge class + 16 bytes for the rows; each call enqueues one kernel on
+ * `stream`.  Same limits as psdf_batch_screened. */
 int psdf_batch_stage(psdf_batch_plan* plan, const float* ax, const float* ay, const float* bx,
                      const float* by, const int32_t* obst_off, hipStream_t stream);
 

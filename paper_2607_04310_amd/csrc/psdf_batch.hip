@@ -68,6 +68,7 @@ struct psdf_batch_plan {
   // bounding circles taken once per edge set (psdf_batch_stage), indexed
   // like the horizon lists, and the edge arrays they were taken from
   float4* d_circ = nullptr;
+  unsigned char* d_rows = nullptr;   // staged obstacle rows (psdf_staged.hpp)
   bool circ_staged = false;
   const void* circ_src[5] = {};
   // graph
@@ -496,6 +497,7 @@ static int screened_run(psdf_batch_plan* p, bool bound, const float* theta, int3
     circ = p->d_circ;
   }
   ScreenArgs a;
+  a.rows = circ ? p->d_rows : nullptr;
   a.fps = p->d_fp; a.insts = p->d_inst; a.stage_inst = p->d_stage_inst;
   a.poses = poses; a.ax = ax; a.ay = ay; a.bx = bx; a.by = by; a.off = off;
   a.hlist = p->d_hlist; a.hcount = p->d_hcount; a.hrest = p->d_hrest;
@@ -577,18 +579,23 @@ int psdf_batch_stage(psdf_batch_plan* p, const float* ax, const float* ay, const
     if (!off) return set_error(PSDF_EINVAL, "obst_off is NULL");
     if (!ax || !ay || !bx || !by) return set_error(PSDF_EINVAL, "an edge array is NULL");
     hipError_t err = hipSuccess;
-    if (!p->d_circ) err = hipMalloc(&p->d_circ, p->sum_M * sizeof(float4));
-    if (err != hipSuccess) {
-      p->d_circ = nullptr;
-      return hip_status(err);
+    if (!p->d_circ) {
+      err = hipMalloc(&p->d_circ, p->sum_M * sizeof(float4));
+      if (err != hipSuccess) p->d_circ = nullptr;
     }
+    if (err == hipSuccess && !p->d_rows) {
+      err = hipMalloc(&p->d_rows, p->sum_M * (size_t)(40 * p->mi_class + 16));
+      if (err != hipSuccess) p->d_rows = nullptr;
+    }
+    if (err != hipSuccess) return hip_status(err);
     const dim3 grid((p->max_M + 255) / 256, p->n_inst);
-    if (p->mi_class == 4)
-      circle_kernel<4><<<grid, 256, 0, stream>>>(p->d_inst, ax, ay, bx, by, off, p->d_circ);
-    else if (p->mi_class == 8)
-      circle_kernel<8><<<grid, 256, 0, stream>>>(p->d_inst, ax, ay, bx, by, off, p->d_circ);
-    else
-      circle_kernel<16><<<grid, 256, 0, stream>>>(p->d_inst, ax, ay, bx, by, off, p->d_circ);
+#define PSDF_STAGE_BATCH(MI)                                                               \
+  stage_batch_kernel<MI><<<grid, 256, 0, stream>>>(p->d_fp, p->d_inst, ax, ay, bx, by, off, \
+                                                   p->d_circ, p->d_rows)
+    if (p->mi_class == 4) PSDF_STAGE_BATCH(4);
+    else if (p->mi_class == 8) PSDF_STAGE_BATCH(8);
+    else PSDF_STAGE_BATCH(16);
+#undef PSDF_STAGE_BATCH
     err = hipGetLastError();
     if (err != hipSuccess) return hip_status(err);
   }
@@ -641,6 +648,7 @@ void psdf_batch_plan_destroy(psdf_batch_plan* p) {
   (void)hipFree(p->d_sctrl);
   (void)hipFree(p->d_hlist);
   (void)hipFree(p->d_circ);
+  (void)hipFree(p->d_rows);
   (void)hipFree(p->d_frag);
   (void)hipFree(p->d_hcount);
   (void)hipFree(p->d_hrest);

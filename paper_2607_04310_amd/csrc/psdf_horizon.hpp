@@ -255,19 +255,30 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     }
 }
 
-// Bounding circles of every obstacle of every instance (obstacle_circle),
-// taken once per edge set: grid (ceil(max M / 256), instances), circ
-// indexed like the horizon lists (circ_off + obstacle).
+// The pose-independent part of the screened forms, taken once per edge set
+// (psdf_batch_stage): every obstacle's bounding circle (obstacle_circle) and
+// its staged row (write_row: the registers the screen kernels' exact
+// evaluation loads, made by load_obstacle + own_intervals exactly as they
+// do), both indexed like the horizon lists (circ_off + obstacle).  Grid
+// (ceil(max M / 256), instances).
 template <int MI>
-__global__ __launch_bounds__(256) void circle_kernel(
-    const BatchInst* __restrict__ insts, const float* __restrict__ ax,
-    const float* __restrict__ ay, const float* __restrict__ bx, const float* __restrict__ by,
-    const int* __restrict__ off, float4* __restrict__ circ) {
+__global__ __launch_bounds__(256) void stage_batch_kernel(
+    const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
+    const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ bx,
+    const float* __restrict__ by, const int* __restrict__ off, float4* __restrict__ circ,
+    unsigned char* __restrict__ rows) {
   const BatchInst in = insts[blockIdx.y];
   const int o = blockIdx.x * 256 + threadIdx.x;
   if (o >= in.M) return;
-  circ[in.circ_off + o] =
-      obstacle_circle<MI>(in, ax, ay, bx, by, off[in.obst_off + o], off[in.obst_off + o + 1]);
+  const int a = off[in.obst_off + o], b = off[in.obst_off + o + 1];
+  circ[in.circ_off + o] = obstacle_circle<MI>(in, ax, ay, bx, by, a, b);
+  const int mi = b - a;
+  Obst<MI> ob;
+  load_obstacle<MI>(ob, ax, ay, bx, by, in.edge_off + a, mi, in.edge_off + in.E,
+                    fps[blockIdx.y].eps);
+  if (a < 0) ob.bad = true;
+  own_intervals<MI>(ob);
+  write_row<MI>(rows, (size_t)in.circ_off + o, ob, a, mi);
 }
 
 }  // namespace psdf

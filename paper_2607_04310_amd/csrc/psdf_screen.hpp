@@ -32,6 +32,7 @@
 
 #include "psdf_batch.hpp"
 #include "psdf_mlp.hpp"
+#include "psdf_staged.hpp"
 
 namespace psdf {
 
@@ -57,6 +58,7 @@ struct ScreenArgs {
   const float* bx;
   const float* by;
   const int* off;
+  const unsigned char* rows;  // staged obstacle rows (circ_off + local index), or nullptr
   const float4* hlist;     // per instance (at circ_off): the circles its stages screen, the
                            // obstacle's local index in .w (int bits)
   const int* hcount;       // per instance: length of hlist, or -1 for every obstacle
@@ -72,6 +74,30 @@ struct ScreenArgs {
   int* stage_cert;         // optional: 1 if certified
   uint64_t* cand_keys;     // optional: the candidates' minimum key (before any fallback)
 };
+
+// Obstacle o (local index) of instance `in` in registers: from its staged
+// row when the screened call has rows, else from the offsets and the edges
+// (load_obstacle; an out-of-range first edge marks it invalid).  mi gets
+// its edge count (0 for an inactive lane).
+template <int MI>
+__device__ __forceinline__ void screen_obstacle(Obst<MI>& ob, const ScreenArgs& A,
+                                                const BatchInst& in, int o, bool act, float eps,
+                                                int& mi) {
+  if (A.rows) {
+    int a;
+    row_obstacle<MI>(ob, A.rows, (size_t)in.circ_off + (act ? o : 0), act, a, mi);
+    return;
+  }
+  int e0 = 0;
+  mi = 0;
+  if (act) {
+    e0 = A.off[in.obst_off + o];
+    mi = A.off[in.obst_off + o + 1] - e0;
+    e0 += in.edge_off;
+  }
+  load_obstacle<MI>(ob, A.ax, A.ay, A.bx, A.by, e0, mi, in.edge_off + in.E, eps);
+  if (act && e0 < in.edge_off) ob.bad = true;
+}
 
 __device__ __forceinline__ float obstacle_lb(float px, float py, const float* __restrict__ ax,
                                              const float* __restrict__ ay,
@@ -415,16 +441,10 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
     for (int c0 = 0; c0 < n_cand; c0 += kScreenThreads) {
       const int c = c0 + tid;
       const bool act = c < n_cand;
-      int e0 = 0, mi = 0, o = 0;
-      if (act) {
-        o = cand_o[c];
-        e0 = off[o];
-        mi = off[o + 1] - e0;
-        e0 += in.edge_off;
-      }
+      const int o = act ? cand_o[c] : 0;
+      int mi;
       Obst<MI> ob;
-      load_obstacle<MI>(ob, A.ax, A.ay, A.bx, A.by, e0, mi, Eend, F.eps);
-      if (act && e0 < in.edge_off) ob.bad = true;
+      screen_obstacle<MI>(ob, A, in, o, act, F.eps, mi);
       uint32_t kk = 0xffffffffu;
       if (act && mi != 0) kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, rf, px, py)) : 0u;
       const uint64_t key = kk == 0xffffffffu ? kEmptyKey : (((uint64_t)kk << 32) | (uint32_t)o);
@@ -514,9 +534,7 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
   sincosf(p[2], &sn, &cs);
   const bool pose_ok = isfinite(px) && isfinite(py) && isfinite(cs) && isfinite(sn);
   if (lane < MF) rf[lane] = rotated_slot(F, lane, cs, sn);
-  const int Eend = in.edge_off + in.E;
-  const int* off = A.off + in.obst_off;
-
+  
   const int hc = A.hcount[inst];
   if (hc < 0 || hc > kHorizonCap) {
     if (lane == 0) {
@@ -540,11 +558,13 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
     return orderable(pose_ok ? lbv : -__builtin_huge_valf());
   };
 
-  // ---- pass 1: the seed, the smallest bound (lowest list slot on ties)
+  // ---- pass 1: the seed, the smallest bound (lowest list slot on ties);
+  // the key's low word is (slot << 16 | obstacle): slot < 2048, obstacle <
+  // 16384, so the wave minimum names the seed without another list read
   uint64_t lo = ~0ull;
   for (int idx = lane; idx < hc; idx += 64) {
     int o;
-    const uint64_t v = ((uint64_t)lb_key(idx, o) << 32) | (uint32_t)idx;
+    const uint64_t v = ((uint64_t)lb_key(idx, o) << 32) | ((uint32_t)idx << 16) | (uint32_t)o;
     lo = v < lo ? v : lo;
   }
   lo = wave_min_u64(lo);
@@ -552,13 +572,12 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
   uint64_t seed_key = kEmptyKey;
   int seed_o = -1;
   if (lo != ~0ull) {
-    seed_o = __float_as_int(hl[(int)(uint32_t)lo].w);
+    seed_o = (int)(lo & 0xffffu);
     uint32_t kk = 0u;
     if (lane == 0) {
-      const int a = off[seed_o], mi = off[seed_o + 1] - a;
+      int mi;
       Obst<MI> ob;
-      load_obstacle<MI>(ob, A.ax, A.ay, A.bx, A.by, in.edge_off + a, mi, Eend, F.eps);
-      if (a < 0) ob.bad = true;
+      screen_obstacle<MI>(ob, A, in, seed_o, true, F.eps, mi);
       kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, rf, px, py)) : 0u;
     }
     kk = lane_u32(kk, 0);
@@ -590,16 +609,10 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
     for (int c0 = 0; c0 < n_cand; c0 += 64) {
       const int c = c0 + lane;
       const bool act = c < n_cand;
-      int e0 = 0, mi = 0, o = 0;
-      if (act) {
-        o = cand_o[c];
-        e0 = off[o];
-        mi = off[o + 1] - e0;
-        e0 += in.edge_off;
-      }
+      const int o = act ? cand_o[c] : 0;
+      int mi;
       Obst<MI> ob;
-      load_obstacle<MI>(ob, A.ax, A.ay, A.bx, A.by, e0, mi, Eend, F.eps);
-      if (act && e0 < in.edge_off) ob.bad = true;
+      screen_obstacle<MI>(ob, A, in, o, act, F.eps, mi);
       uint32_t kk = 0xffffffffu;
       if (act && mi != 0) kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, rf, px, py)) : 0u;
       const uint64_t key = kk == 0xffffffffu ? kEmptyKey : (((uint64_t)kk << 32) | (uint32_t)o);
@@ -651,15 +664,9 @@ __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int 
       __syncthreads();
       const int o = tile * 256 + tid;
       const bool act = o < in.M;
-      int e0 = 0, mi = 0;
-      if (act) {
-        e0 = A.off[in.obst_off + o];
-        mi = A.off[in.obst_off + o + 1] - e0;
-        e0 += in.edge_off;
-      }
+      int mi;
       Obst<MI> ob;
-      load_obstacle<MI>(ob, A.ax, A.ay, A.bx, A.by, e0, mi, in.edge_off + in.E, F.eps);
-      if (act && e0 < in.edge_off) ob.bad = true;
+      screen_obstacle<MI>(ob, A, in, o, act, F.eps, mi);
       uint32_t kk = 0xffffffffu;
       if (act && mi != 0) kk = pose_ok ? orderable(obstacle_sd<MF, MI>(F, ob, rf, px, py)) : 0u;
       const uint64_t key = kk == 0xffffffffu ? kEmptyKey : (((uint64_t)kk << 32) | (uint32_t)o);

@@ -111,4 +111,72 @@ __device__ __forceinline__ void staged_obstacle(Obst<MIX>& o, const StagedView& 
   }
 }
 
+// Row-major form for gathers (the screened batch, psdf_batch_stage): one row
+// of 40 * MI + 16 bytes per obstacle, indexed like the horizon lists
+// (circ_off + local obstacle):
+//   float4 [MI]  (A_j.x, A_j.y, u_j.x, u_j.y)
+//   float4 [MI]  (|B_j - A_j|, own-axis interval lo, hi, 0)
+//   float2 [MI]  B_j (read only for an open obstacle)
+//   int4         (local first edge a, edge count mi, closed | bad << 1, 0)
+// A lane that evaluates a scattered obstacle reads its row with one round
+// trip (the meta and slot loads are issued together) instead of an offset
+// load followed by the edge loads, and skips the per-lane setup.
+template <int MI>
+constexpr int kRowBytes = 40 * MI + 16;
+
+template <int MI>
+__device__ __forceinline__ void write_row(unsigned char* __restrict__ rows, size_t r,
+                                          const Obst<MI>& o, int a, int mi) {
+  unsigned char* b = rows + r * kRowBytes<MI>;
+  float4* A = reinterpret_cast<float4*>(b);
+  float4* B = reinterpret_cast<float4*>(b + 16 * MI);
+  float2* P = reinterpret_cast<float2*>(b + 32 * MI);
+#pragma unroll
+  for (int j = 0; j < MI; ++j) {
+    A[j] = make_float4(o.ax[j], o.ay[j], o.ux[j], o.uy[j]);
+    B[j] = make_float4(o.len[j], o.olo[j], o.ohi[j], 0.f);
+    P[j] = make_float2(o.bx[j], o.by[j]);
+  }
+  *reinterpret_cast<int4*>(b + 40 * MI) = make_int4(a, mi, (o.closed ? 1 : 0) | (o.bad ? 2 : 0), 0);
+}
+
+// The obstacle of row r as the registers load_obstacle + own_intervals
+// would hold (an inactive lane gets the empty obstacle); a and mi receive
+// the row's local first edge and edge count.
+template <int MI>
+__device__ __forceinline__ void row_obstacle(Obst<MI>& o, const unsigned char* __restrict__ rows,
+                                             size_t r, bool act, int& a, int& mi) {
+  const unsigned char* b = rows + r * kRowBytes<MI>;
+  int4 meta = make_int4(0, 0, 0, 0);
+  float4 A[MI], B[MI];
+#pragma unroll
+  for (int j = 0; j < MI; ++j) {
+    A[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    B[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  if (act) {
+    meta = *reinterpret_cast<const int4*>(b + 40 * MI);
+#pragma unroll
+    for (int j = 0; j < MI; ++j) {
+      A[j] = reinterpret_cast<const float4*>(b)[j];
+      B[j] = reinterpret_cast<const float4*>(b + 16 * MI)[j];
+    }
+  }
+  a = meta.x;
+  mi = meta.y;
+  o.mi = mi;
+  o.closed = (meta.z & 1) != 0;
+  o.bad = (meta.z & 2) != 0;
+  o.own = true;
+  const bool open = act && !o.closed;
+#pragma unroll
+  for (int j = 0; j < MI; ++j) {
+    o.ax[j] = A[j].x; o.ay[j] = A[j].y; o.ux[j] = A[j].z; o.uy[j] = A[j].w;
+    o.len[j] = B[j].x; o.olo[j] = B[j].y; o.ohi[j] = B[j].z;
+    float2 q = make_float2(0.f, 0.f);
+    if (open) q = reinterpret_cast<const float2*>(b + 32 * MI)[j];
+    o.bx[j] = q.x; o.by[j] = q.y;
+  }
+}
+
 }  // namespace psdf

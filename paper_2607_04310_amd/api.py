@@ -67,10 +67,14 @@ class EdgeSet:
         """Take the edge set's pose-independent constants once
         (psdf_stage_edges, Alg. 1 EncodeEdges): later calls with this EdgeSet
         read them from a device table.  Stage again after changing the edge
-        tensors in place."""
+        tensors in place (the table is rewritten in place)."""
         params = params or Params()
         nbytes = int(_lib.lib().psdf_staged_bytes(self.M, self.mbar))
-        table = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=self.ax.device)
+        # staging again rewrites the same table, so that graphs captured on
+        # this edge set keep reading it
+        table = self._table
+        if table is None or table.numel() < max(nbytes, 16):
+            table = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=self.ax.device)
         st = _lib.PsdfStaged()
         ec, pc = self._plain(), params.c()
         _lib.check(_lib.lib().psdf_stage_edges(ctypes.byref(ec), ctypes.byref(pc),

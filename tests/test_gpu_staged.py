@@ -230,3 +230,43 @@ def test_table_made_with_another_eps_is_refused(api):
         _grad(api, inst, edges, api.Params())
     edges.unstage()
     _grad(api, inst, edges, api.Params())
+
+
+def test_graph_replays_of_staged_calls(api):
+    """psdf_grad on a staged edge set captured in a HIP graph: every replay,
+    with eager work and synchronisations between them, equals the eager
+    call; after staging again from changed edges, replays give the new
+    outputs (the graph reads the table, which the staging kernel rewrote)."""
+    inst = inputs.c2(4)
+    p = api.Params()
+    poses = torch.tensor(inst.poses, device="cuda")
+    edges = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar).stage(p)
+    ws = api.workspace(inst.N, inst.M, "cuda")
+    out = api.psdf_grad(inst.footprint, poses, edges, p, ws=ws)
+    torch.cuda.synchronize()
+    ref = [x.clone() for x in out]
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cap):
+        api.psdf_grad(inst.footprint, poses, edges, p, out=out, ws=ws)
+    for r in range(4):
+        for x in out:
+            x.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for x, y in zip(out, ref):
+            assert _same(x, y), r
+        api.psdf_grad(inst.footprint, poses, edges, p, ws=torch.empty_like(ws))  # eager work between
+        torch.cuda.synchronize()
+    for col in (edges.ay, edges.by):
+        col.sub_(0.29)
+    edges.stage(p)
+    fresh = api.EdgeSet.from_device(edges.ax, edges.ay, edges.bx, edges.by, edges.obst_off,
+                                    edges.mbar)
+    ref2 = [x.clone() for x in _grad(api, inst, fresh, p)]
+    g.replay()
+    torch.cuda.synchronize()
+    for x, y in zip(out, ref2):
+        assert _same(x, y)
+    del g

@@ -182,12 +182,12 @@ int psdf_constraints(const float* footprint, int32_t m, const float* poses, int3
                      float* hj_host, uint64_t* keys, void* ws, size_t ws_bytes,
                      hipStream_t stream);
 
-/* psdf_time_stage_min - measurement aid: enqueues `reps` back-to-back
+/* psdf_time_stage_min - measurement aid: enqueues `reps` (1..100000)
  * launches of psdf_eval's per-stage-minimum kernel (the same launch shape)
- * on `stream` between two events, waits for them, and stores the mean time
- * per launch in *ms (host).  Back-to-back launches keep the events' own
- * overhead out of the per-launch figure.  Writes only the workspace (sized
- * as for psdf_eval). */
+ * on `stream`, each with an event pair that the dispatch records at its own
+ * start and end, waits for them, and stores the mean kernel duration in *ms
+ * (host): the kernel's own time, whatever the host's enqueue rate.  Writes
+ * only the workspace (sized as for psdf_eval). */
 int psdf_time_stage_min(const float* footprint, int32_t m, const float* poses, int32_t N,
                         const psdf_edges* edges, const psdf_params* params, void* ws,
                         size_t ws_bytes, int32_t reps, hipStream_t stream, float* ms);

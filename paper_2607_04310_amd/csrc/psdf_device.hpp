@@ -133,11 +133,30 @@ __device__ __forceinline__ void load_obstacle(Obst<MI>& o, const float* __restri
   const int n = o.bad ? 1 : (mi < 1 ? 1 : mi);
   const int base = o.bad ? 0 : e0;
   const bool any = !o.bad && mi > 0;
+  // a four-edge obstacle whose edges start at 16-byte aligned addresses
+  // (rectangles in a CSR set of rectangles) takes one vector load per array;
+  // the values are the same either way
+  const uintptr_t al = reinterpret_cast<uintptr_t>(ax + base) | reinterpret_cast<uintptr_t>(ay + base) |
+                       reinterpret_cast<uintptr_t>(bx + base) | reinterpret_cast<uintptr_t>(by + base);
+  const bool vec = MI >= 4 && any && n == 4 && (al & 15u) == 0;
+  float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0, v2 = v0, v3 = v0;
+  if (vec) {
+    v0 = *reinterpret_cast<const float4*>(ax + base);
+    v1 = *reinterpret_cast<const float4*>(ay + base);
+    v2 = *reinterpret_cast<const float4*>(bx + base);
+    v3 = *reinterpret_cast<const float4*>(by + base);
+  }
+  const float x0[4] = {v0.x, v0.y, v0.z, v0.w}, y0[4] = {v1.x, v1.y, v1.z, v1.w};
+  const float x1[4] = {v2.x, v2.y, v2.z, v2.w}, y1[4] = {v3.x, v3.y, v3.z, v3.w};
 #pragma unroll
   for (int j = 0; j < MI; ++j) {
     const int jj = j < n ? j : n - 1;
     float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
-    if (any) {
+    if (vec) {
+      const int q = j < 4 ? j : 3;
+      a0 = x0[q]; a1 = y0[q];
+      b0 = x1[q]; b1 = y1[q];
+    } else if (any) {
       a0 = ax[base + jj]; a1 = ay[base + jj];
       b0 = bx[base + jj]; b1 = by[base + jj];
     }
@@ -168,22 +187,35 @@ __device__ __forceinline__ void load_obstacle(Obst<MI>& o, const float* __restri
 }
 
 // Own-axis intervals (Sec. IV-C), relative to A_j: pose independent, needed
-// only at stages that no robot axis separates, so taken on first need.
-template <int MI>
+// only at stages that no robot axis separates, so taken on first need.  With
+// LAZY the obstacle's coordinates pass through empty asm statements first (no
+// instruction, the same values), which keeps the compiler from computing the
+// intervals ahead of that need, so a wave whose lanes are all separated by a
+// robot axis skips them (the plain path at one stage per wave, where each
+// wave meets its obstacles once).  Without it the compiler takes them once,
+// ahead of the stage loop (the batch kernel's many-stage items, where that
+// is cheaper).
+template <int MI, bool LAZY = false>
 __device__ __forceinline__ void own_intervals(Obst<MI>& o) {
+  float ax[MI], ay[MI], ux[MI], uy[MI];
+#pragma unroll
+  for (int k = 0; k < MI; ++k) {
+    ax[k] = o.ax[k]; ay[k] = o.ay[k]; ux[k] = o.ux[k]; uy[k] = o.uy[k];
+    if (LAZY) asm volatile("" : "+v"(ax[k]), "+v"(ay[k]), "+v"(ux[k]), "+v"(uy[k]));
+  }
 #pragma unroll
   for (int j = 0; j < MI; ++j) {
     float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
 #pragma unroll
     for (int k = 0; k < MI; ++k) {
-      const float q = fmaf(o.ay[k] - o.ay[j], o.ux[j], -((o.ax[k] - o.ax[j]) * o.uy[j]));
+      const float q = fmaf(ay[k] - ay[j], ux[j], -((ax[k] - ax[j]) * uy[j]));
       lo = fminf(lo, q);
       hi = fmaxf(hi, q);
     }
     if (!o.closed) {
 #pragma unroll
       for (int k = 0; k < MI; ++k) {
-        const float q = fmaf(o.by[k] - o.ay[j], o.ux[j], -((o.bx[k] - o.ax[j]) * o.uy[j]));
+        const float q = fmaf(o.by[k] - ay[j], ux[j], -((o.bx[k] - ax[j]) * uy[j]));
         lo = fminf(lo, q);
         hi = fmaxf(hi, q);
       }
@@ -228,7 +260,7 @@ __device__ __forceinline__ float frame_d2(float a, float b, float L) {
 // of footprint slots evaluated: the exact m (3..8) or 16 (padded); rf holds
 // the footprint rotated by the stage heading (rotated_slot, MF slots) and
 // (px, py) is the stage position.
-template <int MF, int MI>
+template <int MF, int MI, bool LAZY = false>
 __device__ __forceinline__ float obstacle_sd(const FpConst& F, Obst<MI>& o,
                                              const float4* rf, float px, float py) {
   // the obstacle translated to the pose origin, and its edge frames' offsets
@@ -295,7 +327,7 @@ __device__ __forceinline__ float obstacle_sd(const FpConst& F, Obst<MI>& o,
     sep = sep || (dl[l] < -F.eps_sat);
   }
   if (!sep) {
-    if (!o.own) own_intervals<MI>(o);
+    if (!o.own) own_intervals<MI, LAZY>(o);
 #pragma unroll
     for (int j = 0; j < MI; ++j) {
       dl[MF + j] = fminf(o.ohi[j] - rlo[j], rhi[j] - o.olo[j]);

@@ -62,7 +62,10 @@ __global__ __launch_bounds__(BLK) void main_kernel(FpConst F, const float* __res
         }
       }
     };
-    wave_stages<MF, MI>(F, ax, ay, bx, by, e0, mi, E, active, false, wave_base, ns, st, rft, emit);
+    // lazy own-axis intervals: a wave meets its obstacles at one or a few
+    // stages here, and far obstacles never need them
+    wave_stages<MF, MI, decltype(emit), true>(F, ax, ay, bx, by, e0, mi, E, active, false,
+                                              wave_base, ns, st, rft, emit);
   } else if (NW > 1 && lane == 0) {
     for (int t = 0; t < ns; ++t) { wk[w][t] = kEmptyKey; wa[w][t] = 0; }
   }

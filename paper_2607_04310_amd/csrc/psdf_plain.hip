@@ -12,6 +12,7 @@
 
 #include <cmath>
 #include <mutex>
+#include <vector>
 
 #include "psdf.h"
 #include "psdf_kernels.hpp"
@@ -582,22 +583,28 @@ int psdf_time_stage_min(const float* footprint, int32_t m, const float* poses, i
     return set_error(PSDF_EWS, "workspace of %zu bytes, %zu needed", ws_bytes, need);
   if ((reinterpret_cast<uintptr_t>(ws) & 15u) != 0)
     return set_error(PSDF_EINVAL, "workspace is not 16-byte aligned");
+  if (reps > 100000) return set_error(PSDF_EINVAL, "reps = %d, at most 100000", reps);
   const LaunchShape ls = tuned_shape(F.m, e.mbar, N, e.M);
   uint64_t* partial = static_cast<uint64_t*>(ws);
-  hipEvent_t a = nullptr, b = nullptr;
-  hipError_t err = hipEventCreate(&a);
-  if (err == hipSuccess) err = hipEventCreate(&b);
-  if (err == hipSuccess) err = hipEventRecord(a, stream);
+  // one event pair per launch, recorded by the dispatch itself at its start
+  // and end: the mean is the kernel's own duration, whatever the host's
+  // enqueue rate
+  std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+  hipError_t err = hipSuccess;
+  for (size_t k = 0; k < ev.size() && err == hipSuccess; ++k) err = hipEventCreate(&ev[k]);
   for (int r = 0; r < reps && err == hipSuccess; ++r)
     err = PSDF_BY_MF(launch_main_mf, obst_class(e.mbar), ls, F, poses, N, e, partial, stream,
-                     nullptr, nullptr);
-  if (err == hipSuccess) err = hipEventRecord(b, stream);
-  if (err == hipSuccess) err = hipEventSynchronize(b);
-  float t = 0.f;
-  if (err == hipSuccess) err = hipEventElapsedTime(&t, a, b);
-  if (a) (void)hipEventDestroy(a);
-  if (b) (void)hipEventDestroy(b);
-  if (err == hipSuccess) *ms = t / (float)reps;
+                     ev[2 * r], ev[2 * r + 1]);
+  if (err == hipSuccess) err = hipEventSynchronize(ev.back());
+  double total = 0.0;
+  for (int r = 0; r < reps && err == hipSuccess; ++r) {
+    float t = 0.f;
+    err = hipEventElapsedTime(&t, ev[2 * r], ev[2 * r + 1]);
+    total += t;
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (err == hipSuccess) *ms = (float)(total / reps);
   return hip_status(err);
 }
 

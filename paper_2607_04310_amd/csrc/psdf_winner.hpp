@@ -177,8 +177,8 @@ __device__ __forceinline__ void fill_stage_table(const FpConst& F, const float* 
 // rotated footprints rft[t * MF + l] (rotated_slot).  For each stage
 // emit(t, key, aux) receives the wave's minimum key (orderable(sd) << 32 |
 // obase + lane of the first minimum, or the empty key) and that lane's
-// (e0 << 32 | mi).
-template <int MF, int MIX, class Emit>
+// (e0 << 32 | mi).  LAZY: see own_intervals.
+template <int MF, int MIX, class Emit, bool LAZY = false>
 __device__ __forceinline__ void wave_stage_loop(const FpConst& F, Obst<MIX>& o, int e0, int mi,
                                                 bool active, int obase, int ns,
                                                 const float4* st, const float4* rft, Emit emit) {
@@ -190,7 +190,7 @@ __device__ __forceinline__ void wave_stage_loop(const FpConst& F, Obst<MIX>& o, 
     const bool pose_ok = isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && isfinite(q.w);
     uint32_t k = 0xffffffffu;
     if (contributes)
-      k = pose_ok ? orderable(obstacle_sd<MF, MIX>(F, o, rft + t * MF, q.z, q.w)) : 0u;
+      k = pose_ok ? orderable(obstacle_sd<MF, MIX, LAZY>(F, o, rft + t * MF, q.z, q.w)) : 0u;
     const uint32_t kmin = wave_min_u32(k);
     uint64_t key = kEmptyKey, a = 0;
     if (kmin != 0xffffffffu) {
@@ -207,7 +207,7 @@ __device__ __forceinline__ void wave_stage_loop(const FpConst& F, Obst<MIX>& o, 
 // whose obstacles all have at most one edge (free segments) takes the
 // one-edge specialisation (wave_stages), the same arithmetic on one slot
 // instead of MI.
-template <int MF, int MIX, class Emit>
+template <int MF, int MIX, class Emit, bool LAZY = false>
 __device__ __forceinline__ void wave_stages_t(const FpConst& F, const float* __restrict__ ax,
                                               const float* __restrict__ ay,
                                               const float* __restrict__ bx,
@@ -217,10 +217,10 @@ __device__ __forceinline__ void wave_stages_t(const FpConst& F, const float* __r
   Obst<MIX> o;
   load_obstacle<MIX>(o, ax, ay, bx, by, e0, mi, Eend, F.eps);
   o.bad = o.bad || bad;
-  wave_stage_loop<MF, MIX>(F, o, e0, mi, active, obase, ns, st, rft, emit);
+  wave_stage_loop<MF, MIX, Emit, LAZY>(F, o, e0, mi, active, obase, ns, st, rft, emit);
 }
 
-template <int MF, int MI, class Emit>
+template <int MF, int MI, class Emit, bool LAZY = false>
 __device__ __forceinline__ void wave_stages(const FpConst& F, const float* __restrict__ ax,
                                             const float* __restrict__ ay,
                                             const float* __restrict__ bx,
@@ -229,9 +229,11 @@ __device__ __forceinline__ void wave_stages(const FpConst& F, const float* __res
                                             const float4* st, const float4* rft, Emit emit) {
   const bool segments = __ballot(active && mi > 1) == 0;
   if (MI > 1 && segments)
-    wave_stages_t<MF, 1>(F, ax, ay, bx, by, e0, mi, Eend, active, bad, obase, ns, st, rft, emit);
+    wave_stages_t<MF, 1, Emit, LAZY>(F, ax, ay, bx, by, e0, mi, Eend, active, bad, obase, ns, st,
+                                     rft, emit);
   else
-    wave_stages_t<MF, MI>(F, ax, ay, bx, by, e0, mi, Eend, active, bad, obase, ns, st, rft, emit);
+    wave_stages_t<MF, MI, Emit, LAZY>(F, ax, ay, bx, by, e0, mi, Eend, active, bad, obase, ns, st,
+                                      rft, emit);
 }
 
 // Whole-wave call with uniform arguments; the obstacle owns edges

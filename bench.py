@@ -191,39 +191,48 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(c5, seconds):
-    """The FP64 oracle (value, winner, gradient) timed on this host: all cores
-    on whole c5 instances, repeated until half the budget is spent, then one
-    core on the first 4 stages of instance 0, for the other half."""
+def _oracle_rate(oracle, insts, nthreads, budget, stages=None):
+    """stage x edge pairs per second of the FP64 oracle over `insts` (cycled
+    until `budget` seconds are spent), all stages or the first `stages`."""
+    t0 = time.perf_counter()
+    pairs, k, used = 0, 0, 0
+    while True:
+        i = insts[k % len(insts)]
+        n = i.N if stages is None else min(stages, i.N)
+        r = oracle.psdf(i.footprint, i.poses[:n], i.edges, i.obst_off, nthreads=nthreads)
+        used = r["threads"]
+        pairs += n * i.E
+        k += 1
+        done = time.perf_counter() - t0
+        if done >= budget:
+            return pairs / done, k, done, int(used)
+
+
+def cpu_baseline(c5, seconds, inputs):
+    """The FP64 oracle (value, winner, gradient) timed on this host, on all
+    cores and on one core: the headline on c5 (a third of the budget each),
+    and c1, c2 and a c4 sample (the last third)."""
     import oracle
     oracle.use_native_build()
     inst = c5[0]
     oracle.psdf(inst.footprint, inst.poses[:1], inst.edges, inst.obst_off)   # load / warm
-    t0 = time.perf_counter()
-    pairs, k, used = 0, 0, 0
-    while True:
-        i = c5[k % len(c5)]
-        r = oracle.psdf(i.footprint, i.poses, i.edges, i.obst_off)
-        used = r["threads"]
-        pairs += i.N * i.E
-        k += 1
-        done = time.perf_counter() - t0
-        if done >= seconds / 2:
-            break
-    t1 = time.perf_counter()
-    p1, k1 = 0, 0
-    while True:
-        r = oracle.psdf(inst.footprint, inst.poses[:4], inst.edges, inst.obst_off, nthreads=1)
-        p1 += 4 * inst.E
-        k1 += 1
-        done1 = time.perf_counter() - t1
-        if done1 >= seconds / 2:
-            break
-    return dict(value=pairs / done, unit="stage×edge evals/s", cores=int(used), kind="oracle",
+    v, k, done, used = _oracle_rate(oracle, c5, 0, seconds / 3)
+    v1, k1, done1, _ = _oracle_rate(oracle, c5[:1], 1, seconds / 3, stages=4)
+    others = {}
+    small = dict(c1=[inputs.c1(s) for s in range(4)], c2=[inputs.c2(s) for s in range(2)],
+                 c4=[inputs.c4_instance(k) for k in range(16)])
+    share = seconds / 3 / (2 * len(small))
+    for name, insts in small.items():
+        a, ka, _, ua = _oracle_rate(oracle, insts, 0, share)
+        b, kb, _, _ = _oracle_rate(oracle, insts, 1, share)
+        others[name] = dict(value=a, one_core_value=b, threads=ua,
+                            sample=f"{len(insts)} instances cycled, {ka} / {kb} calls")
+    return dict(value=v, unit="stage×edge evals/s", cores=used, kind="oracle",
                 sample=f"{k} whole c5 instances (N={inst.N}, E={inst.E}, value+winner+gradient, "
                        f"FP64) in {done:.1f} s on {used} threads",
-                one_core_value=p1 / done1,
+                one_core_value=v1,
                 one_core_sample=f"{k1} x the first 4 stages of c5 instance 0 in {done1:.1f} s",
+                other_configs=others,
                 cpu_model=cpu_model(), nproc=os.cpu_count(),
                 build="g++ -O3 -march=native -ffp-contract=off -fopenmp")
 
@@ -513,7 +522,7 @@ def main():
     if args.extras:
         res["extras"] = extras(torch, api, flops, inputs)
     if not args.no_cpu and args.cpu_seconds > 0:
-        res["cpu_baseline"] = cpu_baseline(c5, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(c5, args.cpu_seconds, inputs)
     print(json.dumps(res), flush=True)
 
 

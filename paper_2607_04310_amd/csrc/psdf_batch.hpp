@@ -59,10 +59,20 @@ struct BatchArgs {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Waves per SIMD the compiler must fit: four for four-edge obstacles with a
+// footprint of at most six slots, whose register need (154 VGPRs at six
+// slots, three waves) then drops to 128 at the cost of a few spills to
+// scratch outside the arithmetic (an A/B on c5 at six slots: 0.5589 against
+// 0.5700 ms per call); larger footprints and edge classes would spill far
+// more and keep the compiler's own choice.
+template <int MF, int MI>
+constexpr int kBatchWavesPerEU = (MI == 4 && MF <= 6) ? 4 : 1;
+
 // One launch per footprint-size group: MF footprint slots, MI obstacle edge
 // class, NW waves per work-group (64 NW obstacles per tile).
 template <int MF, int MI, int NW>
-__global__ __launch_bounds__(64 * NW) void batch_kernel(BatchArgs A) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(kBatchWavesPerEU<MF, MI>)))
+void batch_kernel(BatchArgs A) {
   __shared__ int s_item;
   __shared__ float4 st[kMaxStageBlock];
   __shared__ float4 rft[kMaxStageBlock * MF];

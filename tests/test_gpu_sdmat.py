@@ -48,6 +48,10 @@ def compare(inst, sd, eta):
     same_special = (np.isnan(sd) == np.isnan(ref)) & (np.isinf(sd) == np.isinf(ref))
     assert same_special.all()
     fin = np.isfinite(ref)
+    err = np.abs(sd - np.where(fin, ref, 0))[fin]
+    if err.size:
+        print(f"[sdmat] max |dsd| {err.max():.3g} m, entries above 1e-5 m: {(err > 1e-5).sum()} "
+              f"of {err.size}, largest |sd| {np.abs(ref[fin]).max():.1f} m", flush=True)
     tol = D_TOL + D_REL * np.abs(np.where(fin, ref, 0))
     bad = np.argwhere(fin & (np.abs(sd - np.where(fin, ref, 0)) > tol))
     branch_ties = 0
@@ -76,6 +80,14 @@ def test_mixed_penetrating(api, seed):
     sd, d, o = gpu_sdm(api, inst)
     compare(inst, sd, 1000.0)
     assert (sd < 0).any()
+
+
+def test_c2_full_matrix(api):
+    """Every entry of c2 (4096 obstacles, 50 stages, 40 x 40 m: distances up
+    to about 55 m)."""
+    inst = inputs.c2(0)
+    sd, d, o = gpu_sdm(api, inst)
+    assert compare(inst, sd, 1000.0) == inst.N * inst.M
 
 
 @pytest.mark.parametrize("M,N", [(1, 1), (255, 5), (257, 130), (3000, 7)])

@@ -50,8 +50,10 @@ def compare(inst, sd, eta):
     fin = np.isfinite(ref)
     err = np.abs(sd - np.where(fin, ref, 0))[fin]
     if err.size:
-        print(f"[sdmat] max |dsd| {err.max():.3g} m, entries above 1e-5 m: {(err > 1e-5).sum()} "
-              f"of {err.size}, largest |sd| {np.abs(ref[fin]).max():.1f} m", flush=True)
+        above = np.abs(ref[fin])[err > 1e-5]
+        print(f"[sdmat] max |dsd| {err.max():.3g} m, entries above 1e-5 m: {above.size} "
+              f"of {err.size}" + (f" (|sd| {above.min():.1f}-{above.max():.1f} m)" if above.size else "")
+              + f", largest |sd| {np.abs(ref[fin]).max():.1f} m", flush=True)
     tol = D_TOL + D_REL * np.abs(np.where(fin, ref, 0))
     bad = np.argwhere(fin & (np.abs(sd - np.where(fin, ref, 0)) > tol))
     branch_ties = 0

@@ -1,22 +1,21 @@
 """Algorithmic work model of the PSDF pipeline, used for roofline figures.
 
-Counts the floating-point operations the method needs per (stage, obstacle)
-in the separated branch of the paper's pipeline (Sec. IV-A..IV-D), an FMA
-counting as 2 FLOP and min / max / clamp / compare / select as 0; square roots
-and reciprocals are counted apart as transcendental ops.  The soft-min
-(only reached by non-separated pairs) is not counted, so the figure is a
-lower bound of the work per pair.
-
-For a footprint of m vertices and an obstacle of mi edges and ni vertices in
-V_obs (ni = mi for a closed polygon, 2 * mi for open chains, 2 for a free
-segment):
-    transform of ni vertices                  8 ni
-    edge vectors and |v|^2 + eps              6 mi
-    point-segment pairs, 13 FLOP each         13 (m mi + ni m)
-    obstacle axes n' = rot90(v)/(|v| + eps)   3 mi
-    projections, 3 FLOP each                  3 (m mi + ni m + ni mi)
-    overlaps (two differences per axis)       2 (m + mi)
-Rectangle (mi = ni = 4): m = 4 -> 644 FLOP (161 per edge); m = 6 -> 904 (226).
+Counts the floating-point operations of the paper's pipeline (Sec. IV-A..IV-D)
+per (stage, obstacle), an FMA counting as 2 FLOP and min / max / clamp /
+compare / select as 0; square roots, reciprocals, exponentials and the
+logarithm are counted apart as transcendental ops.  For a footprint of m
+vertices and an obstacle of mi edges and ni points in V_obs (ni = mi for a
+closed polygon, 2 mi for an open chain, 2 for a free segment):
+    transform of the ni obstacle points                         8 ni
+    edge vectors and |v|^2 + eps                                6 mi
+    point-segment pairs, 13 FLOP each                           13 (m mi + m ni)
+    projections of the obstacle points on the robot axes        3 m ni
+    robot-side constants                                        2 m
+    obstacle axes and the projections on them                   mi (5 + 3 m + 3 ni)
+    overlaps and the separated test                             3 (m + mi)
+    the final selection                                         1
+A closed polygon gives 32 m mi + 3 mi^2 + 22 mi + 5 m + 1 (a rectangle:
+935 FLOP at m = 6, 669 at m = 4), a free segment 37 + 53 m.
 
 Memory: the edges are read once per work-group as 16 B per edge (ax, ay, bx,
 by float32) plus 4 B per obstacle offset; poses 12 B per stage; outputs and
@@ -28,8 +27,8 @@ import numpy as np
 
 
 def flops_pair(m: int, mi: int, ni: int) -> int:
-    return (8 * ni + 6 * mi + 13 * (m * mi + ni * m) + 3 * mi
-            + 3 * (m * mi + ni * m + ni * mi) + 2 * (m + mi))
+    return (8 * ni + 6 * mi + 13 * (m * mi + m * ni) + 3 * m * ni + 2 * m
+            + mi * (5 + 3 * m + 3 * ni) + 3 * (m + mi) + 1)
 
 
 def obstacle_shapes(edges, obst_off):

@@ -1,12 +1,8 @@
-// Explicit instantiation of the persistent batch and screening kernels for 4 footprint slots.
+// Explicit instantiation of the persistent batch kernel for 4 footprint slots.
 #include "psdf_batch.hpp"
-#include "psdf_screen.hpp"
 
 namespace psdf {
 template hipError_t launch_batch_mf<4>(int, int, int, const BatchArgs&, hipStream_t, hipEvent_t,
                                           hipEvent_t);
 template hipError_t batch_occupancy_mf<4>(int, int, int*);
-template hipError_t launch_screen_mf<4>(int, int, const ScreenArgs&, hipStream_t);
-template hipError_t launch_screen_bound_mf<4>(int, int, const ScreenArgs&, hipStream_t);
-template hipError_t launch_fallback_mf<4>(int, int, int, const ScreenArgs&, hipStream_t);
 }  // namespace psdf

@@ -1,0 +1,8 @@
+// Explicit instantiation of the screening kernels for 7 footprint slots.
+#include "psdf_screen.hpp"
+
+namespace psdf {
+template hipError_t launch_screen_mf<7>(int, int, const ScreenArgs&, hipStream_t);
+template hipError_t launch_screen_bound_mf<7>(int, int, const ScreenArgs&, hipStream_t);
+template hipError_t launch_fallback_mf<7>(int, int, int, const ScreenArgs&, hipStream_t);
+}  // namespace psdf

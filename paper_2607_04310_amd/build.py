@@ -25,14 +25,6 @@ SOURCES = (["psdf_host.cpp", "psdf_plain.hip", "psdf_batch.hip", "psdf_mlp.hip",
            + [f"psdf_batch_mf{m}.hip" for m in (3, 4, 5, 6, 7, 8, 16)]
            + [f"psdf_screen_mf{m}.hip" for m in (3, 4, 5, 6, 7, 8, 16)])
 
-# Per-unit scheduler choice: the six-slot (hexagon) batch kernels are
-# scheduled for instruction-level parallelism, which leaves 15 instead of 25
-# spilled VGPRs at four waves per SIMD for four-edge obstacles and made c5
-# calls 1.6 % faster in an A/B on one box (0.5561 against 0.5650 ms); for
-# the other footprint sizes it spills more or lowers occupancy, and the
-# screening kernels (their own units) would lose occupancy.
-EXTRA_FLAGS = {"psdf_batch_mf6.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
-
 ARCH = os.environ.get("PSDF_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"-I{INCLUDE}", f"-I{CSRC}"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -46,7 +38,7 @@ def _hipcc():
 def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc()] + COMMON + DEVICE + EXTRA_FLAGS.get(src, [])
+    cmd = [_hipcc()] + COMMON + DEVICE
     if src.endswith(".hip"):
         cmd += ["-x", "hip"]
     cmd += ["-c", path, "-o", obj]

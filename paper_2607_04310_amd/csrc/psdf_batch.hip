@@ -54,7 +54,7 @@ struct psdf_batch_plan {
   // screening: stage -> instance, stage rows grouped by footprint size,
   // failed lists and counters (three per group)
   int* d_stage_inst = nullptr;
-  int* d_stage_list = nullptr;
+  int4* d_stage_list = nullptr;   // (stage row, instance, circ_off, M) per screened stage
   int* d_failed = nullptr;
   unsigned* d_sctrl = nullptr;
   float4* d_hlist = nullptr;  // horizon lists (circle, index), sum M
@@ -723,18 +723,23 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
   // screening tables
   if (err == hipSuccess) {
     const int S = std::max(1, p->total_stages);
-    std::vector<int> stage_inst(S, 0), list;
+    std::vector<int> stage_inst(S, 0), circ_off(std::max(1, n_inst), 0);
+    std::vector<int4> list;
     list.reserve(S);
+    int circ = 0;
     for (int k = 0; k < n_inst; ++k) {
       for (int t = 0; t < desc[k].N; ++t) stage_inst[desc[k].pose_off + t] = k;
       p->max_M = std::max(p->max_M, desc[k].M);
+      circ_off[k] = circ;   // as build_items: the instances' M in order
+      circ += desc[k].M;
     }
     for (int g = 0; g < kGroups; ++g) {
       const int start = (int)list.size();
       int max_tiles = 1;
       for (int k = 0; k < n_inst; ++k)
         if (group_of(p->fp[k].m) == g) {
-          for (int t = 0; t < desc[k].N; ++t) list.push_back(desc[k].pose_off + t);
+          for (int t = 0; t < desc[k].N; ++t)
+            list.push_back(make_int4(desc[k].pose_off + t, k, circ_off[k], desc[k].M));
           max_tiles = std::max(max_tiles, (desc[k].M + 255) / 256);
         }
       if ((int)list.size() > start)
@@ -756,14 +761,14 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
     if (err == hipSuccess)
       err = hipMemset(p->d_hrest, 0xff, std::max<size_t>(1, (size_t)n_inst) * sizeof(uint32_t));
     if (err == hipSuccess) err = hipMalloc(&p->d_stage_inst, S * sizeof(int));
-    if (err == hipSuccess) err = hipMalloc(&p->d_stage_list, S * sizeof(int));
+    if (err == hipSuccess) err = hipMalloc(&p->d_stage_list, S * sizeof(int4));
     if (err == hipSuccess) err = hipMalloc(&p->d_failed, S * sizeof(int));
     if (err == hipSuccess) err = hipMalloc(&p->d_sctrl, 2 * kGroups * sizeof(unsigned));
     if (err == hipSuccess) err = hipMemset(p->d_sctrl, 0, 2 * kGroups * sizeof(unsigned));
     if (err == hipSuccess)
       err = hipMemcpy(p->d_stage_inst, stage_inst.data(), S * sizeof(int), hipMemcpyHostToDevice);
     if (err == hipSuccess && !list.empty())
-      err = hipMemcpy(p->d_stage_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice);
+      err = hipMemcpy(p->d_stage_list, list.data(), list.size() * sizeof(int4), hipMemcpyHostToDevice);
   }
   if (err != hipSuccess) {
     int rc = hip_status(err);

@@ -134,7 +134,9 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     const float4* __restrict__ circ, float4* __restrict__ hlist, int* __restrict__ hcount,
     uint32_t* __restrict__ hrest, const float* __restrict__ theta, uint4* __restrict__ frag) {
   __shared__ int scan[kScreenThreads];
-  __shared__ uint32_t red[kScreenThreads / 64];
+  // one slot per combined reduction below (none is reused, so none needs a
+  // barrier after its reads): 5 + 2 + 3 + 2 groups of kWaves words
+  __shared__ uint32_t rs[12 * kWaves];
   __shared__ int s_base;
   if (blockIdx.x == kHorizonSplit) {
     // the extra column: the screener network's per-lane weight fragments,
@@ -181,9 +183,13 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     bx0 = min(bx0, orderable(x)); by0 = min(by0, orderable(y));
     bx1 = min(bx1, orderable(-x)); by1 = min(by1, orderable(-y));
   }
-  bad = block_sum_i32(bad, scan);
-  bx0 = block_min_u32(bx0, red); by0 = block_min_u32(by0, red);
-  bx1 = block_min_u32(bx1, red); by1 = block_min_u32(by1, red);
+  {
+    uint32_t mn[4] = {bx0, by0, bx1, by1};
+    int sm[1] = {bad};
+    block_reduce<4, 1>(mn, sm, rs);
+    bx0 = mn[0]; by0 = mn[1]; bx1 = mn[2]; by1 = mn[3];
+    bad = sm[0];
+  }
   if (bad > 0 || in.N == 0) {
     if (tid == 0 && part == 0) hcount[inst] = -1;
     return;
@@ -198,7 +204,12 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     const float dx = p[0] - cx, dy = p[1] - cy;
     nr = min(nr, orderable(-sqrtf(fmaf(dx, dx, dy * dy))));
   }
-  nr = block_min_u32(nr, red);
+  {
+    uint32_t mn[1] = {nr};
+    int sm[1] = {0};
+    block_reduce<1, 1>(mn, sm, rs + 5 * kWaves);
+    nr = mn[0];
+  }
   const float R = -from_orderable(nr) * (1.0f + 1e-6f) + 1e-6f;
   const float hoff = R + F.rmax + kLbGamma;
   uint32_t k[kHorizonKeys];
@@ -219,9 +230,13 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     k[q] = key;
     if (key != 0xffffffffu) { kmin = min(kmin, key); kmax = max(kmax, key); ++used; }
   }
-  kmin = block_min_u32(kmin, red);
-  kmax = ~block_min_u32(~kmax, red);
-  const int n_used = block_sum_i32(used, scan);
+  int n_used;
+  {
+    uint32_t mn[2] = {kmin, ~kmax};
+    int sm[1] = {used};
+    block_reduce<2, 1>(mn, sm, rs + 7 * kWaves);
+    kmin = mn[0]; kmax = ~mn[1]; n_used = sm[0];
+  }
   constexpr int P = kHorizonPool / kHorizonSplit;
   const uint32_t T = n_used > P ? block_threshold<kHorizonKeys>(k, kHorizonKeys, kmin, kmax,
                                                                 P / 2, P, scan)
@@ -234,9 +249,8 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     if (k[q] <= T) ++mine;
     else rest = min(rest, k[q]);
   }
-  rest = block_min_u32(rest, red);
   int total = 0;
-  int at = block_scan(mine, scan, &total);
+  int at = block_scan_min(mine, rest, rs + 10 * kWaves, &total, &rest);
   if (tid == 0) {
     s_base = total > 0 ? atomicAdd(&hcount[inst], total) : 0;
     if (rest != 0xffffffffu) atomicMin(&hrest[inst], rest);

@@ -50,7 +50,9 @@ struct ScreenArgs {
   const FpConst* fps;
   const BatchInst* insts;
   const int* stage_inst;   // global stage row -> instance
-  const int* stages;       // this launch's stage rows
+  const int4* stages;      // this launch's stages: (stage row, instance, the instance's
+                           // circ_off, its obstacle count M), so that a stage's first
+                           // loads wait on one record only
   int n_stages;
   const float* poses;
   const float* ax;
@@ -199,6 +201,66 @@ __device__ __forceinline__ uint32_t block_min_u32(uint32_t v, uint32_t* red) {
   return r;
 }
 
+// Several reductions behind one barrier: the minima of NM unsigned values
+// and the sums of NS ints over the work-group.  slot holds (NM + NS) x
+// kWaves words; there is no barrier after the reads, so a slot serves one
+// call site of a kernel (or is reused only past another barrier).
+template <int NM, int NS>
+__device__ __forceinline__ void block_reduce(uint32_t (&mn)[NM], int (&sm)[NS], uint32_t* slot) {
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NM; ++i) mn[i] = fw_min_u32(mn[i]);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) sm[i] = fw_sum_i32(sm[i]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < NM; ++i) slot[i * kWaves + w] = mn[i];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) slot[(NM + i) * kWaves + w] = (uint32_t)sm[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NM; ++i) {
+    uint32_t r = slot[i * kWaves];
+#pragma unroll
+    for (int v = 1; v < kWaves; ++v) r = min(r, slot[i * kWaves + v]);
+    mn[i] = r;
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    int t = 0;
+#pragma unroll
+    for (int v = 0; v < kWaves; ++v) t += (int)slot[(NM + i) * kWaves + v];
+    sm[i] = t;
+  }
+}
+
+// Exclusive block scan of one int per thread together with the work-group
+// minimum of one unsigned value, behind one barrier (slot: 2 kWaves words,
+// no barrier after the reads, as block_reduce).  Returns the prefix; *total
+// is the sum and *mn the minimum.
+__device__ __forceinline__ int block_scan_min(int v, uint32_t m, uint32_t* slot, int* total,
+                                              uint32_t* mn) {
+  const int w = threadIdx.x >> 6;
+  int wt = 0;
+  const int x = fw_scan_i32(v, &wt);
+  m = fw_min_u32(m);
+  if ((threadIdx.x & 63) == 0) { slot[w] = (uint32_t)wt; slot[kWaves + w] = m; }
+  __syncthreads();
+  int base = 0, tot = 0;
+  uint32_t r = 0xffffffffu;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    const int t = (int)slot[i];
+    base += i < w ? t : 0;
+    tot += t;
+    r = min(r, slot[kWaves + i]);
+  }
+  *total = tot;
+  *mn = r;
+  return base + x - v;
+}
+
 // Exclusive block scan of one int per thread; returns the prefix, *total
 // the sum.
 __device__ __forceinline__ int block_scan(int v, int* scratch, int* total) {
@@ -236,10 +298,23 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
   __shared__ int cand_o[kPoolCap];
   __shared__ uint64_t wkey[kScreenThreads / 64];
   __shared__ float4 rf[MF];
+  __shared__ uint32_t rs[10 * kWaves];    // one slot per combined reduction
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int s = A.stages[blockIdx.x];
-  const int inst = __builtin_amdgcn_readfirstlane(A.stage_inst[s]);
+  const int4 si = A.stages[blockIdx.x];
+  const int s = si.x;
+  const int inst = __builtin_amdgcn_readfirstlane(si.y);
+  // the first kPreKeys list entries of this thread, issued before the
+  // instance record and the list's length are in (slots past the length
+  // but within the instance's M are read and ignored)
+  constexpr int kPreKeys = 2;
+  const float4* hl = A.hlist + si.z;
+  float4 pre[kPreKeys];
+#pragma unroll
+  for (int q = 0; q < kPreKeys; ++q) {
+    const int idx = tid + kScreenThreads * q;
+    pre[q] = idx < si.w ? hl[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   const BatchInst in = A.insts[inst];
   const FpConst& F = A.fps[inst];
   const float* p = A.poses + 3 * s;
@@ -271,7 +346,6 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
   uint32_t k[kStageKeys];
   int hidx[kStageKeys];
   const int n_h = hc;
-  const float4* hl = A.hlist + in.circ_off;
   const float lb_off = F.rmax + kLbGamma;
   const int nq = (n_h + kScreenThreads - 1) / kScreenThreads;   // live key slots
 #pragma unroll
@@ -280,7 +354,7 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
     uint32_t key = 0xffffffffu;
     hidx[q] = 0;
     if (q < nq && idx < n_h) {   // the list holds no empty obstacle
-      const float4 c = hl[idx];
+      const float4 c = q < kPreKeys ? pre[q] : hl[idx];
       hidx[q] = __float_as_int(c.w);
       const float dx = px - c.x, dy = py - c.y;
       const float lbv = sqrtf(fmaf(dx, dx, dy * dy)) - c.z - lb_off;
@@ -298,20 +372,29 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
     if (q >= nq) break;
     if (k[q] != 0xffffffffu) { kmin = min(kmin, k[q]); kmax = max(kmax, k[q]); ++used; }
   }
-  kmin = block_min_u32(kmin, red);
-  kmax = ~block_min_u32(~kmax, red);
-  const int n_used = block_sum_i32(used, scan);
+  int n_used;
+  {
+    uint32_t mn[2] = {kmin, ~kmax};
+    int sm[1] = {used};
+    block_reduce<2, 1>(mn, sm, rs);
+    kmin = mn[0]; kmax = ~mn[1]; n_used = sm[0];
+  }
   const uint32_t T = n_used > P ? block_threshold<kStageKeys>(k, nq, kmin, kmax,
                                                                          (3 * P) / 4, P, scan)
                                 : 0xfffffffeu;
+  // pool members of this thread, and the smallest bound outside the pool:
+  // the horizon list's circle bounds, and the instance's bound for every
+  // obstacle left out of the list
   int mine = 0;
+  uint32_t rest = A.hrest[inst];
 #pragma unroll
   for (int q = 0; q < kStageKeys; ++q) {
     if (q >= nq) break;
     mine += k[q] <= T && k[q] != 0xffffffffu;
+    if (k[q] > T) rest = min(rest, k[q]);
   }
   int pool_n = 0;
-  int at = block_scan(mine, scan, &pool_n);
+  int at = block_scan_min(mine, rest, rs + 3 * kWaves, &pool_n, &rest);
   const bool overflow = pool_n > kPoolCap;
   if (!overflow) {
 #pragma unroll
@@ -322,15 +405,6 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
         ++at;
       }
   }
-  // smallest bound outside the pool: the horizon list's circle bounds, and
-  // the instance's bound for every obstacle left out of the list
-  uint32_t rest = A.hrest[inst];
-#pragma unroll
-  for (int q = 0; q < kStageKeys; ++q) {
-    if (q >= nq) break;
-    if (k[q] > T) rest = min(rest, k[q]);
-  }
-  rest = block_min_u32(rest, red);
   __syncthreads();
 
   uint64_t keyK = kEmptyKey;
@@ -407,9 +481,13 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
 #pragma unroll
     for (int q = 0; q < SPT; ++q)
       if (sk[q] != 0xffffffffu) { smin = min(smin, sk[q]); smax = max(smax, sk[q]); }
-    smin = block_min_u32(smin, red);
-    smax = ~block_min_u32(~smax, red);
-    const int n_live = block_sum_i32(live, scan);
+    int n_live;
+    {
+      uint32_t mn[2] = {smin, ~smax};
+      int sm[1] = {live};
+      block_reduce<2, 1>(mn, sm, rs + 5 * kWaves);
+      smin = mn[0]; smax = ~mn[1]; n_live = sm[0];
+    }
     const int K = max(1, A.topk);
     const uint32_t S = n_live > K ? block_threshold<SPT>(sk, SPT, smin, smax, (7 * K) / 8, K, scan)
                                   : 0xfffffffeu;
@@ -421,20 +499,20 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
     __syncthreads();
     // compact candidates in pool (index) order; a pool member whose LB is -inf
     // (pose inside, invalid or non-finite) is always a candidate
+    // (each thread reads back only the pool range it wrote itself; excl is
+    // the smallest LB among pool members that are not candidates)
     int cnt = 0;
+    uint32_t excl = rest;
     const int per = (pool_n + kScreenThreads - 1) / kScreenThreads;
     for (int q = tid * per; q < min(pool_n, (tid + 1) * per); ++q) {
       if (pool_lb[q] <= orderable(-__builtin_huge_valf())) cand[q] = 1;
       cnt += cand[q];
+      if (!cand[q]) excl = min(excl, pool_lb[q]);
     }
-    int c_at = block_scan(cnt, scan, &n_cand);
+    int c_at = block_scan_min(cnt, excl, rs + 8 * kWaves, &n_cand, &excl);
     for (int q = tid * per; q < min(pool_n, (tid + 1) * per); ++q)
       if (cand[q]) cand_o[c_at++] = pool_o[q];
-    // smallest LB among pool members that are not candidates
-    uint32_t excl = rest;
-    for (int q = tid; q < pool_n; q += kScreenThreads)
-      if (!cand[q]) excl = min(excl, pool_lb[q]);
-    excl = block_min_u32(excl, red);
+    __syncthreads();   // cand_o is written
 
     // ---- exact evaluation of the candidates (lane <-> candidate)
     uint64_t best = kEmptyKey;
@@ -512,11 +590,14 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
 // certificate built on these bounds can use when the seed is the winner or
 // the stage penetrates (T = tau_sep then).
 //
-// One wave per stage: the list is read twice (the bounds are recomputed in
-// the second pass instead of held in registers), the seed comes from a
-// wave minimum of (bound key, list slot), the candidates are compacted into
-// LDS with ballots, and no work-group barrier is needed.
+// One wave per stage: the first kBoundRegs x 64 list entries are loaded
+// together (all in flight at once) and their bounds held in registers for
+// both passes; entries past them (tie blocks only) are read again in the
+// second pass.  The seed comes from a wave minimum of (bound key, list
+// slot), the candidates are compacted into LDS with ballots, and no
+// work-group barrier is needed.
 constexpr int kBoundCap = 512;   // candidates per stage (more: full evaluation)
+constexpr int kBoundRegs = 8;    // list entries per lane held in registers
 
 template <int MF, int MI>
 __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
@@ -524,8 +605,19 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
   __shared__ float4 rf[MF];
 
   const int lane = threadIdx.x;
-  const int s = A.stages[blockIdx.x];
-  const int inst = __builtin_amdgcn_readfirstlane(A.stage_inst[s]);
+  const int4 si = A.stages[blockIdx.x];
+  const int s = si.x;
+  const int inst = __builtin_amdgcn_readfirstlane(si.y);
+  // the first kBoundRegs x 64 list entries, issued before the instance
+  // record and the list's length are in (slots past the length but within
+  // the instance's M are read and ignored)
+  const float4* hl = A.hlist + si.z;
+  float4 rc[kBoundRegs];
+#pragma unroll
+  for (int q = 0; q < kBoundRegs; ++q) {
+    const int idx = q * 64 + lane;
+    rc[q] = idx < si.w ? hl[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   const BatchInst in = A.insts[inst];
   const FpConst& F = A.fps[inst];
   const float* p = A.poses + 3 * s;
@@ -546,7 +638,6 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
     }
     return;
   }
-  const float4* hl = A.hlist + in.circ_off;
   const float lb_off = F.rmax + kLbGamma;
   // bounding-circle lower bound of list entry idx (as screen_kernel), and
   // its obstacle (local index)
@@ -560,9 +651,26 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
 
   // ---- pass 1: the seed, the smallest bound (lowest list slot on ties);
   // the key's low word is (slot << 16 | obstacle): slot < 2048, obstacle <
-  // 16384, so the wave minimum names the seed without another list read
+  // 16384, so the wave minimum names the seed without another list read.
+  // Entry q * 64 + lane of the first kBoundRegs x 64: key rk[q], obstacle
+  // ro[q] (key 0xffffffff past the list's end, never taken below).
+  uint32_t rk[kBoundRegs];
+  int ro[kBoundRegs];
   uint64_t lo = ~0ull;
-  for (int idx = lane; idx < hc; idx += 64) {
+#pragma unroll
+  for (int q = 0; q < kBoundRegs; ++q) {
+    const int idx = q * 64 + lane;
+    const float4 c = rc[q];
+    ro[q] = __float_as_int(c.w);
+    const float dx = px - c.x, dy = py - c.y;
+    const float lbv = sqrtf(fmaf(dx, dx, dy * dy)) - c.z - lb_off;
+    rk[q] = idx < hc ? orderable(pose_ok ? lbv : -__builtin_huge_valf()) : 0xffffffffu;
+    if (idx < hc) {
+      const uint64_t v = ((uint64_t)rk[q] << 32) | ((uint32_t)idx << 16) | (uint32_t)ro[q];
+      lo = v < lo ? v : lo;
+    }
+  }
+  for (int idx = kBoundRegs * 64 + lane; idx < hc; idx += 64) {
     int o;
     const uint64_t v = ((uint64_t)lb_key(idx, o) << 32) | ((uint32_t)idx << 16) | (uint32_t)o;
     lo = v < lo ? v : lo;
@@ -590,7 +698,16 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
   const uint32_t tkey = orderable(fmaxf(phi1, F.tau_sep));
   const uint64_t below = (1ull << lane) - 1ull;
   int n_cand = 0;
-  for (int i0 = 0; i0 < hc; i0 += 64) {
+#pragma unroll
+  for (int q = 0; q < kBoundRegs; ++q) {
+    const int o = ro[q];
+    const bool take = q * 64 + lane < hc && rk[q] <= tkey && o != seed_o;
+    const uint64_t m = __ballot(take);
+    const int at = n_cand + (int)__popcll(m & below);
+    if (take && at < kBoundCap) cand_o[at] = o;
+    n_cand += (int)__popcll(m);
+  }
+  for (int i0 = kBoundRegs * 64; i0 < hc; i0 += 64) {
     const int idx = i0 + lane;
     int o = -1;
     bool take = false;

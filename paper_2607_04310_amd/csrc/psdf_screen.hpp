@@ -130,16 +130,6 @@ __device__ __forceinline__ float obstacle_lb(float px, float py, const float* __
 constexpr int kWaves = kScreenThreads / 64;
 
 // ---- work-group reductions (every thread of the work-group calls them)
-__device__ __forceinline__ int block_sum_i32(int v, int* red) {
-  v = fw_sum_i32(v);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  int r = 0;
-#pragma unroll
-  for (int i = 0; i < kWaves; ++i) r += red[i];
-  __syncthreads();
-  return r;
-}
 
 // Threshold search on the key values (no atomics): returns X with
 // count(keys <= X) in [lo_n, hi_n] when one exists, else the largest X with
@@ -258,26 +248,6 @@ __device__ __forceinline__ int block_scan_min(int v, uint32_t m, uint32_t* slot,
   }
   *total = tot;
   *mn = r;
-  return base + x - v;
-}
-
-// Exclusive block scan of one int per thread; returns the prefix, *total
-// the sum.
-__device__ __forceinline__ int block_scan(int v, int* scratch, int* total) {
-  const int w = threadIdx.x >> 6;
-  int wt = 0;
-  const int x = fw_scan_i32(v, &wt);
-  if ((threadIdx.x & 63) == 0) scratch[w] = wt;
-  __syncthreads();
-  int base = 0, tot = 0;
-#pragma unroll
-  for (int i = 0; i < kWaves; ++i) {
-    const int t = scratch[i];
-    base += i < w ? t : 0;
-    tot += t;
-  }
-  __syncthreads();
-  *total = tot;
   return base + x - v;
 }
 

@@ -123,9 +123,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=24.0,
                     help="bound on the CPU-oracle sample (0 disables it)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--counters", choices=["", "c5", "c2"], default="",
+    ap.add_argument("--counters", choices=["", "c5", "c2", "screen"], default="",
                     help="only launch the workload's dominant call `steps` times (eagerly) and a "
-                         "256 MiB device copy (the calibration of the HBM byte counters)")
+                         "256 MiB device copy (the calibration of the HBM byte counters); "
+                         "screen: c5's bound-threshold and distance-ranked screened calls on "
+                         "staged circles, `steps` times each")
     ap.add_argument("--extras", type=int, default=1, help="also measure the secondary workloads")
     ap.add_argument("--screened", type=int, default=1, help="also measure the screened forms")
     return ap.parse_args()
@@ -432,6 +434,14 @@ def main():
             b = api.Batch(c5, graph=False)
             for _ in range(args.steps):
                 b.run()
+            b.close()
+        if args.counters == "screen":
+            b = api.Batch(c5, graph=False)
+            b.stage()
+            for _ in range(args.steps):
+                b.screened_bound()
+            for _ in range(args.steps):
+                b.screened(None, pool=128, topk=256)
             b.close()
         src = torch.ones(64 << 20, device="cuda")
         dst = torch.empty_like(src)

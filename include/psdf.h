@@ -354,7 +354,8 @@ int psdf_batch(psdf_batch_plan* plan, const float* poses, const float* ax, const
 /* Autotune the plan's launch shape on real inputs (same arguments as
  * psdf_batch): times each candidate (stages per work item 1, 2, 4, ..., 64 x
  * obstacles per tile 64 or 256 x persistent grid or one work-group per
- * item) on `stream`,
+ * item) on `stream` as a burst of back-to-back calls, in two rounds over
+ * all candidates after ten warm-up calls (the better burst counts),
  * synchronising it, keeps the fastest in the plan and in a
  * process-wide cache keyed by the batch's size signature (later plans of the
  * same signature start from it; with PSDF_TUNE_CACHE set to a file path the

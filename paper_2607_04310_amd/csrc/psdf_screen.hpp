@@ -129,6 +129,125 @@ __device__ __forceinline__ float obstacle_lb(float px, float py, const float* __
 
 constexpr int kWaves = kScreenThreads / 64;
 
+// ---- one four-edge-class obstacle per quad of lanes (staged rows)
+//
+// sd of the obstacle of staged row r, evaluated by the four lanes of a quad,
+// lane j <-> edge slot j (the row's repeated slots included), equal bit for
+// bit to obstacle_sd<MF, 4> on row_obstacle's registers: each lane takes
+// edge j against every robot vertex and the obstacle point(s) of slot j
+// against every robot edge with the same operations, the minima and maxima
+// are then reduced across the quad (the order of a minimum does not matter),
+// and the soft-min's sum adds the obstacle axes' terms in slot order after
+// the robot axes', as obstacle_sd does.  Every lane of the quad must be
+// active; all four return the sd, and mi the row's edge count (0 when !act).
+template <int C>
+__device__ __forceinline__ float quad_dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), C, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float quad_min(float x) {
+  x = fminf(x, quad_dpp<kDppXor1>(x));
+  return fminf(x, quad_dpp<kDppXor2>(x));
+}
+__device__ __forceinline__ float quad_max(float x) {
+  x = fmaxf(x, quad_dpp<kDppXor1>(x));
+  return fmaxf(x, quad_dpp<kDppXor2>(x));
+}
+
+template <int MF>
+__device__ __forceinline__ float quad_sd(const FpConst& F, const unsigned char* __restrict__ rows,
+                                         size_t r, bool act, const float4* rf, float px, float py,
+                                         int& mi) {
+  constexpr int MI = 4;
+  const int j = threadIdx.x & 3;
+  const unsigned char* b = rows + r * kRowBytes<MI>;
+  int4 meta = make_int4(0, 0, 0, 0);
+  float4 Aj = make_float4(0.f, 0.f, 0.f, 0.f), Bj = Aj;
+  if (act) {
+    meta = *reinterpret_cast<const int4*>(b + 40 * MI);
+    Aj = reinterpret_cast<const float4*>(b)[j];
+    Bj = reinterpret_cast<const float4*>(b + 16 * MI)[j];
+  }
+  mi = meta.y;
+  const bool closed = (meta.z & 1) != 0, bad = (meta.z & 2) != 0;
+  float2 Pj = make_float2(0.f, 0.f);
+  if (act && !closed) Pj = reinterpret_cast<const float2*>(b + 32 * MI)[j];
+  const float ux = Aj.z, uy = Aj.w, len = Bj.x, olo = Bj.y, ohi = Bj.z;
+  const float tax = Aj.x - px, tay = Aj.y - py;
+  const float ca = fmaf(tax, ux, tay * uy);
+  const float cb = fmaf(tay, ux, -(tax * uy));
+
+  // robot vertices against edge j; the robot's interval on n'_j
+  float dv2 = __builtin_huge_valf(), rlo = __builtin_huge_valf(), rhi = -__builtin_huge_valf();
+#pragma unroll
+  for (int l = 0; l < MF; ++l) {
+    const float4 q = rf[l];
+    const float a = fmaf(q.x, ux, fmaf(q.y, uy, -ca));
+    const float bb = fmaf(q.y, ux, fmaf(-q.x, uy, -cb));
+    rlo = fminf(rlo, bb);
+    rhi = fmaxf(rhi, bb);
+    dv2 = fminf(dv2, frame_d2(a, bb, len));
+  }
+  // obstacle point(s) of slot j against the robot edges
+  float ra_lo[MF], ra_hi[MF], de2 = __builtin_huge_valf();
+#pragma unroll
+  for (int l = 0; l < MF; ++l) { ra_lo[l] = __builtin_huge_valf(); ra_hi[l] = -__builtin_huge_valf(); }
+  auto visit = [&](float wx, float wy) {
+#pragma unroll
+    for (int l = 0; l < MF; ++l) {
+      const float4 q = rf[l];
+      const float a = fmaf(wx, q.z, fmaf(wy, q.w, -F.cu[l]));
+      const float bb = fmaf(wx, q.w, fmaf(-wy, q.z, -F.cn[l]));
+      ra_lo[l] = fminf(ra_lo[l], bb);
+      ra_hi[l] = fmaxf(ra_hi[l], bb);
+      de2 = fminf(de2, frame_d2(a, bb, F.len[l]));
+    }
+  };
+  visit(tax, tay);
+  if (!closed) visit(Pj.x - px, Pj.y - py);
+
+  // across the quad
+  dv2 = quad_min(dv2);
+  de2 = quad_min(de2);
+  float dl[MF];
+  bool sep = false;
+#pragma unroll
+  for (int l = 0; l < MF; ++l) {
+    ra_lo[l] = quad_min(ra_lo[l]);
+    ra_hi[l] = quad_max(ra_hi[l]);
+    dl[l] = fminf(ra_hi[l] - F.oa[l], F.ob[l] - ra_lo[l]);
+    sep = sep || (dl[l] < -F.eps_sat);
+  }
+  const float dlo = fminf(ohi - rlo, rhi - olo);   // obstacle axis j
+  const float sepo = (dlo < -F.eps_sat) ? 1.f : 0.f;
+  sep = sep || quad_max(sepo) > 0.f;
+
+  float sd = sqrtf(fminf(dv2, de2));
+  if (!sep) {
+    float mu = __builtin_huge_valf();
+#pragma unroll
+    for (int q = 0; q < MF; ++q) mu = fminf(mu, fmaxf(dl[q], 0.0f));
+    mu = fminf(mu, quad_min(fmaxf(dlo, 0.0f)));
+    float depth = mu;
+    if (!F.hard) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int q = 0; q < MF; ++q)
+        if (q < F.m) acc += expf(-F.eta * (fmaxf(dl[q], 0.0f) - mu));
+      const float ej = expf(-F.eta * (fmaxf(dlo, 0.0f) - mu));
+      const float e0 = quad_dpp<0x00>(ej), e1 = quad_dpp<0x55>(ej);
+      const float e2 = quad_dpp<0xAA>(ej), e3 = quad_dpp<0xFF>(ej);
+      if (0 < mi) acc += e0;
+      if (1 < mi) acc += e1;
+      if (2 < mi) acc += e2;
+      if (3 < mi) acc += e3;
+      depth = mu - logf(acc) / F.eta;
+    }
+    sd = -depth;
+  }
+  if (bad) sd = __builtin_nanf("");
+  return sd;
+}
+
 // ---- work-group reductions (every thread of the work-group calls them)
 
 // Threshold search on the key values (no atomics): returns X with
@@ -649,10 +768,22 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
   wave_sync();   // rf is written
   uint64_t seed_key = kEmptyKey;
   int seed_o = -1;
+  // four-edge-class obstacles on staged rows are evaluated one per quad of
+  // lanes (quad_sd, bit-identical to obstacle_sd): the seed by the first
+  // quad, and a few candidates 16 at a time
+  const bool quads = MI == 4 && A.rows != nullptr;
   if (lo != ~0ull) {
     seed_o = (int)(lo & 0xffffu);
     uint32_t kk = 0u;
-    if (lane == 0) {
+    if constexpr (MI == 4) {
+      if (quads) {
+        int mi;
+        const float sdq = quad_sd<MF>(F, A.rows, (size_t)in.circ_off + seed_o, lane < 4, rf, px,
+                                      py, mi);
+        kk = pose_ok ? orderable(sdq) : 0u;
+      }
+    }
+    if (!quads && lane == 0) {
       int mi;
       Obst<MI> ob;
       screen_obstacle<MI>(ob, A, in, seed_o, true, F.eps, mi);
@@ -690,9 +821,28 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
   const bool overflow = n_cand > kBoundCap;
   wave_sync();
 
-  // ---- exact evaluation of the candidates (lane <-> candidate)
+  // ---- exact evaluation of the candidates: a quad per candidate while they
+  // fit two passes (32), else lane <-> candidate
   uint64_t keyK = seed_key;
-  if (!overflow) {
+  bool done = false;
+  if constexpr (MI == 4) {
+    if (quads && !overflow && n_cand <= 32) {
+      for (int c0 = 0; c0 < n_cand; c0 += 16) {
+        const int c = c0 + (lane >> 2);
+        const bool act = c < n_cand;
+        const int o = act ? cand_o[c] : 0;
+        int mi;
+        const float sdq = quad_sd<MF>(F, A.rows, (size_t)in.circ_off + o, act, rf, px, py, mi);
+        uint32_t kk = 0xffffffffu;
+        if (act && mi != 0) kk = pose_ok ? orderable(sdq) : 0u;
+        const uint64_t key = kk == 0xffffffffu ? kEmptyKey : (((uint64_t)kk << 32) | (uint32_t)o);
+        const uint64_t wmin = fw_min_u64(key);
+        keyK = wmin < keyK ? wmin : keyK;
+      }
+      done = true;
+    }
+  }
+  if (!overflow && !done) {
     for (int c0 = 0; c0 < n_cand; c0 += 64) {
       const int c = c0 + lane;
       const bool act = c < n_cand;

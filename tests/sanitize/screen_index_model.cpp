@@ -473,6 +473,12 @@ void bound_stage(std::mt19937& g, int n_h, int mode) {
   if (!overflow && written != n_cand) { std::fprintf(stderr, "candidates written\n"); std::abort(); }
   for (size_t i = 1; i < order.size(); ++i)
     if (order[i] <= order[i - 1]) { std::fprintf(stderr, "candidates out of list order\n"); std::abort(); }
+  // exact evaluation: a quad of lanes per candidate while they fit two
+  // passes (four-edge class on staged rows), else a lane per candidate
+  if (!overflow && n_cand <= 32)
+    for (int c0 = 0; c0 < n_cand; c0 += 16)
+      for (int l = 0; l < 64; ++l)
+        if (c0 + (l >> 2) < n_cand) (void)cand_o[c0 + (l >> 2)];
   if (!overflow)
     for (int c0 = 0; c0 < n_cand; c0 += 64)
       for (int l = 0; l < 64; ++l)

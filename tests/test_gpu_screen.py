@@ -520,3 +520,37 @@ def test_staged_circles_checks_and_restage(api):
     torch.cuda.synchronize()
     _assert_same([x.clone() for x in out], plain)
     b.close()
+
+
+@pytest.mark.parametrize("eta", [50.0, 1000.0, math.inf])
+def test_staged_bound_quads_bitwise(api, eta):
+    """The bound screen on staged rows evaluates its seed and a few candidates
+    one obstacle per quad of lanes, and larger candidate sets one obstacle
+    per lane: both give the plain batch's outputs bit for bit, at a soft, the
+    default and the hard minimum, on penetrating stages, free segments, an
+    open chain, an obstacle with a NaN coordinate and candidate sets on both
+    sides of the quad path's limit (32)."""
+    rng = np.random.default_rng(57)
+    mixed = [inputs.random_small(rng, n_obst=60, n_poses=24, segments=8, lo=-2, hi=2)
+             for _ in range(4)]
+    bad = mixed[2]
+    bad.edges = bad.edges.copy()
+    bad.edges[5, 1] = np.nan             # an edge of the second rectangle
+    fp = inputs.hexagon_footprint(inputs.rng_for(2, 0))
+    chain = inputs.Instance(fp, np.array([[3.0, 1.0, 0.0], [3.0, 1.0, 0.4]], np.float32),
+                            np.array([[0, 0, 4, 0], [4, 0, 4, 4]], np.float32),
+                            np.array([0, 2], np.int32), 4, dict(workload="open_chain"))
+    insts = mixed + [chain, _copies_instance(40, (0.5, 0.0), 0.3, 6, 5), inputs.c5_instance(3)]
+    p = api.Params(eta=eta)
+    b = api.Batch(insts, graph=False, params=p)
+    print(f"[quads] eta={eta} {len(insts)} instances", flush=True)
+    plain = _run_plain(b)
+    lanes = [x.clone() for x in b.screened_bound()]
+    b.stage()
+    out, (cand, cert, _) = b.screened_bound(stats=True)
+    torch.cuda.synchronize()
+    _assert_same([x.clone() for x in out], plain)
+    _assert_same(lanes, plain)
+    n = cand.cpu().numpy()
+    assert (n <= 33).any() and (n > 33).any(), "both evaluation paths taken"
+    b.close()

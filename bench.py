@@ -123,11 +123,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=24.0,
                     help="bound on the CPU-oracle sample (0 disables it)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--counters", choices=["", "c5", "c2", "screen"], default="",
+    ap.add_argument("--counters", choices=["", "c5", "c2", "screen", "single"], default="",
                     help="only launch the workload's dominant call `steps` times (eagerly) and a "
                          "256 MiB device copy (the calibration of the HBM byte counters); "
                          "screen: c5's bound-threshold and distance-ranked screened calls on "
-                         "staged circles, `steps` times each")
+                         "staged circles, `steps` times each; single: one pose against 4194304 "
+                         "rectangles (16.7 M edges)")
     ap.add_argument("--extras", type=int, default=1, help="also measure the secondary workloads")
     ap.add_argument("--screened", type=int, default=1, help="also measure the screened forms")
     return ap.parse_args()
@@ -416,6 +417,15 @@ def main():
 
     from paper_2607_04310_amd import _lib, api, flops, inputs
 
+    if args.counters == "single":
+        inst = inputs.single_pose(1 << 22)
+        es = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar, device="cuda")
+        poses = torch.tensor(inst.poses, device="cuda")
+        ws = api.workspace(1, inst.M, "cuda")
+        for _ in range(args.steps):
+            api.psdf_grad(inst.footprint, poses, es, ws=ws)
+        torch.cuda.synchronize()
+        del es
     if args.counters == "c2":
         inst = inputs.c2(0)
         es = api.EdgeSet(inst.edges, inst.obst_off, inst.mbar, device="cuda")

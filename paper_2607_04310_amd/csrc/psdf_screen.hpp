@@ -13,7 +13,8 @@
 // Lower bounds (world frame, pose origin p, footprint radius rmax about the
 // origin; every footprint point is within rmax of p):
 //  * every obstacle: its bounding circle (c_i, r_i), computed once per call
-//    (obstacle_circle, in the horizon pass), gives
+//    (obstacle_circle, in the horizon pass) or once per edge set
+//    (psdf_batch_stage), gives
 //    dist(P0(x), P^i) >= |p - c_i| - r_i - rmax;
 //  * an instance's stages share a horizon bound (horizon_kernel) for the
 //    obstacles left out of the instance's list;

@@ -59,6 +59,15 @@ struct BatchArgs {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Instance inst's footprint constants read through the constant address
+// space: the table is written before a launch and never during it, so the
+// compiler may keep its uniform fields in scalar registers or reload them
+// with scalar loads instead of vector loads (same values).
+__device__ __forceinline__ const FpConst& fp_const(const FpConst* fps, int inst) {
+  typedef const __attribute__((address_space(4))) FpConst FpC;
+  return *(const FpConst*)((FpC*)fps + inst);
+}
+
 // Waves per SIMD the compiler must fit: four for four-edge obstacles with a
 // footprint of at most six slots, whose register need (154 VGPRs at six
 // slots with the own-axis intervals hoisted, three waves) then fits 128
@@ -95,7 +104,7 @@ void batch_kernel(BatchArgs A) {
     const int inst = uniform(item.inst), s0 = uniform(item.s0), ns = uniform(item.ns);
     const int o0 = uniform(item.o0), no = uniform(item.no), tile = uniform(item.tile);
     const BatchInst in = A.insts[inst];
-    const FpConst& F = A.fps[inst];
+    const FpConst& F = fp_const(A.fps, inst);
 
     // obstacle of this lane (indices local to the instance; edges global)
     const int ol = w * 64 + lane;

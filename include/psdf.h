@@ -330,7 +330,9 @@ enum {
 /* Build a plan.  desc: host array of n_inst descriptors; footprints: host
  * float32[][2] indexed by desc[k].fp_off; mbar: bound on the edges per
  * obstacle over all instances (1..16).  Validates every footprint
- * (PSDF_ENONCONVEX / PSDF_EDEGENERATE name the instance in the message),
+ * (PSDF_ENONCONVEX / PSDF_EDEGENERATE name the instance in the message) and
+ * that the instances' stage rows [pose_off, pose_off + N) tile the packed
+ * rows [0, sum N) (else PSDF_EINVAL),
  * allocates the plan's device tables and scratch (freed by
  * psdf_batch_plan_destroy) on the current device.  Calls that use one plan
  * must not overlap in time (the plan's scratch is shared). */

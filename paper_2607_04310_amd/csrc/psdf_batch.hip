@@ -54,6 +54,7 @@ struct psdf_batch_plan {
   // screening: stage -> instance, stage rows grouped by footprint size,
   // failed lists and counters (three per group)
   int* d_stage_inst = nullptr;
+  FinStage* d_fin = nullptr;      // per stage: the finish kernel's record (set per shape)
   int4* d_stage_list = nullptr;   // (stage row, instance, circ_off, M) per screened stage
   int* d_failed = nullptr;
   unsigned* d_sctrl = nullptr;
@@ -184,6 +185,7 @@ void free_graph(psdf_batch_plan* p) {
 int build_items(psdf_batch_plan* p, Shape sh) {
   const int tile = 64 * sh.nw;
   std::vector<BatchInst> inst(p->n_inst);
+  std::vector<FinStage> fin(std::max(1, p->total_stages), FinStage{0, 0, 0, 0, 0, 0, 0, 0});
   std::vector<BatchItem> items;
   std::vector<double> cost;
   size_t part = 0, circ = 0;
@@ -199,6 +201,8 @@ int build_items(psdf_batch_plan* p, Shape sh) {
     // ceil(N / sb) stage blocks of equal length (within one stage), so no
     // block pays an item's setup for a short remainder
     const int nb = (d.N + sh.sb - 1) / sh.sb;
+    for (int t = 0; t < d.N; ++t)
+      fin[d.pose_off + t] = FinStage{k, b.part_off + t * b.nt, b.nt, d.obst_off, d.M, d.edge_off, d.E, 0};
     part += (size_t)d.N * b.nt;
     if (d.M == 0) continue;
     const double per_edge = (double)d.E / std::max(1, d.M);
@@ -226,6 +230,8 @@ int build_items(psdf_batch_plan* p, Shape sh) {
     return set_error(PSDF_EINVAL, "internal: plan capacity exceeded");
   hipError_t err = hipMemcpy(p->d_inst, inst.data(), inst.size() * sizeof(BatchInst),
                              hipMemcpyHostToDevice);
+  if (err == hipSuccess)
+    err = hipMemcpy(p->d_fin, fin.data(), fin.size() * sizeof(FinStage), hipMemcpyHostToDevice);
   if (err == hipSuccess && !sorted.empty())
     err = hipMemcpy(p->d_items, sorted.data(), sorted.size() * sizeof(BatchItem),
                     hipMemcpyHostToDevice);
@@ -271,86 +277,106 @@ BatchArgs make_args(psdf_batch_plan* p, const float* poses, const float* ax, con
 // item (or screening) counters of the launches before it on the stream, and
 // opens the n_inst horizon lists for the next screened call (count 0, bound
 // +inf).
-constexpr int kFinWaves = 1;   // stages per finish work-group (one wave each)
+//
+// The kernel is latency-bound (one wave per stage, a few waves per CU), so
+// its loads are issued in as few dependent rounds as the data allows: the
+// stage record, pose and key first; then the footprint, the partial row
+// (up to four keys per lane in flight) or the obstacle's offsets; then the
+// winning column's aux word (a partial row's keys are distinct, each
+// column's obstacle indices being its own, so the column is unique); then
+// the winner's edges.
+constexpr int kFinKeys = 4;   // partial keys per lane per round
 
-__global__ __launch_bounds__(64 * kFinWaves) void batch_finish_kernel(
-    const FpConst* __restrict__ fps, const BatchInst* __restrict__ insts,
-    const int* __restrict__ stage_inst, int S, const float* __restrict__ poses,
-    const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ bx,
-    const float* __restrict__ by, const int* __restrict__ off,
+// One 64-lane work-group per stage: g = blockIdx.x, uniform.
+__global__ __launch_bounds__(64) void batch_finish_kernel(
+    const FpConst* __restrict__ fps, const FinStage* __restrict__ fin, int S,
+    const float* __restrict__ poses, const float* __restrict__ ax, const float* __restrict__ ay,
+    const float* __restrict__ bx, const float* __restrict__ by, const int* __restrict__ off,
     const uint64_t* __restrict__ partial, const uint64_t* __restrict__ aux,
     uint64_t* __restrict__ keys, float* __restrict__ d, int* __restrict__ edge,
     int* __restrict__ obst, float* __restrict__ grad, unsigned* __restrict__ ctrl, int n_ctrl,
     int* __restrict__ hcount, uint32_t* __restrict__ hrest, int n_inst) {
-  __shared__ FpLds fl[kFinWaves];
-  __shared__ WinnerLds wl[kFinWaves];
+  __shared__ FpLds fl;
+  __shared__ WinnerLds wl;
+  const int lane = threadIdx.x;
+  const int g = blockIdx.x;
+  if (g < S) {
+    // round 1: the record (written before the launch: scalar loads), pose, key
+    typedef const __attribute__((address_space(4))) FinStage FinC;
+    const FinStage& R = *(const FinStage*)((FinC*)fin + g);
+    const float* p = poses + 3 * g;
+    const float px = p[0], py = p[1], th = p[2];
+    uint64_t key = partial ? kEmptyKey : keys[g];
+    // round 2: footprint, partial keys or offsets
+    const FpConst& F = fp_const(fps, R.inst);
+    stage_footprint(fl, F);
+    int e0 = 0, mi = 0;
+    bool valid;
+    if (partial) {
+      const uint64_t* prow = partial + R.row;
+      int col = 0;
+      for (int j0 = 0; j0 < R.nt; j0 += 64 * kFinKeys) {
+        uint64_t k[kFinKeys];
+#pragma unroll
+        for (int u = 0; u < kFinKeys; ++u) {
+          const int j = j0 + 64 * u + lane;
+          k[u] = j < R.nt ? prow[j] : kEmptyKey;
+        }
+#pragma unroll
+        for (int u = 0; u < kFinKeys; ++u)
+          if (k[u] < key) { key = k[u]; col = j0 + 64 * u + lane; }
+      }
+      const uint64_t kmin = wave_min_u64(key);
+      const int first = __ffsll((unsigned long long)__ballot(key == kmin)) - 1;
+      col = (int)lane_u32((uint32_t)col, first);
+      key = kmin;
+      // round 3: the winning column's aux word
+      const uint64_t a = key != kEmptyKey ? aux[R.row + col] : 0ull;
+      e0 = (int)(uint32_t)(a >> 32);
+      mi = (int)(uint32_t)(a & 0xffffffffu);
+      valid = key != kEmptyKey && (key >> 32) != 0 && mi >= 1 && mi <= kMaxObst;
+    } else {
+      const int i = (int)(key & 0xffffffffu);
+      valid = key != kEmptyKey && (key >> 32) != 0 && (uint64_t)i < (uint64_t)R.M;
+      if (valid) {
+        e0 = off[R.obst_off + i];
+        mi = off[R.obst_off + i + 1] - e0;
+        e0 += R.edge_off;
+        valid = mi >= 1 && mi <= kMaxObst && e0 >= R.edge_off && e0 <= R.edge_off + R.E - mi;
+      }
+    }
+    float sn, cs;
+    sincosf(th, &sn, &cs);
+    wave_sync();
+    float dv = __builtin_huge_valf(), gv[3] = {0.f, 0.f, 0.f};
+    int ev = -1, ov = -1;
+    if (key != kEmptyKey && !valid) {
+      dv = __builtin_nanf("");
+      gv[0] = gv[1] = gv[2] = dv;
+    } else if (valid) {
+      // last round: the winner's edges
+      int jstar = 0;
+      winner_adjoint(F, fl, wl, ax, ay, bx, by, e0, mi, cs, sn, px, py, true, jstar, gv);
+      dv = from_orderable((uint32_t)(key >> 32));
+      ov = (int)(key & 0xffffffffu);
+      ev = e0 - R.edge_off + jstar;
+    }
+    if (lane == 0) {
+      keys[g] = key;
+      d[g] = dv;
+      edge[g] = ev;
+      obst[g] = ov;
+      grad[3 * g + 0] = gv[0];
+      grad[3 * g + 1] = gv[1];
+      grad[3 * g + 2] = gv[2];
+    }
+  }
   if (blockIdx.x == 0) {
     if ((int)threadIdx.x < n_ctrl) ctrl[threadIdx.x] = 0u;
     for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
       hcount[i] = 0;
       hrest[i] = 0xffffffffu;
     }
-  }
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = blockIdx.x * kFinWaves + w;
-  if (g >= S) return;
-  const int inst = __builtin_amdgcn_readfirstlane(stage_inst[g]);
-  const BatchInst in = insts[inst];
-  const FpConst& F = fps[inst];
-  stage_footprint(fl[w], F);
-  const float* p = poses + 3 * g;
-  const float px = p[0], py = p[1];
-  float sn, cs;
-  sincosf(p[2], &sn, &cs);
-  uint64_t key = kEmptyKey;
-  int e0 = 0, mi = 0;
-  bool valid;
-  if (partial) {
-    uint64_t a = 0;
-    const size_t row = (size_t)in.part_off + (size_t)(g - in.pose_off) * in.nt;
-    for (int j = lane; j < in.nt; j += 64) {
-      const uint64_t k = partial[row + j];
-      if (k < key) { key = k; a = aux[row + j]; }
-    }
-    const uint64_t kmin = wave_min_u64(key);
-    const int first = __ffsll((unsigned long long)__ballot(key == kmin)) - 1;
-    a = lane_u64(a, first);
-    key = kmin;
-    e0 = (int)(uint32_t)(a >> 32);
-    mi = (int)(uint32_t)(a & 0xffffffffu);
-    valid = key != kEmptyKey && (key >> 32) != 0 && mi >= 1 && mi <= kMaxObst;
-  } else {
-    key = keys[g];
-    const int i = (int)(key & 0xffffffffu);
-    valid = key != kEmptyKey && (key >> 32) != 0 && (uint64_t)i < (uint64_t)in.M;
-    if (valid) {
-      e0 = off[in.obst_off + i];
-      mi = off[in.obst_off + i + 1] - e0;
-      e0 += in.edge_off;
-      valid = mi >= 1 && mi <= kMaxObst && e0 >= in.edge_off && e0 <= in.edge_off + in.E - mi;
-    }
-  }
-  wave_sync();
-  float dv = __builtin_huge_valf(), gv[3] = {0.f, 0.f, 0.f};
-  int ev = -1, ov = -1;
-  if (key != kEmptyKey && !valid) {
-    dv = __builtin_nanf("");
-    gv[0] = gv[1] = gv[2] = dv;
-  } else if (valid) {
-    int jstar = 0;
-    winner_adjoint(F, fl[w], wl[w], ax, ay, bx, by, e0, mi, cs, sn, px, py, true, jstar, gv);
-    dv = from_orderable((uint32_t)(key >> 32));
-    ov = (int)(key & 0xffffffffu);
-    ev = e0 - in.edge_off + jstar;
-  }
-  if (lane == 0) {
-    keys[g] = key;
-    d[g] = dv;
-    edge[g] = ev;
-    obst[g] = ov;
-    grad[3 * g + 0] = gv[0];
-    grad[3 * g + 1] = gv[1];
-    grad[3 * g + 2] = gv[2];
   }
 }
 
@@ -386,9 +412,9 @@ int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay
       if (err == hipSuccess && k > 0) err = hipStreamWaitEvent(st, p->ev[k], 0);
     }
     if (err != hipSuccess) return err;
-    batch_finish_kernel<<<(p->total_stages + kFinWaves - 1) / kFinWaves, 64 * kFinWaves, 0, st>>>(
-        p->d_fp, p->d_inst, p->d_stage_inst, p->total_stages, poses, ax, ay, bx, by, off,
-        a.partial, a.aux, keys, d, edge, obst, grad, p->d_ctrl, kGroups, nullptr, nullptr, 0);
+    batch_finish_kernel<<<p->total_stages, 64, 0, st>>>(
+        p->d_fp, p->d_fin, p->total_stages, poses, ax, ay, bx, by, off, a.partial, a.aux, keys, d,
+        edge, obst, grad, p->d_ctrl, kGroups, nullptr, nullptr, 0);
     return hipGetLastError();
   };
   if (!use_graph) return hip_status(enqueue(stream, true));
@@ -538,11 +564,9 @@ static int screened_run(psdf_batch_plan* p, bool bound, const float* theta, int3
   }
   timer_end(stream);
   if (err == hipSuccess) {
-    batch_finish_kernel<<<(p->total_stages + kFinWaves - 1) / kFinWaves, 64 * kFinWaves, 0,
-                          stream>>>(
-        p->d_fp, p->d_inst, p->d_stage_inst, p->total_stages, poses, ax, ay, bx, by, off, nullptr,
-        nullptr, keys, d, edge, obst, grad, p->d_sctrl, 2 * kGroups, p->d_hcount, p->d_hrest,
-        p->n_inst);
+    batch_finish_kernel<<<p->total_stages, 64, 0, stream>>>(
+        p->d_fp, p->d_fin, p->total_stages, poses, ax, ay, bx, by, off, nullptr, nullptr, keys, d,
+        edge, obst, grad, p->d_sctrl, 2 * kGroups, p->d_hcount, p->d_hrest, p->n_inst);
     err = hipGetLastError();
   }
   return hip_status(err);
@@ -643,6 +667,7 @@ void psdf_batch_plan_destroy(psdf_batch_plan* p) {
   (void)hipFree(p->d_partial);
   (void)hipFree(p->d_ctrl);
   (void)hipFree(p->d_stage_inst);
+  (void)hipFree(p->d_fin);
   (void)hipFree(p->d_stage_list);
   (void)hipFree(p->d_failed);
   (void)hipFree(p->d_sctrl);
@@ -692,6 +717,31 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
     items_max += (size_t)d.N * nt64;
   }
   if (stages > 0x7fffffffL) { delete p; return set_error(PSDF_ETOOBIG, "too many stages"); }
+  // partial rows are addressed with 32-bit offsets (at most one 64-obstacle
+  // tile per column)
+  if (part_max > 0x7fffffffu) { delete p; return set_error(PSDF_ETOOBIG, "too many partial keys"); }
+  // the instances' stage rows tile [0, sum N): each row belongs to exactly
+  // one instance (in range and disjoint; the counts then cover every row)
+  {
+    std::vector<int> owner((size_t)stages, -1);
+    for (int k = 0; k < n_inst; ++k) {
+      const psdf_batch_desc& d = desc[k];
+      if ((long)d.pose_off + d.N > stages) {
+        delete p;
+        return set_error(PSDF_EINVAL, "instance %d: stage rows [%d, %ld) beyond the %ld packed rows",
+                         k, d.pose_off, (long)d.pose_off + d.N, stages);
+      }
+      for (int t = 0; t < d.N; ++t) {
+        int& o = owner[(size_t)d.pose_off + t];
+        if (o >= 0) {
+          delete p;
+          return set_error(PSDF_EINVAL, "instance %d: stage row %d also belongs to instance %d", k,
+                           d.pose_off + t, o);
+        }
+        o = k;
+      }
+    }
+  }
   p->total_stages = (int)stages;
   hipError_t err = hipGetDevice(&p->device);
   int cu = 0;
@@ -761,6 +811,7 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
     if (err == hipSuccess)
       err = hipMemset(p->d_hrest, 0xff, std::max<size_t>(1, (size_t)n_inst) * sizeof(uint32_t));
     if (err == hipSuccess) err = hipMalloc(&p->d_stage_inst, S * sizeof(int));
+    if (err == hipSuccess) err = hipMalloc(&p->d_fin, S * sizeof(FinStage));
     if (err == hipSuccess) err = hipMalloc(&p->d_stage_list, S * sizeof(int4));
     if (err == hipSuccess) err = hipMalloc(&p->d_failed, S * sizeof(int));
     if (err == hipSuccess) err = hipMalloc(&p->d_sctrl, 2 * kGroups * sizeof(unsigned));

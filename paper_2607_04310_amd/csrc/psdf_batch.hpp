@@ -30,6 +30,14 @@ struct BatchInst {
   int circ_off;   // first bounding circle of this instance's obstacles (screening)
 };
 
+// What the finish kernel needs of a stage's instance, one record per stage,
+// so that its first loads (record, pose, key) do not wait on an instance
+// lookup.  row = part_off + (stage - pose_off) * nt: the stage's partial row
+// (depends on the tile width, so it is rewritten with the shape).
+struct FinStage {
+  int inst, row, nt, obst_off, M, edge_off, E, pad;
+};
+
 struct BatchItem {
   int inst, s0, ns, o0, no, tile;
 };

@@ -203,6 +203,25 @@ def test_stage_edges_argument_checks():
     assert list(out.src) == [None, None, None, None, 1]
 
 
+@pytest.mark.parametrize("rows", [
+    [(0, 3), (2, 2)],           # row 2 in both instances (row 4 in none)
+    [(0, 3), (4, 2)],           # beyond the 5 packed rows
+    [(3, 2), (0, 2), (2, 2)],   # row 3 twice
+])
+def test_batch_plan_rejects_stage_rows_that_do_not_tile(rows):
+    # plan creation checks the descriptors before it touches the device, so
+    # a rejected layout returns without a GPU
+    n = len(rows)
+    desc = (_lib.PsdfBatchDesc * n)(*[_lib.PsdfBatchDesc(0, 4, po, N, 0, 0, 0, 0) for po, N in rows])
+    fp = np.ascontiguousarray(RECT)
+    p = _lib.PsdfParams(1e-12, 1e-6, 1000.0)
+    plan = ctypes.c_void_p()
+    rc = _lib.lib().psdf_batch_plan_create(ctypes.byref(plan), desc, n,
+                                           fp.ctypes.data_as(ctypes.c_void_p), 4, ctypes.byref(p), 0)
+    assert rc == _lib.PSDF_EINVAL and not plan.value
+    assert "stage row" in _lib.lib().psdf_last_error().decode()
+
+
 def test_batch_stage_argument_checks():
     lib = _lib.lib()
     assert lib.psdf_batch_stage(None, 1, 1, 1, 1, 1, None) == _lib.PSDF_EINVAL

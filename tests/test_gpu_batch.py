@@ -210,3 +210,61 @@ def test_time_varying_edge_sets(api):
     ref0 = __import__("oracle").psdf(fp, poses[last:], stage_edges[0], stage_off[0])
     assert ref0["phi"][0] != pytest.approx(float(d[last]), abs=1e-4)
     b.close()
+
+
+def test_stage_rows_in_any_order(api):
+    """The instances' stage rows may tile the packed poses in any order: a plan
+    whose rows run in reverse instance order gives every stage the outputs it
+    gets in instance order, for the plain batch and the screened forms."""
+    import ctypes
+    from paper_2607_04310_amd import _lib
+    rng = np.random.default_rng(91)
+    insts = [inputs.random_small(rng, n_obst=40 + 30 * k, n_poses=10 + 3 * k, segments=3, lo=-3, hi=3)
+             for k in range(6)]
+    b = api.Batch(insts, graph=False)
+    n = b.n_inst
+    Ns = [dd[3] for dd in b.desc]
+    new_off, acc = [0] * n, 0
+    for k in reversed(range(n)):
+        new_off[k] = acc
+        acc += Ns[k]
+    # rows[r] = the row that stage r (instance order) takes in the reversed plan
+    rows = np.concatenate([np.arange(new_off[k], new_off[k] + Ns[k]) for k in range(n)])
+    b2 = api.Batch(insts, graph=False)
+    _lib.lib().psdf_batch_plan_destroy(b2.plan)
+    b2.plan = None
+    desc = [(dd[0], dd[1], new_off[k]) + tuple(dd[3:]) for k, dd in enumerate(b.desc)]
+    arr = (_lib.PsdfBatchDesc * n)(*[_lib.PsdfBatchDesc(*dd) for dd in desc])
+    plan, pc = ctypes.c_void_p(0), b2.params.c()
+    _lib.check(_lib.lib().psdf_batch_plan_create(
+        ctypes.byref(plan), arr, n, b2.footprints.ctypes.data_as(ctypes.c_void_p), b2.mbar,
+        ctypes.byref(pc), 0))
+    b2.plan, b2.desc = plan, desc
+    back = torch.tensor(np.argsort(rows), device=b.poses.device)   # new row -> old row
+    b2.poses = b.poses[back].contiguous()
+    print(f"[batch] {n} instances, {len(rows)} stage rows in reverse instance order", flush=True)
+
+    def outs(x):
+        torch.cuda.synchronize()
+        return [t.cpu().numpy() for t in (x.d, x.edge, x.obst, x.grad, x.keys)]
+
+    for form in ("plain", "bound", "distance", "bound_staged"):
+        if form == "bound_staged":
+            b.stage()
+            b2.stage()
+        for x in (b, b2):
+            if form == "plain":
+                x.run()
+            elif form == "distance":
+                x.screened(None, pool=128, topk=256)
+            else:
+                x.screened_bound()
+        ref, got = outs(b), outs(b2)
+        for u, v in zip(got, ref):
+            assert np.array_equal(u[rows], v, equal_nan=True), form
+    for k, inst in enumerate(insts):
+        sl = slice(b.desc[k][2], b.desc[k][2] + inst.N)
+        check_stages(inst.footprint, inst.poses, inst.edges, inst.obst_off, 1000.0,
+                     *[t[sl] for t in ref[:4]])
+    b.close()
+    b2.close()

@@ -57,6 +57,7 @@ struct psdf_batch_plan {
   FinStage* d_fin = nullptr;      // per stage: the finish kernel's record (set per shape)
   int4* d_stage_list = nullptr;   // (stage row, instance, circ_off, M) per screened stage
   int* d_failed = nullptr;
+  int* d_fdone = nullptr;         // per failed slot: tiles done (bound form)
   unsigned* d_sctrl = nullptr;
   float4* d_hlist = nullptr;  // horizon lists (circle, index), sum M
   uint4* d_frag = nullptr;    // the screener's lane fragments, kFragWords x 64
@@ -336,40 +337,14 @@ __global__ __launch_bounds__(64) void batch_finish_kernel(
       mi = (int)(uint32_t)(a & 0xffffffffu);
       valid = key != kEmptyKey && (key >> 32) != 0 && mi >= 1 && mi <= kMaxObst;
     } else {
-      const int i = (int)(key & 0xffffffffu);
-      valid = key != kEmptyKey && (key >> 32) != 0 && (uint64_t)i < (uint64_t)R.M;
-      if (valid) {
-        e0 = off[R.obst_off + i];
-        mi = off[R.obst_off + i + 1] - e0;
-        e0 += R.edge_off;
-        valid = mi >= 1 && mi <= kMaxObst && e0 >= R.edge_off && e0 <= R.edge_off + R.E - mi;
-      }
+      valid = key_range(key, off, R.obst_off, R.M, R.edge_off, R.E, e0, mi);
     }
     float sn, cs;
     sincosf(th, &sn, &cs);
     wave_sync();
-    float dv = __builtin_huge_valf(), gv[3] = {0.f, 0.f, 0.f};
-    int ev = -1, ov = -1;
-    if (key != kEmptyKey && !valid) {
-      dv = __builtin_nanf("");
-      gv[0] = gv[1] = gv[2] = dv;
-    } else if (valid) {
-      // last round: the winner's edges
-      int jstar = 0;
-      winner_adjoint(F, fl, wl, ax, ay, bx, by, e0, mi, cs, sn, px, py, true, jstar, gv);
-      dv = from_orderable((uint32_t)(key >> 32));
-      ov = (int)(key & 0xffffffffu);
-      ev = e0 - R.edge_off + jstar;
-    }
-    if (lane == 0) {
-      keys[g] = key;
-      d[g] = dv;
-      edge[g] = ev;
-      obst[g] = ov;
-      grad[3 * g + 0] = gv[0];
-      grad[3 * g + 1] = gv[1];
-      grad[3 * g + 2] = gv[2];
-    }
+    // last round: the winner's edges
+    write_stage(F, fl, wl, ax, ay, bx, by, key, valid, e0, mi, R.edge_off, cs, sn, px, py, g, keys,
+                d, edge, obst, grad);
   }
   if (blockIdx.x == 0) {
     if ((int)threadIdx.x < n_ctrl) ctrl[threadIdx.x] = 0u;
@@ -491,7 +466,10 @@ extern "C" {
 // The screened call of either form: the horizon pass, per footprint-size
 // group the screening kernel (ranked top-K with the network or the edge
 // distance, or the bound-threshold form) and the fallback of the stages
-// that fail the certificate, then the finish kernel.
+// that fail the certificate, then (ranked forms) the finish kernel.  The
+// bound form has no finish launch: its screen kernel writes the outputs of
+// the stages it certifies, the fallback those of the others, and the last
+// fallback launch reopens the horizon lists.
 static int screened_run(psdf_batch_plan* p, bool bound, const float* theta, int32_t pool,
                         int32_t topk, const float* poses, const float* ax, const float* ay,
                         const float* bx, const float* by, const int32_t* off, float* d,
@@ -529,6 +507,9 @@ static int screened_run(psdf_batch_plan* p, bool bound, const float* theta, int3
   a.hlist = p->d_hlist; a.hcount = p->d_hcount; a.hrest = p->d_hrest;
   a.theta = theta; a.frag = p->d_frag; a.pool = pool; a.topk = topk; a.keys = keys;
   a.stage_cand = stage_cand; a.stage_cert = stage_cert; a.cand_keys = cand_keys;
+  a.finish = bound ? 1 : 0;
+  a.d = d; a.edge = edge; a.obst = obst; a.grad = grad;
+  a.reset_n = 0; a.reset_hcount = p->d_hcount; a.reset_hrest = p->d_hrest;
   timer_begin(stream);
   hipError_t err = hipSuccess;
   if (p->n_inst > 0) {
@@ -537,24 +518,27 @@ static int screened_run(psdf_batch_plan* p, bool bound, const float* theta, int3
     if (p->mi_class == 4)
       horizon_kernel<4><<<grid, kScreenThreads, 0, stream>>>(
           p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, circ, p->d_hlist, p->d_hcount,
-          p->d_hrest, theta, p->d_frag);
+          p->d_hrest, theta, p->d_frag, p->d_sctrl, 2 * kGroups);
     else if (p->mi_class == 8)
       horizon_kernel<8><<<grid, kScreenThreads, 0, stream>>>(
           p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, circ, p->d_hlist, p->d_hcount,
-          p->d_hrest, theta, p->d_frag);
+          p->d_hrest, theta, p->d_frag, p->d_sctrl, 2 * kGroups);
     else
       horizon_kernel<16><<<grid, kScreenThreads, 0, stream>>>(
           p->d_fp, p->d_inst, poses, ax, ay, bx, by, off, circ, p->d_hlist, p->d_hcount,
-          p->d_hrest, theta, p->d_frag);
+          p->d_hrest, theta, p->d_frag, p->d_sctrl, 2 * kGroups);
     err = hipGetLastError();
   }
-  for (const auto& g : p->sgroups) {
+  for (size_t k = 0; k < p->sgroups.size(); ++k) {
     if (err != hipSuccess) break;
+    const auto& g = p->sgroups[k];
     ScreenArgs ga = a;
     ga.stages = p->d_stage_list + g.start;
     ga.n_stages = g.count;
     ga.failed = p->d_failed + g.start;
+    ga.fdone = p->d_fdone + g.start;
     ga.ctrl = p->d_sctrl + 2 * group_of(g.mf);
+    if (bound && k + 1 == p->sgroups.size()) ga.reset_n = p->n_inst;
     err = bound ? launch_screen_bound(g.mf, p->mi_class, g.count, ga, stream)
                 : launch_screen(g.mf, p->mi_class, g.count, ga, stream);
     if (err != hipSuccess) break;
@@ -563,7 +547,7 @@ static int screened_run(psdf_batch_plan* p, bool bound, const float* theta, int3
     if (err != hipSuccess) break;
   }
   timer_end(stream);
-  if (err == hipSuccess) {
+  if (err == hipSuccess && !bound) {
     batch_finish_kernel<<<p->total_stages, 64, 0, stream>>>(
         p->d_fp, p->d_fin, p->total_stages, poses, ax, ay, bx, by, off, nullptr, nullptr, keys, d,
         edge, obst, grad, p->d_sctrl, 2 * kGroups, p->d_hcount, p->d_hrest, p->n_inst);
@@ -670,6 +654,7 @@ void psdf_batch_plan_destroy(psdf_batch_plan* p) {
   (void)hipFree(p->d_fin);
   (void)hipFree(p->d_stage_list);
   (void)hipFree(p->d_failed);
+  (void)hipFree(p->d_fdone);
   (void)hipFree(p->d_sctrl);
   (void)hipFree(p->d_hlist);
   (void)hipFree(p->d_circ);
@@ -814,6 +799,7 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
     if (err == hipSuccess) err = hipMalloc(&p->d_fin, S * sizeof(FinStage));
     if (err == hipSuccess) err = hipMalloc(&p->d_stage_list, S * sizeof(int4));
     if (err == hipSuccess) err = hipMalloc(&p->d_failed, S * sizeof(int));
+    if (err == hipSuccess) err = hipMalloc(&p->d_fdone, S * sizeof(int));
     if (err == hipSuccess) err = hipMalloc(&p->d_sctrl, 2 * kGroups * sizeof(unsigned));
     if (err == hipSuccess) err = hipMemset(p->d_sctrl, 0, 2 * kGroups * sizeof(unsigned));
     if (err == hipSuccess)

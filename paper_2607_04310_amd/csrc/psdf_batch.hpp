@@ -76,6 +76,62 @@ __device__ __forceinline__ const FpConst& fp_const(const FpConst* fps, int inst)
   return *(const FpConst*)((FpC*)fps + inst);
 }
 
+// The winner's global edge range [e0, e0 + mi) from a final key whose low
+// word is the obstacle's index local to its instance (the screened forms):
+// false for the empty key, a NaN-free key that names no obstacle of the
+// instance, or an offset pair outside the instance's edges.
+__device__ __forceinline__ bool key_range(uint64_t key, const int* __restrict__ off, int obst_off,
+                                          int M, int edge_off, int E, int& e0, int& mi) {
+  const int i = (int)(key & 0xffffffffu);
+  e0 = 0;
+  mi = 0;
+  if (key == kEmptyKey || (key >> 32) == 0 || (uint64_t)i >= (uint64_t)M) return false;
+  e0 = off[obst_off + i];
+  mi = off[obst_off + i + 1] - e0;
+  e0 += edge_off;
+  return mi >= 1 && mi <= kMaxObst && e0 >= edge_off && e0 <= edge_off + E - mi;
+}
+
+// Stage g's outputs from its final key (Sec. IV-D: the winner adjoint of
+// the winning obstacle, edges [e0, e0 + mi) global): an empty key gives the
+// empty-set result (d = +inf, no winner, zero gradient); a key that names
+// no usable obstacle (valid false) gives NaN.  One whole wave with uniform
+// arguments; fl must hold F (stage_footprint) and be visible to the wave.
+// Every kernel that ends a stage goes through here, so a stage's outputs do
+// not depend on which kernel finished it.
+__device__ __forceinline__ void write_stage(const FpConst& F, const FpLds& fl, WinnerLds& wl,
+                                            const float* __restrict__ ax,
+                                            const float* __restrict__ ay,
+                                            const float* __restrict__ bx,
+                                            const float* __restrict__ by, uint64_t key,
+                                            bool valid, int e0, int mi, int edge_off, float cs,
+                                            float sn, float px, float py, int g,
+                                            uint64_t* __restrict__ keys, float* __restrict__ d,
+                                            int* __restrict__ edge, int* __restrict__ obst,
+                                            float* __restrict__ grad) {
+  float dv = __builtin_huge_valf(), gv[3] = {0.f, 0.f, 0.f};
+  int ev = -1, ov = -1;
+  if (key != kEmptyKey && !valid) {
+    dv = __builtin_nanf("");
+    gv[0] = gv[1] = gv[2] = dv;
+  } else if (valid) {
+    int jstar = 0;
+    winner_adjoint(F, fl, wl, ax, ay, bx, by, e0, mi, cs, sn, px, py, true, jstar, gv);
+    dv = from_orderable((uint32_t)(key >> 32));
+    ov = (int)(key & 0xffffffffu);
+    ev = e0 - edge_off + jstar;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    keys[g] = key;
+    d[g] = dv;
+    edge[g] = ev;
+    obst[g] = ov;
+    grad[3 * g + 0] = gv[0];
+    grad[3 * g + 1] = gv[1];
+    grad[3 * g + 2] = gv[2];
+  }
+}
+
 // Waves per SIMD the compiler must fit: four for four-edge obstacles with a
 // footprint of at most six slots, whose register need (154 VGPRs at six
 // slots with the own-axis intervals hoisted, three waves) then fits 128

@@ -111,8 +111,11 @@ __device__ float4 obstacle_circle(const BatchInst& in, const float* __restrict__
 // every stage.  A non-finite stage position disables the list (-1); a list
 // longer than kHorizonCap (tie blocks) is not used by the stage pass either:
 // the instance's stages then take the full evaluation.  On entry the
-// instance's count is 0 and its bound +inf (plan creation, then the finish
-// kernel of every screened call).  With a network the grid has one more
+// instance's count is 0 and its bound +inf (plan creation, then the end of
+// every screened call: its finish kernel, or in the bound form its last
+// fallback launch).  Work-group (0, 0) also clears the n_sctrl screening
+// counters (failed-stage counts) that the call's screen launches append
+// with.  With a network the grid has one more
 // column, whose first work-group builds the network's fragment table.
 // circ (may be null): the instances' bounding circles taken once per edge
 // set (circle_kernel, psdf_batch_stage), indexed like the lists; without it
@@ -132,12 +135,14 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
     const float* __restrict__ poses, const float* __restrict__ ax, const float* __restrict__ ay,
     const float* __restrict__ bx, const float* __restrict__ by, const int* __restrict__ off,
     const float4* __restrict__ circ, float4* __restrict__ hlist, int* __restrict__ hcount,
-    uint32_t* __restrict__ hrest, const float* __restrict__ theta, uint4* __restrict__ frag) {
+    uint32_t* __restrict__ hrest, const float* __restrict__ theta, uint4* __restrict__ frag,
+    unsigned* __restrict__ sctrl, int n_sctrl) {
   __shared__ int scan[kScreenThreads];
   // one slot per combined reduction below (none is reused, so none needs a
   // barrier after its reads): 5 + 2 + 3 + 2 groups of kWaves words
   __shared__ uint32_t rs[12 * kWaves];
   __shared__ int s_base;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && (int)threadIdx.x < n_sctrl) sctrl[threadIdx.x] = 0u;
   if (blockIdx.x == kHorizonSplit) {
     // the extra column: the screener network's per-lane weight fragments,
     // once per call (one wave), so that every stage's work-group reads them

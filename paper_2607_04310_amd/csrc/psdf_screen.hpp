@@ -76,6 +76,20 @@ struct ScreenArgs {
   int* stage_cand;         // optional: candidates evaluated per stage
   int* stage_cert;         // optional: 1 if certified
   uint64_t* cand_keys;     // optional: the candidates' minimum key (before any fallback)
+  // finish 1 (the bound form): the screen kernel writes a certified stage's
+  // outputs itself, and the fallback's last tile of a failed stage writes
+  // that stage's (no finish kernel); fdone counts a failed slot's tiles
+  int finish;
+  float* d;
+  int* edge;
+  int* obst;
+  float* grad;
+  int* fdone;              // this launch's, parallel to failed
+  // reset_n > 0: the fallback's work-group 0 reopens the horizon lists
+  // (count 0, bound +inf) after the call's last screen launch
+  int reset_n;
+  int* reset_hcount;
+  uint32_t* reset_hrest;
 };
 
 // Obstacle o (local index) of instance `in` in registers: from its staged
@@ -693,6 +707,8 @@ template <int MF, int MI>
 __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
   __shared__ int cand_o[kBoundCap];
   __shared__ float4 rf[MF];
+  __shared__ FpLds fl;
+  __shared__ WinnerLds wl;
 
   const int lane = threadIdx.x;
   const int4 si = A.stages[blockIdx.x];
@@ -716,7 +732,8 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
   sincosf(p[2], &sn, &cs);
   const bool pose_ok = isfinite(px) && isfinite(py) && isfinite(cs) && isfinite(sn);
   if (lane < MF) rf[lane] = rotated_slot(F, lane, cs, sn);
-  
+  if (A.finish) stage_footprint(fl, F);   // for the outputs of a certified stage
+
   const int hc = A.hcount[inst];
   if (hc < 0 || hc > kHorizonCap) {
     if (lane == 0) {
@@ -724,7 +741,9 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
       if (A.stage_cand) A.stage_cand[s] = 0;
       if (A.stage_cert) A.stage_cert[s] = 0;
       if (A.cand_keys) A.cand_keys[s] = kEmptyKey;
-      A.failed[atomicAdd(&A.ctrl[0], 1u)] = s;
+      const unsigned slot = atomicAdd(&A.ctrl[0], 1u);
+      A.failed[slot] = s;
+      if (A.finish) A.fdone[slot] = 0;
     }
     return;
   }
@@ -863,26 +882,52 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
   const uint32_t rest = A.hrest[inst];
   const bool cert = (keyK != kEmptyKey && (keyK >> 32) == 0)          // NaN wins anyway
                     || (!overflow && (rest == 0xffffffffu || rest > tkey));
+  if (A.finish && cert) {
+    // keyK is the stage's final key: its outputs, here
+    int e0, mi;
+    const bool valid = key_range(keyK, A.off, in.obst_off, in.M, in.edge_off, in.E, e0, mi);
+    wave_sync();   // fl is written
+    write_stage(F, fl, wl, A.ax, A.ay, A.bx, A.by, keyK, valid, e0, mi, in.edge_off, cs, sn, px,
+                py, s, A.keys, A.d, A.edge, A.obst, A.grad);
+  }
   if (lane == 0) {
-    A.keys[s] = keyK;
+    if (!(A.finish && cert)) A.keys[s] = keyK;
     if (A.stage_cand) A.stage_cand[s] = overflow ? 0 : n_cand + (seed_o >= 0 ? 1 : 0);
     if (A.stage_cert) A.stage_cert[s] = cert ? 1 : 0;
     if (A.cand_keys) A.cand_keys[s] = keyK;
-    if (!cert) A.failed[atomicAdd(&A.ctrl[0], 1u)] = s;
+    if (!cert) {
+      const unsigned slot = atomicAdd(&A.ctrl[0], 1u);
+      A.failed[slot] = s;
+      if (A.finish) A.fdone[slot] = 0;
+    }
   }
 }
 
 // Full evaluation of the failed stages: items (failed stage, tile of 256
 // obstacles), every item the same work, taken by the work-groups in turn
 // (item b, b + grid, ...); each work-group folds its tile's minimum into
-// keys[s] with a 64-bit atomicMin.  The failed count starts at zero: plan
-// creation clears it, and so does the finish kernel at the end of every
-// screened call.
-template <int MF, int MI>
+// keys[s] with a 64-bit atomicMin.  A stage has max(1, ceil(M / 256))
+// tiles (tile 0 stands for an instance without obstacles).  With FIN (the
+// bound form, A.finish), each tile then counts itself done on the stage's slot (agent-scope
+// acquire-release), and the tile that completes the count, which then sees
+// every tile's minimum, writes the stage's outputs.  The failed count
+// starts at zero: plan creation clears it, and so does the horizon pass at
+// the start of every screened call.  The finishing code raises the
+// kernel's register count, so the ranked forms launch the variant without
+// it (FIN false; their finish kernel ends the stages).
+template <int MF, int MI, bool FIN>
 __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int max_tiles) {
   __shared__ uint64_t wk[4];
   __shared__ float4 rf[MF];
+  __shared__ FpLds fl;
+  __shared__ WinnerLds wl;
+  __shared__ int s_last;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (blockIdx.x == 0)
+    for (int i = tid; i < A.reset_n; i += 256) {
+      A.reset_hcount[i] = 0;
+      A.reset_hrest[i] = 0xffffffffu;
+    }
   const int n_failed = (int)__hip_atomic_load(&A.ctrl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const long n_items = (long)n_failed * max_tiles;
   for (long item = blockIdx.x; item < n_items; item += gridDim.x) {
@@ -891,7 +936,7 @@ __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int 
     const int s = A.failed[it];
     const int inst = __builtin_amdgcn_readfirstlane(A.stage_inst[s]);
     const BatchInst in = A.insts[inst];
-    if (tile * 256 < in.M) {
+    if (tile == 0 || tile * 256 < in.M) {
       const FpConst& F = A.fps[inst];
       const float* p = A.poses + 3 * s;
       const float px = p[0], py = p[1];
@@ -915,6 +960,24 @@ __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int 
         uint64_t m = wk[0];
         for (int i = 1; i < 4; ++i) m = wk[i] < m ? wk[i] : m;
         if (m != kEmptyKey) atomicMin((unsigned long long*)&A.keys[s], (unsigned long long)m);
+        if constexpr (FIN) {
+          const int nt = max(1, (in.M + 255) / 256);
+          s_last = __hip_atomic_fetch_add(&A.fdone[it], 1, __ATOMIC_ACQ_REL,
+                                          __HIP_MEMORY_SCOPE_AGENT) == nt - 1;
+        }
+      }
+      if constexpr (FIN) {
+        __syncthreads();
+        if (s_last && w == 0) {
+          const uint64_t kf = __hip_atomic_load((unsigned long long*)&A.keys[s], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+          stage_footprint(fl, F);
+          int e0, mi2;
+          const bool valid = key_range(kf, A.off, in.obst_off, in.M, in.edge_off, in.E, e0, mi2);
+          wave_sync();   // fl is written
+          write_stage(F, fl, wl, A.ax, A.ay, A.bx, A.by, kf, valid, e0, mi2, in.edge_off, cs, sn,
+                      px, py, s, A.keys, A.d, A.edge, A.obst, A.grad);
+        }
       }
     }
     __syncthreads();
@@ -940,9 +1003,15 @@ hipError_t launch_screen_bound_mf(int mi_class, int grid, const ScreenArgs& a, h
 template <int MF>
 hipError_t launch_fallback_mf(int mi_class, int grid, int max_tiles, const ScreenArgs& a,
                               hipStream_t st) {
-  if (mi_class == 4) screen_fallback_kernel<MF, 4><<<grid, 256, 0, st>>>(a, max_tiles);
-  else if (mi_class == 8) screen_fallback_kernel<MF, 8><<<grid, 256, 0, st>>>(a, max_tiles);
-  else screen_fallback_kernel<MF, 16><<<grid, 256, 0, st>>>(a, max_tiles);
+  if (a.finish) {
+    if (mi_class == 4) screen_fallback_kernel<MF, 4, true><<<grid, 256, 0, st>>>(a, max_tiles);
+    else if (mi_class == 8) screen_fallback_kernel<MF, 8, true><<<grid, 256, 0, st>>>(a, max_tiles);
+    else screen_fallback_kernel<MF, 16, true><<<grid, 256, 0, st>>>(a, max_tiles);
+  } else {
+    if (mi_class == 4) screen_fallback_kernel<MF, 4, false><<<grid, 256, 0, st>>>(a, max_tiles);
+    else if (mi_class == 8) screen_fallback_kernel<MF, 8, false><<<grid, 256, 0, st>>>(a, max_tiles);
+    else screen_fallback_kernel<MF, 16, false><<<grid, 256, 0, st>>>(a, max_tiles);
+  }
   return hipGetLastError();
 }
 

@@ -203,15 +203,17 @@ def single_pose(n_rects: int, seed: int = 0) -> Instance:
                     dict(workload="single_pose", rects=n_rects))
 
 
-def moving_obstacles(seed: int = 0, N: int = 30, R: int = 200, dt: float = 0.1):
-    """A horizon whose edge set changes per stage: R rectangles moving at
-    constant velocities (|v| <= 1 m/s) seen at t = s * dt for stage s, and a
-    c2-style path of N poses through them.  Returns (footprint, poses,
-    [edges of stage s], [offsets of stage s])."""
+def moving_obstacles(seed: int = 0, N: int = 30, R: int = 200, dt: float = 0.1,
+                     half: float = 6.0):
+    """A horizon whose edge set changes per stage: R rectangles (centres in
+    [-half, half]^2) moving at constant velocities (|v| <= 1 m/s) seen at
+    t = s * dt for stage s, and a c2-style path of N poses through them
+    (within [-half / 2, half / 2]^2).  Returns (footprint, poses, [edges of
+    stage s], [offsets of stage s])."""
     rng = rng_for(8, seed)
     fp = hexagon_footprint(rng)
-    poses = path_poses(rng, N, -3.0, 3.0)
-    centres = rng.uniform(-6.0, 6.0, size=(R, 2))
+    poses = path_poses(rng, N, -half / 2, half / 2)
+    centres = rng.uniform(-half, half, size=(R, 2))
     sides = rng.uniform(0.1, 0.8, size=(R, 2))
     angles = rng.uniform(-np.pi, np.pi, size=R)
     vel = rng.uniform(-0.7, 0.7, size=(R, 2))

@@ -42,8 +42,9 @@ struct GeoLds {
   float iv2[kMaxObst], il[kMaxObst];     // 1 / (|v|^2 + eps), 1 / (|v| + eps)
   float len[kMaxObst];                   // |v|
   float px[2 * kMaxObst], py[2 * kMaxObst];   // V_obs
-  int tgt[64][kSlots];
-  float gx[64][kSlots], gy[64][kSlots];
+  alignas(16) int tgt[64][kSlots];
+  alignas(16) float gx[64][kSlots];
+  alignas(16) float gy[64][kSlots];
 };
 
 // Target id of V_obs point k: A~_k, or B~_{k - mi} for open obstacles.
@@ -274,11 +275,21 @@ __global__ __launch_bounds__(64 * kGeoWaves) void geom_bwd_kernel(
   if (lane < 2 * mi) t = lane;
   else if (lane >= 32 && lane < 32 + m) t = kRobot + (lane - 32);
   if (t < 0) return;
+  // every lane's four slots as one vector read each, the adds selected (a
+  // slot of another point adds +0), so the reads of many lanes are in
+  // flight at once instead of one read and branch per slot
+  static_assert(kSlots == 4, "the sums read a lane's slots as one vector");
   float sx = 0.f, sy = 0.f;
-  for (int l = 0; l < 64; ++l)
-#pragma unroll
-    for (int q = 0; q < kSlots; ++q)
-      if (G.tgt[l][q] == t) { sx += G.gx[l][q]; sy += G.gy[l][q]; }
+#pragma unroll 8
+  for (int l = 0; l < 64; ++l) {
+    const int4 tg = *reinterpret_cast<const int4*>(G.tgt[l]);
+    const float4 ux = *reinterpret_cast<const float4*>(G.gx[l]);
+    const float4 uy = *reinterpret_cast<const float4*>(G.gy[l]);
+    sx += tg.x == t ? ux.x : 0.f; sy += tg.x == t ? uy.x : 0.f;
+    sx += tg.y == t ? ux.y : 0.f; sy += tg.y == t ? uy.y : 0.f;
+    sx += tg.z == t ? ux.z : 0.f; sy += tg.z == t ? uy.z : 0.f;
+    sx += tg.w == t ? ux.w : 0.f; sy += tg.w == t ? uy.w : 0.f;
+  }
   if (sx == 0.f && sy == 0.f && isfinite(scale)) return;
   if (t < kRobot) {
     // d phi / dA = R d phi / dA~

@@ -449,6 +449,55 @@ def test_screened_fallback_triggers(api):
     b.close()
 
 
+def test_screened_graph_replays(api):
+    """Screened calls captured in a HIP graph and replayed three times, with
+    eager plain and screened calls (and synchronisations) between the
+    replays: every replay gives the plain batch's outputs.  The batch has
+    stages that fail the certificate, so the replays run the fallback, and
+    in the bound form its finishing tiles and the reopening of the horizon
+    lists, from the graph."""
+    rng = np.random.default_rng(14)
+    fp = inputs.hexagon_footprint(inputs.rng_for(2, 0))
+    stacked = inputs.rect_edges(rng.uniform(-0.3, 0.3, (600, 2)), np.full((600, 2), 0.2),
+                                rng.uniform(-np.pi, np.pi, 600))
+    dense = inputs.Instance(fp, np.array([[0.0, 0.0, 0.3], [0.1, -0.1, 1.0]], np.float32),
+                            stacked.astype(np.float32), inputs.csr_offsets([4] * 600), 4,
+                            dict(workload="stacked"))
+    b = api.Batch([dense, inputs.c5_instance(5), _copies_instance(2500, (10.0, 0.0), 0.3, 6, 7)],
+                  graph=False)
+    ref = _run_plain(b)
+    for form in ("bound", "distance"):
+        call = (lambda: b.screened_bound()) if form == "bound" else \
+            (lambda: b.screened(None, pool=128, topk=256))
+        _, (cand, cert, _) = b.screened_bound(stats=True) if form == "bound" else \
+            b.screened(None, pool=128, topk=256, stats=True)
+        torch.cuda.synchronize()
+        assert int((cert == 0).sum()) > 0        # the fallback has work
+        call()
+        torch.cuda.synchronize()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cap):
+            call()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=cap):
+            call()
+        for rep in range(3):
+            for x in (b.d, b.edge, b.obst, b.grad, b.keys):
+                x.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            print(f"[graph {form}] replay {rep}", flush=True)
+            _assert_same([x.clone() for x in (b.d, b.edge, b.obst, b.grad, b.keys)], ref)
+            b.run()                              # eager work between the replays
+            b.screened(None, pool=1, topk=1)     # an eager screened call (pool 1, top-1)
+            torch.cuda.synchronize()
+            _assert_same([x.clone() for x in (b.d, b.edge, b.obst, b.grad, b.keys)], ref)
+        del g
+    b.close()
+
+
 # ---------------------------------------------------------------- staged circles
 
 def _all_forms(b, theta):

@@ -22,6 +22,7 @@
 // The footprint gradient is reported in the caller's vertex order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "psdf.h"
@@ -52,9 +53,11 @@ __device__ __forceinline__ int point_target(int k, int mi) {
   return k < mi ? 2 * k : 2 * (k - mi) + 1;
 }
 
-__global__ void zero_kernel(float* __restrict__ a, int n) {
+// Clears a[0..n) and b[0..nb) (the two outputs) in one launch.
+__global__ void zero2_kernel(float* __restrict__ a, int n, float* __restrict__ b, int nb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = 0.0f;
+  if (i < nb) b[i] = 0.0f;
 }
 
 __global__ __launch_bounds__(64 * kGeoWaves) void geom_bwd_kernel(
@@ -327,8 +330,8 @@ int psdf_bwd_geometry(const float* footprint, int32_t m, const float* poses, int
   if (N > 0 && (!poses || !keys || !gout))
     return set_error(PSDF_EINVAL, "poses, keys or gout is NULL");
   if ((size_t)e.E * 4 > (size_t)INT32_MAX) return set_error(PSDF_ETOOBIG, "E = %d", e.E);
-  if (e.E > 0) zero_kernel<<<(4 * e.E + 255) / 256, 256, 0, stream>>>(gedges, 4 * e.E);
-  zero_kernel<<<1, 64, 0, stream>>>(gfp, 2 * m);
+  const int nz = std::max(4 * e.E, 2 * m);
+  zero2_kernel<<<(nz + 255) / 256, 256, 0, stream>>>(gedges, 4 * e.E, gfp, 2 * m);
   hipError_t err = hipGetLastError();
   if (err == hipSuccess && N > 0) {
     geom_bwd_kernel<<<(N + kGeoWaves - 1) / kGeoWaves, 64 * kGeoWaves, 0, stream>>>(

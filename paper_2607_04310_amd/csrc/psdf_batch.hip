@@ -41,8 +41,11 @@ struct psdf_batch_plan {
   int n_items = 0;
   int cu = 256;
   // one persistent launch per footprint-size group (MF = 3..8 or 16)
-  struct Group { int mf, start, count, grid; };
+  // lane: the stream the group's launch goes to (0: the caller's, l > 0:
+  // side[l - 1]); groups of one lane run one after another
+  struct Group { int mf, start, count, grid, lane; };
   std::vector<Group> groups;
+  int n_lanes = 1;
   // device memory owned by the plan
   FpConst* d_fp = nullptr;
   BatchInst* d_inst = nullptr;
@@ -75,8 +78,9 @@ struct psdf_batch_plan {
   const void* circ_src[5] = {};
   // graph
   hipStream_t cap_stream = nullptr;
-  // footprint-size groups run concurrently: group k > 0 on side[k - 1],
-  // forked from and joined back to the caller's stream with events
+  // footprint-size groups run concurrently on up to kLanes streams: the
+  // caller's and side[0 .. kLanes - 2], forked from and joined back to the
+  // caller's stream with events (ev[0] the fork, ev[l] lane l's end)
   hipStream_t side[6] = {};
   hipEvent_t ev[7] = {};
   hipGraph_t graph = nullptr;
@@ -141,6 +145,8 @@ bool cache_find(const std::string& key, Shape* s) {
 
 constexpr int kGroupMF[] = {3, 4, 5, 6, 7, 8, 16};
 constexpr int kGroups = 7;
+// Streams one call's groups run on (the caller's and kLanes - 1 plan-owned).
+constexpr int kLanes = 4;
 static_assert(sizeof(psdf_batch_plan::side) / sizeof(hipStream_t) == kGroups - 1 &&
                   sizeof(psdf_batch_plan::ev) / sizeof(hipEvent_t) == kGroups,
               "one side stream per group after the first, one event per group");
@@ -248,8 +254,37 @@ int build_items(psdf_batch_plan* p, Shape sh) {
     const int per_cu = occupancy(mf, p->mi_class, sh.nw);
     const int count = (int)(j - i);
     const int grid = sh.direct ? count : std::max(1, std::min(count, per_cu * p->cu));
-    p->groups.push_back({mf, (int)i, count, grid});
+    p->groups.push_back({mf, (int)i, count, grid, 0});
     i = j;
+  }
+  // lanes: the groups, largest estimated work first, each to the lane with
+  // the least work so far (at most kLanes: a process gets a few hardware
+  // queues, and streams beyond them share a queue, which serialises their
+  // launches behind one another's whole kernels)
+  {
+    std::vector<double> gcost(p->groups.size(), 0.0);
+    for (size_t k = 0; k < p->groups.size(); ++k)
+      for (int i = p->groups[k].start; i < p->groups[k].start + p->groups[k].count; ++i)
+        gcost[k] += cost[order[i]];
+    std::vector<int> by(p->groups.size());
+    for (size_t k = 0; k < by.size(); ++k) by[k] = (int)k;
+    std::stable_sort(by.begin(), by.end(), [&](int a, int b) { return gcost[a] > gcost[b]; });
+    p->n_lanes = std::max(1, std::min((int)p->groups.size(), kLanes));
+    std::vector<double> load(p->n_lanes, 0.0);
+    std::vector<psdf_batch_plan::Group> lanes;
+    for (int k : by) {
+      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[l] += gcost[k];
+      psdf_batch_plan::Group g = p->groups[k];
+      g.lane = l;
+      lanes.push_back(g);
+    }
+    // launch order: lane by lane, each lane's groups largest first
+    std::stable_sort(lanes.begin(), lanes.end(),
+                     [](const psdf_batch_plan::Group& a, const psdf_batch_plan::Group& b) {
+                       return a.lane < b.lane;
+                     });
+    p->groups = lanes;
   }
   free_graph(p);
   return PSDF_OK;
@@ -365,13 +400,13 @@ int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay
   auto enqueue = [&](hipStream_t st, bool timed) -> hipError_t {
     // the groups write disjoint partial rows and count their items on
     // counters of their own, so they run concurrently (their tails overlap)
-    const int ng = (int)p->groups.size();
+    const int ng = (int)p->groups.size(), nl = p->n_lanes;
     hipError_t err = hipSuccess;
-    if (ng > 1 && !p->side[ng - 2]) return hipErrorInvalidValue;   // created with the plan
-    if (ng > 1) {
+    if (nl > 1 && !p->side[nl - 2]) return hipErrorInvalidValue;   // created with the plan
+    if (nl > 1) {
       err = hipEventRecord(p->ev[0], st);
-      for (int k = 1; k < ng && err == hipSuccess; ++k)
-        err = hipStreamWaitEvent(p->side[k - 1], p->ev[0], 0);
+      for (int l = 1; l < nl && err == hipSuccess; ++l)
+        err = hipStreamWaitEvent(p->side[l - 1], p->ev[0], 0);
     }
     for (int k = 0; k < ng && err == hipSuccess; ++k) {
       const auto& g = p->groups[k];
@@ -379,12 +414,14 @@ int run(psdf_batch_plan* p, const float* poses, const float* ax, const float* ay
       ga.items = a.items + g.start;
       ga.n_items = g.count;
       ga.ctrl = a.ctrl + group_of(g.mf);
-      hipStream_t gs = k == 0 ? st : p->side[k - 1];
+      hipStream_t gs = g.lane == 0 ? st : p->side[g.lane - 1];
       hipEvent_t ev0 = nullptr, ev1 = nullptr;
       if (!timed || !timer_kernel_events(&ev0, &ev1)) ev0 = ev1 = nullptr;
       err = launch_batch(g.mf, p->mi_class, p->shape.nw, g.grid, ga, gs, ev0, ev1);
-      if (err == hipSuccess && k > 0) err = hipEventRecord(p->ev[k], gs);
-      if (err == hipSuccess && k > 0) err = hipStreamWaitEvent(st, p->ev[k], 0);
+    }
+    for (int l = 1; l < nl && err == hipSuccess; ++l) {
+      err = hipEventRecord(p->ev[l], p->side[l - 1]);
+      if (err == hipSuccess) err = hipStreamWaitEvent(st, p->ev[l], 0);
     }
     if (err != hipSuccess) return err;
     batch_finish_kernel<<<p->total_stages, 64, 0, st>>>(
@@ -744,15 +781,16 @@ int psdf_batch_plan_create(psdf_batch_plan** out, const psdf_batch_desc* desc, i
     err = hipMemcpy(p->d_fp, p->fp.data(), n_inst * sizeof(FpConst), hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
   // side streams and events for the concurrent footprint-size groups: one
-  // stream per group present after the first, one event per group
+  // stream per lane after the first, one event per lane
   {
     bool present[kGroups] = {};
     for (int k = 0; k < n_inst; ++k) present[group_of(p->fp[k].m)] = true;
     int ng = 0;
     for (bool b : present) ng += b ? 1 : 0;
-    for (int k = 0; k + 1 < ng && err == hipSuccess; ++k)
+    const int nl = std::min(ng, kLanes);
+    for (int k = 0; k + 1 < nl && err == hipSuccess; ++k)
       err = hipStreamCreateWithFlags(&p->side[k], hipStreamNonBlocking);
-    for (int k = 0; k < ng && ng > 1 && err == hipSuccess; ++k)
+    for (int k = 0; k < nl && nl > 1 && err == hipSuccess; ++k)
       err = hipEventCreateWithFlags(&p->ev[k], hipEventDisableTiming);
   }
   // screening tables

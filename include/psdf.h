@@ -404,7 +404,11 @@ int psdf_batch_plan_info(const psdf_batch_plan* plan, int32_t* stages_per_item,
  * (PSDF_ETOOBIG otherwise).
  * Optional device outputs (length sum N, may be NULL): stage_cand = obstacles
  * evaluated exactly by the screen, stage_cert = 1 if certified, cand_keys =
- * the candidates' minimum key before any fallback. */
+ * the candidates' minimum key before any fallback.
+ * The plan keeps per-instance screening lists that every call opens and
+ * closes on the stream; a screened call that returns an error after it has
+ * enqueued work may leave them open, so destroy such a plan rather than
+ * call it again (the kernels stay within the plan's buffers either way). */
 int psdf_batch_screened(psdf_batch_plan* plan, const float* theta, int32_t pool, int32_t topk,
                         const float* poses, const float* ax, const float* ay, const float* bx,
                         const float* by, const int32_t* obst_off, float* d, int32_t* edge,

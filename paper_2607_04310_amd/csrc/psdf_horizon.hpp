@@ -263,14 +263,18 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   __syncthreads();
   at += s_base;
   // the instance's list has M slots and holds each obstacle at most once,
-  // as its circle with the local index in .w
+  // as its circle with the local index in .w; a count that did not start at
+  // zero (a call that stopped before reopening the lists) could pass M, so
+  // slots past M are not written (the stage passes then find the count
+  // above M and take the full evaluation)
 #pragma unroll
   for (int q = 0; q < kHorizonKeys; ++q)
     if (k[q] != 0xffffffffu && k[q] <= T) {
       const int o = o0 + tid + kScreenThreads * q;
       float4 c = cq[q];
       c.w = __int_as_float(o);
-      hlist[in.circ_off + at++] = c;
+      if (at >= 0 && at < M) hlist[in.circ_off + at] = c;
+      ++at;
     }
 }
 

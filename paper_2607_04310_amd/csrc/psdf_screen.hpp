@@ -431,10 +431,11 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
   const int* off = A.off + in.obst_off;
 
   // An instance without a usable horizon list (a non-finite stage position,
-  // or tie blocks that make it longer than kHorizonCap) sends its stages to
-  // the full evaluation.
+  // tie blocks that make it longer than kHorizonCap, or a count beyond its M
+  // slots, which only a call that stopped before reopening the lists leaves)
+  // sends its stages to the full evaluation.
   const int hc = A.hcount[inst];
-  if (hc < 0 || hc > kHorizonCap) {
+  if (hc < 0 || hc > kHorizonCap || hc > M) {
     if (tid == 0) {
       A.keys[s] = kEmptyKey;
       if (A.stage_cand) A.stage_cand[s] = 0;
@@ -735,7 +736,7 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
   if (A.finish) stage_footprint(fl, F);   // for the outputs of a certified stage
 
   const int hc = A.hcount[inst];
-  if (hc < 0 || hc > kHorizonCap) {
+  if (hc < 0 || hc > kHorizonCap || hc > in.M) {   // as screen_kernel
     if (lane == 0) {
       A.keys[s] = kEmptyKey;
       if (A.stage_cand) A.stage_cand[s] = 0;

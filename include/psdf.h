@@ -343,12 +343,14 @@ void psdf_batch_plan_destroy(psdf_batch_plan* plan);
 
 /* Evaluate every instance: d, edge, obst, grad and keys as described above.
  * The launches of the different footprint sizes run concurrently: they fork
- * from `stream` onto plan-owned side streams with events and join back
- * before the final kernel, so the call still completes in `stream` order.
- * With PSDF_BATCH_GRAPH the first call (and any call whose pointers differ
- * from the captured ones) captures the launch into a hipGraph on a
- * plan-owned stream; later calls replay it on `stream`.  Input contents may
- * change between replays. */
+ * from `stream` onto up to three plan-owned side streams with events and
+ * join back before the final kernel, so the call still completes in
+ * `stream` order.  With PSDF_BATCH_GRAPH the first call (and any call whose
+ * pointers differ from the captured ones) captures the launch into a
+ * hipGraph on a plan-owned stream; later calls replay it on `stream`.  Input
+ * contents may change between replays.  The final kernel also clears the
+ * plan's work counters for the next call: if a call returns an error after
+ * it has enqueued work, destroy the plan rather than call it again. */
 int psdf_batch(psdf_batch_plan* plan, const float* poses, const float* ax, const float* ay,
                const float* bx, const float* by, const int32_t* obst_off, float* d,
                int32_t* edge, int32_t* obst, float* grad, uint64_t* keys, hipStream_t stream);

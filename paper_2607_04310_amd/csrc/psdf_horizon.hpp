@@ -181,9 +181,13 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   // bounding box of the stage positions (orderable keys: min of x, y, -x, -y)
   uint32_t bx0 = 0xffffffffu, by0 = 0xffffffffu, bx1 = 0xffffffffu, by1 = 0xffffffffu;
   int bad = 0;
+  // the thread's first stage position stays in registers for the radius
+  // pass below (all of them when N <= kScreenThreads)
+  float x0 = 0.f, y0 = 0.f;
   for (int t = tid; t < in.N; t += kScreenThreads) {
     const float* p = poses + 3 * (in.pose_off + t);
     const float x = p[0], y = p[1];
+    if (t == tid) { x0 = x; y0 = y; }
     if (!(isfinite(x) && isfinite(y))) { bad = 1; continue; }
     bx0 = min(bx0, orderable(x)); by0 = min(by0, orderable(y));
     bx1 = min(bx1, orderable(-x)); by1 = min(by1, orderable(-y));
@@ -205,8 +209,13 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   // orderable image of -d)
   uint32_t nr = 0xffffffffu;
   for (int t = tid; t < in.N; t += kScreenThreads) {
-    const float* p = poses + 3 * (in.pose_off + t);
-    const float dx = p[0] - cx, dy = p[1] - cy;
+    float x = x0, y = y0;
+    if (t != tid) {
+      const float* p = poses + 3 * (in.pose_off + t);
+      x = p[0];
+      y = p[1];
+    }
+    const float dx = x - cx, dy = y - cy;
     nr = min(nr, orderable(-sqrtf(fmaf(dx, dx, dy * dy))));
   }
   {

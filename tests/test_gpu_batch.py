@@ -268,3 +268,30 @@ def test_stage_rows_in_any_order(api):
                      *[t[sl] for t in ref[:4]])
     b.close()
     b2.close()
+
+
+def test_all_footprint_groups_share_four_lanes(api):
+    """Footprints of 3..8 and 9..16 vertices: all seven footprint-size groups
+    in one batch, more groups than the call's four streams, so some streams
+    run two groups back to back.  Eager calls and graph replays equal the
+    per-instance loop bit for bit; sampled instances match the oracle."""
+    rng = np.random.default_rng(93)
+    ms = [3, 4, 5, 6, 7, 8, 9, 12, 16] * 3
+    insts = [inputs.random_small(rng, n_obst=int(rng.integers(20, 120)), n_poses=int(rng.integers(5, 40)),
+                                 segments=int(rng.integers(0, 6)), lo=-3, hi=3, fp_m=m) for m in ms]
+    ref = None
+    for graph in (False, True):
+        b = api.Batch(insts, graph=graph)
+        if ref is None:
+            ref = per_instance(api, b)
+        for _ in range(2):
+            assert_equal_outputs(batch_out(b), ref)
+        b.close()
+    d, e, o, g = ref
+    b = api.Batch(insts, graph=False)
+    for k in (0, 6, 7, 8, 17, 26):
+        inst = insts[k]
+        sl = slice(b.desc[k][2], b.desc[k][2] + inst.N)
+        check_stages(inst.footprint, inst.poses, inst.edges, inst.obst_off, 1000.0,
+                     d[sl], e[sl], o[sl], g[sl])
+    b.close()

@@ -500,20 +500,23 @@ def test_screened_graph_replays(api):
 
 def test_screened_all_footprint_groups(api):
     """Footprints of 3..16 vertices (all seven footprint-size groups, the
-    16-slot screen kernels included): the bound-threshold, distance-ranked
-    and forced-fallback screened calls, on the edges and on staged circles,
-    give the plain batch's outputs bit for bit, twice in a row."""
+    16-slot screen kernels included): the bound-threshold, distance-ranked,
+    network-ranked (untrained weights) and forced-fallback screened calls,
+    on the edges and on staged circles, give the plain batch's outputs bit
+    for bit, twice in a row."""
     rng = np.random.default_rng(94)
     ms = [3, 4, 5, 6, 7, 8, 9, 12, 16] * 2
     insts = [inputs.random_small(rng, n_obst=int(rng.integers(20, 150)), n_poses=int(rng.integers(5, 30)),
                                  segments=int(rng.integers(0, 6)), lo=-3, hi=3, fp_m=m) for m in ms]
     b = api.Batch(insts, graph=False)
     ref = _run_plain(b)
+    theta = torch.tensor(_rand_theta(5), device="cuda")
     for staged in (False, True):
         if staged:
             b.stage()
         for name, fn in (("bound", lambda: b.screened_bound()),
                          ("distance", lambda: b.screened(None, pool=64, topk=64)),
+                         ("network", lambda: b.screened(theta, pool=64, topk=64)),
                          ("fallback", lambda: b.screened(None, pool=1, topk=1))):
             for _ in range(2):
                 out = fn()

@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kScreenThreads) void horizon_kernel(
   }
   const int inst = blockIdx.y, part = blockIdx.x, tid = threadIdx.x;
   const BatchInst in = insts[inst];
-  const FpConst& F = fps[inst];
+  const FpConst& F = fp_const(fps, inst);   // uniform fields: scalar loads
   const int M = in.M;
   const int chunk = (M + kHorizonSplit - 1) / kHorizonSplit;
   const int o0 = part * chunk, o1 = min(M, o0 + chunk);

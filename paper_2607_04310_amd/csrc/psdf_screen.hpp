@@ -420,7 +420,7 @@ __attribute__((amdgpu_waves_per_eu(MI == 4 && MF <= 8 ? 4 : 1))) void screen_ker
     pre[q] = idx < si.w ? hl[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
   const BatchInst in = A.insts[inst];
-  const FpConst& F = A.fps[inst];
+  const FpConst& F = fp_const(A.fps, inst);   // uniform fields: scalar loads
   const float* p = A.poses + 3 * s;
   const float px = p[0], py = p[1];
   float sn, cs;
@@ -726,7 +726,7 @@ __global__ __launch_bounds__(64) void screen_bound_kernel(ScreenArgs A) {
     rc[q] = idx < si.w ? hl[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
   const BatchInst in = A.insts[inst];
-  const FpConst& F = A.fps[inst];
+  const FpConst& F = fp_const(A.fps, inst);   // uniform fields: scalar loads
   const float* p = A.poses + 3 * s;
   const float px = p[0], py = p[1];
   float sn, cs;
@@ -938,7 +938,7 @@ __global__ __launch_bounds__(256) void screen_fallback_kernel(ScreenArgs A, int 
     const int inst = __builtin_amdgcn_readfirstlane(A.stage_inst[s]);
     const BatchInst in = A.insts[inst];
     if (tile == 0 || tile * 256 < in.M) {
-      const FpConst& F = A.fps[inst];
+      const FpConst& F = fp_const(A.fps, inst);   // uniform fields: scalar loads
       const float* p = A.poses + 3 * s;
       const float px = p[0], py = p[1];
       float sn, cs;
